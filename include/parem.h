@@ -1,0 +1,152 @@
+/*
+ * parem.h - C interface of the MI355X (gfx950) speculative chunked DFA walk.
+ *
+ * Method: PaREM (Memeti & Pllana, "PaREM: A Novel Approach for Parallel
+ * Regular Expression Matching", CSE 2014), Section II-B and Algorithm 1: the
+ * input is decomposed into chunks; each chunk is walked only from the states
+ * that have an incoming transition on the symbol just before the chunk
+ * (R = S intersect L, with S = every state for a total table); the resulting
+ * per-chunk state maps are joined into the run of the whole input.
+ *
+ * The result equals the sequential DFA run of Section II-A exactly: the
+ * state reached after the last symbol, whether it is final, and the number
+ * of steps whose destination state is final (the `found` tally of
+ * Algorithm 1 along the connected route; the start state is not counted).
+ *
+ * Conventions for every call:
+ *  - Plain pointers and sizes only. "Host" pointers are ordinary CPU memory;
+ *    "device" pointers are HIP device memory of the current device.
+ *  - Nothing is thrown across this interface: every call returns a
+ *    parem_status; on failure outputs are left unspecified.
+ *  - Handles are immutable after parem_compile; calls that pass their own
+ *    workspace may run concurrently on different streams with one handle.
+ *  - Streams are passed as `void*` holding a hipStream_t (NULL = the null
+ *    stream of the current device).
+ */
+#ifndef PAREM_H
+#define PAREM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct parem_dfa *parem_handle;
+
+typedef enum {
+    PAREM_OK = 0,
+    PAREM_EINVAL = -1,      /* a null pointer, a zero size, a bad option */
+    PAREM_ENOMEM = -2,      /* host or device allocation failed          */
+    PAREM_EDEVICE = -3,     /* a HIP runtime call failed                  */
+    PAREM_ESYMBOL = -4,     /* a text byte is not in the alphabet         */
+    PAREM_ESTATE = -5,      /* a table entry / start / final id >= Q      */
+    PAREM_EUNSUPPORTED = -6 /* sizes beyond what this build handles       */
+} parem_status;
+
+/* Table layouts the compile step may choose (parem_options.layout). */
+enum {
+    PAREM_LAYOUT_AUTO = 0,
+    PAREM_LAYOUT_BYTE_LDS = 1,   /* (Q+1) x 256 byte-indexed table in LDS       */
+    PAREM_LAYOUT_BYTE_GLOBAL = 2,/* same table read through L2 (large tables)   */
+    PAREM_LAYOUT_KGRAM_LDS = 3,  /* k-symbol stride table in LDS (small alphabets) */
+    PAREM_LAYOUT_SPARSE_LDS = 4  /* per-state default + exception records in LDS */
+};
+
+typedef struct {
+    uint32_t chunk_len;   /* bytes per chunk, multiple of 64; 0 = automatic     */
+    uint32_t layout;      /* PAREM_LAYOUT_*; AUTO lets the compile step choose  */
+    uint32_t group;       /* speculated states walked in lockstep per lane; 0 = auto */
+    uint32_t kgram;       /* symbols per step for the k-gram layout; 0 = auto   */
+    uint32_t reserved[4]; /* must be zero                                        */
+} parem_options;
+
+typedef struct {
+    uint32_t final_state;  /* state after the last byte (start state if len == 0) */
+    uint32_t accept;       /* 1 iff final_state is final                           */
+    uint64_t count;        /* number of steps whose destination state is final    */
+    uint64_t chunks;       /* chunks the text was split into                       */
+    uint64_t spec_runs;    /* speculated (chunk, state) walks started              */
+    uint64_t rerun_chunks; /* chunks walked again because their true entry state
+                              was not speculated (always 0 for the plain set)     */
+} parem_result;
+
+/*
+ * Build a handle from a total DFA (Section II-A: Q, Sigma, delta, q0, F).
+ *  table        host, row-major [num_states][alphabet_size]; entry (q, j) is
+ *               delta(q, alphabet[j]); entry_bytes is 1, 2 or 4 (unsigned).
+ *               Every entry must be < num_states (else PAREM_ESTATE): the
+ *               table must be total (the S set of Algorithm 1 is then Q).
+ *  alphabet     host, alphabet_size distinct byte values (1..256); column j
+ *               of the table is the byte alphabet[j]. Bytes not listed are
+ *               invalid in texts (PAREM_ESYMBOL at match time).
+ *  start        q0 < num_states.
+ *  accepting    host, num_accepting state ids (duplicates allowed) of F.
+ *  opt          NULL for defaults.
+ *  out          receives the handle; owned by the caller, release with
+ *               parem_free. All inputs are copied; the caller keeps them.
+ * The compile step precomputes, per symbol, the speculated set of a chunk
+ * that follows that symbol (the image of the symbol's column, the L set of
+ * Algorithm 1) and uploads the chosen table layout to the current device.
+ * Limits: 1 <= num_states <= 32767.
+ */
+parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_states,
+                           const uint8_t *alphabet, uint32_t alphabet_size, uint32_t start,
+                           const uint32_t *accepting, uint32_t num_accepting,
+                           const parem_options *opt, parem_handle *out);
+
+/* Release a handle and its device memory. NULL is accepted. */
+void parem_free(parem_handle h);
+
+/* Text of a status code (static storage). */
+const char *parem_strerror(parem_status s);
+
+/* Layout and sizes the compile step chose, for logs and the autotuner.
+ * Any output pointer may be NULL. */
+parem_status parem_describe(parem_handle h, uint32_t *layout, uint32_t *max_spec,
+                            uint32_t *lds_bytes, uint32_t *kgram);
+
+/*
+ * Device workspace (bytes) that parem_match_async needs for a text of `len`
+ * bytes with this handle and its options.
+ */
+parem_status parem_workspace_size(parem_handle h, uint64_t len, uint64_t *bytes);
+
+/*
+ * Enqueue one match on `stream` and return at once.
+ *  d_text       device, len bytes (any alignment); read only.
+ *  d_workspace  device, at least parem_workspace_size bytes; the call owns
+ *               it until the stream reaches the end of the match.
+ *  d_out        device, one parem_result written when the match completes.
+ *               A byte outside the alphabet yields final_state = 0xFFFFFFFF
+ *               and accept = 0 in *d_out (the status is then known only
+ *               after the stream is synchronised; parem_match maps it to
+ *               PAREM_ESYMBOL).
+ */
+parem_status parem_match_async(parem_handle h, const uint8_t *d_text, uint64_t len,
+                               void *d_workspace, uint64_t workspace_bytes, void *stream,
+                               parem_result *d_out);
+
+/*
+ * parem_match_async plus two caller-owned hipEvent_t (passed as void*)
+ * recorded on `stream` right before and right after the walk kernel, the
+ * dominant kernel of a match, so that it can be timed alone. Either event
+ * may be NULL. Same arguments, ownership and errors as parem_match_async.
+ */
+parem_status parem_match_async_timed(parem_handle h, const uint8_t *d_text, uint64_t len,
+                                     void *d_workspace, uint64_t workspace_bytes, void *stream,
+                                     parem_result *d_out, void *ev_walk_begin, void *ev_walk_end);
+
+/*
+ * Synchronous match. `text` may be host or device memory (detected with
+ * hipPointerGetAttributes); host text is staged through pinned memory. The
+ * workspace is allocated and freed inside the call. Returns PAREM_ESYMBOL if
+ * a byte is not in the alphabet.
+ */
+parem_status parem_match(parem_handle h, const uint8_t *text, uint64_t len, parem_result *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAREM_H */

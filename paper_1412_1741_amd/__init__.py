@@ -1,0 +1,253 @@
+"""Python binding of ``libparem.so``: the MI355X speculative chunked DFA walk.
+
+Argument marshalling only. Every step of a match runs in the library's HIP
+kernels; PyTorch is used for device memory and streams. The first call loads
+the library and raises ImportError when it has not been built
+(``python -m paper_1412_1741_amd.build``): there is no CPU fallback.
+
+The functions carry the C names (``parem_compile``, ``parem_match``,
+``parem_match_async``, ...); ``Matcher`` wraps a handle for convenience.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libparem.so")
+
+PAREM_OK = 0
+PAREM_EINVAL = -1
+PAREM_ENOMEM = -2
+PAREM_EDEVICE = -3
+PAREM_ESYMBOL = -4
+PAREM_ESTATE = -5
+PAREM_EUNSUPPORTED = -6
+
+LAYOUT_AUTO = 0
+LAYOUT_BYTE_LDS = 1
+LAYOUT_BYTE_GLOBAL = 2
+LAYOUT_KGRAM_LDS = 3
+LAYOUT_SPARSE_LDS = 4
+
+RESULT_BYTES = 40
+INVALID_STATE = 0xFFFFFFFF
+
+
+class ParemError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {parem_strerror(status)} ({status})")
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("chunk_len", ctypes.c_uint32), ("layout", ctypes.c_uint32), ("group", ctypes.c_uint32),
+                ("kgram", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 4)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("final_state", ctypes.c_uint32), ("accept", ctypes.c_uint32), ("count", ctypes.c_uint64),
+                ("chunks", ctypes.c_uint64), ("spec_runs", ctypes.c_uint64), ("rerun_chunks", ctypes.c_uint64)]
+
+
+assert ctypes.sizeof(Result) == RESULT_BYTES
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1412_1741_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    lib.parem_compile.restype = i32
+    lib.parem_compile.argtypes = [vp, i32, u32, vp, u32, u32, vp, u32, ctypes.POINTER(Options),
+                                  ctypes.POINTER(vp)]
+    lib.parem_free.restype = None
+    lib.parem_free.argtypes = [vp]
+    lib.parem_strerror.restype = ctypes.c_char_p
+    lib.parem_strerror.argtypes = [i32]
+    lib.parem_describe.restype = i32
+    lib.parem_describe.argtypes = [vp, ctypes.POINTER(u32), ctypes.POINTER(u32), ctypes.POINTER(u32),
+                                   ctypes.POINTER(u32)]
+    lib.parem_workspace_size.restype = i32
+    lib.parem_workspace_size.argtypes = [vp, u64, ctypes.POINTER(u64)]
+    lib.parem_match_async.restype = i32
+    lib.parem_match_async.argtypes = [vp, vp, u64, vp, u64, vp, vp]
+    lib.parem_match_async_timed.restype = i32
+    lib.parem_match_async_timed.argtypes = [vp, vp, u64, vp, u64, vp, vp, vp, vp]
+    lib.parem_match.restype = i32
+    lib.parem_match.argtypes = [vp, vp, u64, ctypes.POINTER(Result)]
+    return lib
+
+
+_lib = None
+
+# every symbol the header declares, for the export check
+EXPORTED = ["parem_compile", "parem_free", "parem_strerror", "parem_describe", "parem_workspace_size",
+            "parem_match_async", "parem_match_async_timed", "parem_match"]
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises ImportError when it has not been built."""
+    global _lib
+    if _lib is None:
+        _lib = _load()
+    return _lib
+
+
+# ---------------------------------------------------------------------------
+# C names
+# ---------------------------------------------------------------------------
+
+def parem_strerror(status: int) -> str:
+    return lib().parem_strerror(int(status)).decode()
+
+
+def _check(status: int, where: str):
+    if status != PAREM_OK:
+        raise ParemError(status, where)
+
+
+def parem_compile(table, alphabet, start: int, accepting, *, chunk_len: int = 0, layout: int = 0,
+                  group: int = 0, kgram: int = 0) -> int:
+    """Compile a total DFA; returns the handle (an integer address)."""
+    t = np.ascontiguousarray(table)
+    if t.ndim != 2:
+        raise ValueError("table must be 2-D [num_states, alphabet_size]")
+    if t.dtype not in (np.uint8, np.uint16, np.uint32):
+        t = np.ascontiguousarray(t, dtype=np.uint32)
+    alpha = np.frombuffer(bytes(alphabet), dtype=np.uint8).copy()
+    acc = np.ascontiguousarray(np.asarray(accepting, dtype=np.uint32).reshape(-1))
+    opt = Options(chunk_len, layout, group, kgram)
+    h = ctypes.c_void_p()
+    st = lib().parem_compile(t.ctypes.data, t.dtype.itemsize, t.shape[0], alpha.ctypes.data, alpha.size,
+                            int(start), acc.ctypes.data if acc.size else None, acc.size, ctypes.byref(opt),
+                            ctypes.byref(h))
+    _check(st, "parem_compile")
+    return h.value
+
+
+def parem_free(handle: int) -> None:
+    lib().parem_free(handle)
+
+
+def parem_describe(handle: int) -> dict:
+    a, b, c, d = (ctypes.c_uint32() for _ in range(4))
+    _check(lib().parem_describe(handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(d)),
+           "parem_describe")
+    return {"layout": a.value, "max_spec": b.value, "lds_bytes": c.value, "kgram": d.value}
+
+
+def parem_workspace_size(handle: int, length: int) -> int:
+    n = ctypes.c_uint64()
+    _check(lib().parem_workspace_size(handle, int(length), ctypes.byref(n)), "parem_workspace_size")
+    return n.value
+
+
+def parem_match_async(handle: int, d_text_ptr: int, length: int, d_workspace_ptr: int, workspace_bytes: int,
+                      stream_ptr: int, d_out_ptr: int) -> None:
+    """Enqueue a match; all pointers are device addresses (ints)."""
+    _check(lib().parem_match_async(handle, d_text_ptr or None, int(length), d_workspace_ptr or None,
+                                  int(workspace_bytes), stream_ptr or None, d_out_ptr), "parem_match_async")
+
+
+def parem_match_async_timed(handle: int, d_text_ptr: int, length: int, d_workspace_ptr: int,
+                            workspace_bytes: int, stream_ptr: int, d_out_ptr: int, ev_begin: int,
+                            ev_end: int) -> None:
+    """parem_match_async with hipEvent_t handles recorded around the walk kernel."""
+    _check(lib().parem_match_async_timed(handle, d_text_ptr or None, int(length), d_workspace_ptr or None,
+                                        int(workspace_bytes), stream_ptr or None, d_out_ptr, ev_begin or None,
+                                        ev_end or None), "parem_match_async_timed")
+
+
+def parem_match(handle: int, text_ptr: int, length: int) -> Result:
+    """Synchronous match on a host or device address."""
+    r = Result()
+    _check(lib().parem_match(handle, text_ptr or None, int(length), ctypes.byref(r)), "parem_match")
+    return r
+
+
+# ---------------------------------------------------------------------------
+# convenience wrapper
+# ---------------------------------------------------------------------------
+
+@dataclass
+class MatchResult:
+    final_state: int
+    accept: bool
+    count: int
+    chunks: int
+    spec_runs: int
+    rerun_chunks: int
+
+    @classmethod
+    def from_struct(cls, r: Result) -> "MatchResult":
+        return cls(int(r.final_state), bool(r.accept), int(r.count), int(r.chunks), int(r.spec_runs),
+                   int(r.rerun_chunks))
+
+    @classmethod
+    def from_bytes(cls, raw: bytes) -> "MatchResult":
+        return cls.from_struct(Result.from_buffer_copy(raw))
+
+
+class Matcher:
+    """Owns a compiled handle; matches torch uint8 device tensors or host bytes."""
+
+    def __init__(self, table, alphabet, start, accepting, **opts):
+        self.handle = parem_compile(table, alphabet, start, accepting, **opts)
+        self._ws = None
+
+    def close(self):
+        if self.handle:
+            parem_free(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def describe(self) -> dict:
+        return parem_describe(self.handle)
+
+    def workspace(self, length: int):
+        import torch
+        need = parem_workspace_size(self.handle, length)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
+        return self._ws
+
+    def match_async(self, text, out=None, stream=None):
+        """Enqueue on torch's current stream (or ``stream``); returns the
+        40-byte device result tensor."""
+        import torch
+        assert text.is_cuda and text.dtype == torch.uint8 and text.is_contiguous()
+        ws = self.workspace(text.numel())
+        if out is None:
+            out = torch.empty(RESULT_BYTES, dtype=torch.uint8, device=text.device)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        parem_match_async(self.handle, text.data_ptr(), text.numel(), ws.data_ptr(), ws.numel(), s.cuda_stream,
+                          out.data_ptr())
+        return out
+
+    def match(self, text) -> MatchResult:
+        try:
+            import torch
+            is_tensor = isinstance(text, torch.Tensor)
+        except ImportError:
+            is_tensor = False
+        if is_tensor and text.is_cuda:
+            out = self.match_async(text)
+            raw = out.cpu().numpy().tobytes()
+            res = MatchResult.from_bytes(raw)
+            if res.final_state == INVALID_STATE:
+                raise ParemError(PAREM_ESYMBOL, "parem_match_async")
+            return res
+        if is_tensor:
+            text = text.numpy()
+        arr = np.ascontiguousarray(np.frombuffer(text, dtype=np.uint8) if isinstance(text, (bytes, bytearray))
+                                   else text, dtype=np.uint8).reshape(-1)
+        return MatchResult.from_struct(parem_match(self.handle, arr.ctypes.data, arr.size))

@@ -1,0 +1,288 @@
+// C-ABI of the speculative chunked DFA walk: compile (validation, per-symbol
+// speculated sets, table layout, upload) and the match entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "parem_internal.h"
+
+using parem::DeviceDfa;
+
+namespace {
+
+template <typename T>
+parem_status upload(const std::vector<T> &h, T **d, size_t pad_to = 16) {
+    size_t bytes = h.size() * sizeof(T);
+    size_t alloc = std::max<size_t>((bytes + pad_to - 1) / pad_to * pad_to, pad_to);
+    if (hipMalloc(reinterpret_cast<void **>(d), alloc) != hipSuccess) return PAREM_ENOMEM;
+    if (hipMemset(*d, 0, alloc) != hipSuccess) return PAREM_EDEVICE;
+    if (bytes && hipMemcpy(*d, h.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) return PAREM_EDEVICE;
+    return PAREM_OK;
+}
+
+void release(DeviceDfa &d) {
+    hipFree(d.d_table);
+    hipFree(d.d_cls);
+    hipFree(d.d_loff);
+    hipFree(d.d_llist);
+    hipFree(d.d_final);
+    hipFree(d.d_verify);
+    d.d_table = nullptr;
+    d.d_cls = nullptr;
+    d.d_loff = nullptr;
+    d.d_llist = nullptr;
+    d.d_final = nullptr;
+    d.d_verify = nullptr;
+}
+
+uint32_t read_entry(const void *table, int eb, uint64_t k) {
+    switch (eb) {
+        case 1: return static_cast<const uint8_t *>(table)[k];
+        case 2: return static_cast<const uint16_t *>(table)[k];
+        default: return static_cast<const uint32_t *>(table)[k];
+    }
+}
+
+// Byte-indexed table: entry (q, x) = delta(q, column of x), the sentinel for
+// invalid bytes, with the destination's final flag in the entry's top bit.
+template <typename E>
+std::vector<E> byte_table(const DeviceDfa &d, const std::vector<uint32_t> &t) {
+    constexpr uint32_t acc_shift = sizeof(E) * 8 - 1;
+    std::vector<E> out((size_t)(d.Q + 1) * 256);
+    for (uint32_t q = 0; q <= d.Q; ++q) {
+        for (uint32_t x = 0; x < 256; ++x) {
+            uint32_t nx = d.sent;
+            if (q < d.Q && d.cls[x] < d.A) nx = t[(size_t)q * d.A + d.cls[x]];
+            out[(size_t)q * 256 + x] = (E)(nx | ((uint32_t)d.final_flag[nx] << acc_shift));
+        }
+    }
+    return out;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *parem_strerror(parem_status s) {
+    switch (s) {
+        case PAREM_OK: return "ok";
+        case PAREM_EINVAL: return "invalid argument";
+        case PAREM_ENOMEM: return "out of memory";
+        case PAREM_EDEVICE: return "HIP runtime error";
+        case PAREM_ESYMBOL: return "text byte outside the alphabet";
+        case PAREM_ESTATE: return "state id out of range";
+        case PAREM_EUNSUPPORTED: return "unsupported size";
+        default: return "unknown status";
+    }
+}
+
+parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_states, const uint8_t *alphabet,
+                           uint32_t alphabet_size, uint32_t start, const uint32_t *accepting,
+                           uint32_t num_accepting, const parem_options *opt, parem_handle *out) {
+    if (!out) return PAREM_EINVAL;
+    *out = nullptr;
+    if (!table || !alphabet || (num_accepting && !accepting)) return PAREM_EINVAL;
+    if (entry_bytes != 1 && entry_bytes != 2 && entry_bytes != 4) return PAREM_EINVAL;
+    if (num_states == 0 || alphabet_size == 0 || alphabet_size > 256) return PAREM_EINVAL;
+    if (num_states > 32767) return PAREM_EUNSUPPORTED;
+    if (start >= num_states) return PAREM_ESTATE;
+    parem_options o{};
+    if (opt) {
+        o = *opt;
+        for (uint32_t r : o.reserved)
+            if (r) return PAREM_EINVAL;
+        if (o.chunk_len % 64) return PAREM_EINVAL;
+        if (o.group && o.group != 2 && o.group != 4 && o.group != 8 && o.group != 16) return PAREM_EINVAL;
+        if (o.layout > PAREM_LAYOUT_SPARSE_LDS) return PAREM_EINVAL;
+    }
+
+    parem_dfa *h = new (std::nothrow) parem_dfa();
+    if (!h) return PAREM_ENOMEM;
+    DeviceDfa &d = h->dev;
+    d.Q = num_states;
+    d.A = alphabet_size;
+    d.start = start;
+    d.sent = num_states;
+    d.opt = o;
+    d.num_classes = d.A + 2;
+
+    d.cls.assign(256, (uint8_t)0);
+    std::vector<int> seen(256, 0);
+    for (uint32_t j = 0; j < d.A; ++j) {
+        if (seen[alphabet[j]]) {
+            delete h;
+            return PAREM_EINVAL;
+        }
+        seen[alphabet[j]] = 1;
+    }
+    // class A (invalid) does not fit in a byte when A == 256; all bytes are then valid
+    for (uint32_t x = 0; x < 256; ++x) d.cls[x] = (uint8_t)std::min<uint32_t>(d.A, 255);
+    for (uint32_t j = 0; j < d.A; ++j) d.cls[alphabet[j]] = (uint8_t)j;
+
+    std::vector<uint32_t> t((size_t)d.Q * d.A);
+    for (uint64_t k = 0; k < (uint64_t)d.Q * d.A; ++k) {
+        t[k] = read_entry(table, entry_bytes, k);
+        if (t[k] >= d.Q) {
+            delete h;
+            return PAREM_ESTATE;
+        }
+    }
+    d.final_flag.assign(d.Q + 1, 0);
+    for (uint32_t i = 0; i < num_accepting; ++i) {
+        if (accepting[i] >= d.Q) {
+            delete h;
+            return PAREM_ESTATE;
+        }
+        d.final_flag[accepting[i]] = 1;
+    }
+
+    // speculated set per class: image of the column (L of Algorithm 1), the
+    // sentinel after an invalid byte, and {q0} for the first chunk
+    d.loff.assign(d.num_classes + 1, 0);
+    d.llist.clear();
+    std::vector<uint8_t> mark(d.Q + 1);
+    for (uint32_t c = 0; c < d.num_classes; ++c) {
+        d.loff[c] = (uint32_t)d.llist.size();
+        if (c < d.A) {
+            std::fill(mark.begin(), mark.end(), 0);
+            for (uint32_t q = 0; q < d.Q; ++q) mark[t[(size_t)q * d.A + c]] = 1;
+            for (uint32_t q = 0; q <= d.Q; ++q)
+                if (mark[q]) d.llist.push_back(q);
+        } else if (c == d.A) {
+            d.llist.push_back(d.sent);
+        } else {
+            d.llist.push_back(d.start);
+        }
+        d.max_spec = std::max<uint32_t>(d.max_spec, (uint32_t)d.llist.size() - d.loff[c]);
+    }
+    d.loff[d.num_classes] = (uint32_t)d.llist.size();
+    d.total_list = (uint32_t)d.llist.size();
+
+    // layout
+    uint32_t layout = o.layout;
+    if (layout == PAREM_LAYOUT_AUTO) layout = (d.Q + 1 <= 128) ? PAREM_LAYOUT_BYTE_LDS : PAREM_LAYOUT_BYTE_GLOBAL;
+    if (layout == PAREM_LAYOUT_BYTE_LDS && d.Q + 1 > 128) layout = PAREM_LAYOUT_BYTE_GLOBAL;
+    if (layout != PAREM_LAYOUT_BYTE_LDS && layout != PAREM_LAYOUT_BYTE_GLOBAL) layout = PAREM_LAYOUT_BYTE_GLOBAL;
+    d.layout = layout;
+
+    parem_status st = PAREM_OK;
+    if (hipGetDevice(&d.device) != hipSuccess) st = PAREM_EDEVICE;
+    if (st == PAREM_OK) {
+        if (layout == PAREM_LAYOUT_BYTE_LDS) {
+            auto bt = byte_table<uint8_t>(d, t);
+            d.entry_bytes = 1;
+            d.lds_bytes = (uint32_t)((bt.size() + 15) / 16 * 16);
+            uint8_t *p = nullptr;
+            st = upload(bt, &p);
+            d.d_table = p;
+        } else {
+            auto bt = byte_table<uint16_t>(d, t);
+            d.entry_bytes = 2;
+            d.lds_bytes = 0;
+            uint16_t *p = nullptr;
+            st = upload(bt, &p);
+            d.d_table = p;
+        }
+    }
+    if (st == PAREM_OK) st = upload(d.cls, &d.d_cls);
+    if (st == PAREM_OK) st = upload(d.loff, &d.d_loff);
+    if (st == PAREM_OK) st = upload(d.llist, &d.d_llist);
+    if (st == PAREM_OK) st = upload(d.final_flag, &d.d_final);
+    if (st != PAREM_OK) {
+        release(d);
+        delete h;
+        return st;
+    }
+    *out = h;
+    return PAREM_OK;
+}
+
+void parem_free(parem_handle h) {
+    if (!h) return;
+    release(h->dev);
+    delete h;
+}
+
+parem_status parem_describe(parem_handle h, uint32_t *layout, uint32_t *max_spec, uint32_t *lds_bytes,
+                            uint32_t *kgram) {
+    if (!h) return PAREM_EINVAL;
+    if (layout) *layout = h->dev.layout;
+    if (max_spec) *max_spec = h->dev.max_spec;
+    if (lds_bytes) *lds_bytes = h->dev.lds_bytes;
+    if (kgram) *kgram = h->dev.kgram;
+    return PAREM_OK;
+}
+
+parem_status parem_workspace_size(parem_handle h, uint64_t len, uint64_t *bytes) {
+    if (!h || !bytes) return PAREM_EINVAL;
+    parem::PlainPlan p;
+    parem_status st = parem::plan_plain(h->dev, len, &p);
+    if (st != PAREM_OK) return st;
+    *bytes = p.bytes;
+    return PAREM_OK;
+}
+
+parem_status parem_match_async(parem_handle h, const uint8_t *d_text, uint64_t len, void *d_workspace,
+                               uint64_t workspace_bytes, void *stream, parem_result *d_out) {
+    if (!h || !d_out || (len && !d_text)) return PAREM_EINVAL;
+    parem::PlainPlan p;
+    parem_status st = parem::plan_plain(h->dev, len, &p);
+    if (st != PAREM_OK) return st;
+    if (len && (!d_workspace || workspace_bytes < p.bytes)) return PAREM_EINVAL;
+    return parem::launch_plain(h->dev, p, d_text, d_workspace, reinterpret_cast<hipStream_t>(stream), d_out);
+}
+
+parem_status parem_match_async_timed(parem_handle h, const uint8_t *d_text, uint64_t len, void *d_workspace,
+                                     uint64_t workspace_bytes, void *stream, parem_result *d_out,
+                                     void *ev_walk_begin, void *ev_walk_end) {
+    if (!h || !d_out || (len && !d_text)) return PAREM_EINVAL;
+    parem::PlainPlan p;
+    parem_status st = parem::plan_plain(h->dev, len, &p);
+    if (st != PAREM_OK) return st;
+    if (len && (!d_workspace || workspace_bytes < p.bytes)) return PAREM_EINVAL;
+    return parem::launch_plain(h->dev, p, d_text, d_workspace, reinterpret_cast<hipStream_t>(stream), d_out,
+                               reinterpret_cast<hipEvent_t>(ev_walk_begin), reinterpret_cast<hipEvent_t>(ev_walk_end));
+}
+
+parem_status parem_match(parem_handle h, const uint8_t *text, uint64_t len, parem_result *out) {
+    if (!h || !out || (len && !text)) return PAREM_EINVAL;
+    parem::PlainPlan p;
+    parem_status st = parem::plan_plain(h->dev, len, &p);
+    if (st != PAREM_OK) return st;
+
+    bool on_device = false;
+    if (len) {
+        hipPointerAttribute_t attr;
+        if (hipPointerGetAttributes(&attr, text) == hipSuccess) {
+            on_device = attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+        } else {
+            (void)hipGetLastError();  // plain host memory
+        }
+    }
+    uint8_t *staged = nullptr;
+    void *ws = nullptr;
+    parem_result *d_out = nullptr;
+    st = PAREM_OK;
+    if (len && !on_device) {
+        if (hipMalloc(&staged, len) != hipSuccess) st = PAREM_ENOMEM;
+        else if (hipMemcpy(staged, text, len, hipMemcpyHostToDevice) != hipSuccess) st = PAREM_EDEVICE;
+    }
+    if (st == PAREM_OK && p.bytes && hipMalloc(&ws, p.bytes) != hipSuccess) st = PAREM_ENOMEM;
+    if (st == PAREM_OK && hipMalloc(&d_out, sizeof(parem_result)) != hipSuccess) st = PAREM_ENOMEM;
+    if (st == PAREM_OK) {
+        const uint8_t *src = on_device ? text : staged;
+        st = parem::launch_plain(h->dev, p, src, ws, nullptr, d_out);
+    }
+    if (st == PAREM_OK && hipMemcpy(out, d_out, sizeof(parem_result), hipMemcpyDeviceToHost) != hipSuccess)
+        st = PAREM_EDEVICE;
+    hipFree(staged);
+    hipFree(ws);
+    hipFree(d_out);
+    if (st == PAREM_OK && out->final_state == 0xffffffffu) st = PAREM_ESYMBOL;
+    return st;
+}
+
+}  // extern "C"

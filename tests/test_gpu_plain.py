@@ -1,0 +1,205 @@
+"""GPU parity of the plain speculative walk against the CPU oracle.
+
+Bit-exact on (final state, accept flag, count) for every case, plus the
+number of speculated walks, which the test derives from the definition of
+the speculated set (the image of the column of the byte before each chunk;
+{q0} for the first chunk).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from conftest import gpu_available
+
+pytestmark = pytest.mark.gpu
+
+if gpu_available():
+    import torch
+    import paper_1412_1741_amd as P
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def expected_spec_runs(dfa, text, L):
+    n = text.size
+    if n == 0:
+        return 0
+    chunks = (n + L - 1) // L
+    col = np.full(256, -1, dtype=np.int64)
+    col[np.frombuffer(dfa.alphabet, dtype=np.uint8)] = np.arange(dfa.alphabet_size)
+    img = np.asarray([np.unique(dfa.table[:, j]).size for j in range(dfa.alphabet_size)], dtype=np.int64)
+    prev = text[np.arange(1, chunks, dtype=np.int64) * L - 1]
+    cols = col[prev]
+    sizes = np.where(cols >= 0, img[np.maximum(cols, 0)], 1)
+    return 1 + int(sizes.sum())
+
+
+def run_case(name, dfa, text, offset=0, **opts):
+    say(f"[case] {name}: Q={dfa.num_states} A={dfa.alphabet_size} n={text.size} opts={opts} off={offset}")
+    m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, **opts)
+    try:
+        buf = torch.empty(text.size + offset + 16, dtype=torch.uint8, device="cuda")
+        dev = buf[offset:offset + text.size]
+        if text.size:
+            dev.copy_(torch.from_numpy(text))
+        want = oracle.walk_dfa(dfa, text)
+        got = m.match(dev)
+        assert (got.final_state, got.accept, got.count) == (want.final_state, want.accept, want.count), name
+        L = opts.get("chunk_len") or None
+        if L is not None:
+            assert got.chunks == (text.size + L - 1) // L
+            assert got.spec_runs == expected_spec_runs(dfa, text, L)
+        assert got.rerun_chunks == 0
+        return got
+    finally:
+        m.close()
+
+
+def test_worked_example():
+    t1 = np.asarray([[1, 0, 0, 0, 0], [1, 2, 0, 0, 0], [1, 0, 3, 0, 0], [1, 4, 0, 0, 0], [1, 0, 0, 0, 5],
+                     [1, 0, 0, 0, 6], [1, 0, 0, 7, 0], [1, 0, 0, 0, 8], [1, 0, 0, 0, 0]], dtype=np.uint8)
+    dfa = W.Dfa(t1, b"parel", 0, np.asarray([8], dtype=np.uint32))
+    text = np.frombuffer(b"plaraparallelapareparapl" * 1000, dtype=np.uint8).copy()
+    for L in (64, 128, 4096):
+        run_case(f"example L={L}", dfa, text, chunk_len=L)
+
+
+def test_config1_full():
+    dfa, text, chunks = W.config1()
+    got = run_case("config1", dfa, text, chunk_len=text.size // chunks)
+    assert got.chunks == 1024
+    ref = oracle.parem(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, text, chunks)
+    assert got.spec_runs == ref.runs
+
+
+@pytest.mark.parametrize("group", [2, 4, 8, 16])
+def test_config2_small_groups(group):
+    dfa, text = W.config2(n=4 << 20)
+    run_case(f"config2 4MiB G={group}", dfa, text, chunk_len=1024, group=group)
+
+
+def test_config2_layouts():
+    dfa, text = W.config2(n=1 << 22)
+    run_case("config2 byte-global", dfa, text, chunk_len=2048, layout=P.LAYOUT_BYTE_GLOBAL)
+    run_case("config2 auto", dfa, text)
+
+
+def test_config2_full_size():
+    dfa, text = W.config2()
+    got = run_case("config2 1GiB", dfa, text)
+    assert got.chunks >= 1024
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 15, 16, 17, 63, 64, 65, 127, 1000, 4095, 4097, 65536 + 7])
+def test_ragged_and_tiny(n):
+    rng = np.random.default_rng(n)
+    dfa = W.random_dense_dfa(rng, 13, b"xyz", num_accepting=4)
+    text = W.uniform_text(rng, b"xyz", n)
+    for off in (0, 3):
+        run_case(f"tiny n={n}", dfa, text, offset=off, chunk_len=64)
+
+
+def test_start_final_and_empty():
+    t = np.asarray([[1, 0], [1, 1]], dtype=np.uint8)
+    dfa = W.Dfa(t, b"ab", 1, np.asarray([1], dtype=np.uint32))
+    run_case("start-final empty", dfa, np.zeros(0, dtype=np.uint8))
+    run_case("start-final", dfa, np.frombuffer(b"ab" * 100, dtype=np.uint8).copy(), chunk_len=64)
+
+
+def test_random_fuzz():
+    rng = np.random.default_rng(1234)
+    for i in range(60):
+        dfa, text = W.random_case(rng, max_states=100, max_alpha=12, max_len=20000)
+        L = int(rng.choice([64, 128, 256, 1024]))
+        g = int(rng.choice([2, 4, 8, 16]))
+        off = int(rng.integers(0, 16))
+        run_case(f"fuzz {i}", dfa, text, offset=off, chunk_len=L, group=g)
+
+
+def test_large_state_counts():
+    rng = np.random.default_rng(77)
+    for q in (128, 300, 1000, 4096):
+        dfa = W.random_dense_dfa(rng, q, bytes(range(0, 256, 16)), num_accepting=q // 8)
+        text = W.uniform_text(rng, dfa.alphabet, 1 << 18)
+        run_case(f"dense Q={q}", dfa, text, chunk_len=4096)
+
+
+def test_invalid_bytes():
+    rng = np.random.default_rng(5)
+    dfa = W.random_dense_dfa(rng, 9, b"ACGT", num_accepting=2)
+    base = W.uniform_text(rng, b"ACGT", 8192)
+    for pos in (0, 63, 64, 1000, 4095, 8191):
+        text = base.copy()
+        text[pos] = ord("N")
+        m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, chunk_len=64)
+        say(f"[case] invalid byte at {pos}")
+        dev = torch.from_numpy(text).cuda()
+        with pytest.raises(P.ParemError) as ei:
+            m.match(dev)
+        assert ei.value.status == P.PAREM_ESYMBOL
+        with pytest.raises(P.ParemError) as ei:
+            m.match(text)  # host path
+        assert ei.value.status == P.PAREM_ESYMBOL
+        m.close()
+
+
+def test_host_text_path():
+    dfa, text = W.config2(n=1 << 20)
+    m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting)
+    got = m.match(text)
+    want = oracle.walk_dfa(dfa, text)
+    assert (got.final_state, got.accept, got.count) == (want.final_state, want.accept, want.count)
+    m.close()
+
+
+def test_compile_errors():
+    with pytest.raises(P.ParemError) as ei:
+        P.parem_compile(np.asarray([[0, 2], [1, 1]], dtype=np.uint8), b"ab", 0, [1])
+    assert ei.value.status == P.PAREM_ESTATE
+    with pytest.raises(P.ParemError) as ei:
+        P.parem_compile(np.asarray([[0, 1], [1, 1]], dtype=np.uint8), b"aa", 0, [1])
+    assert ei.value.status == P.PAREM_EINVAL
+    with pytest.raises(P.ParemError) as ei:
+        P.parem_compile(np.asarray([[0, 1], [1, 1]], dtype=np.uint8), b"ab", 2, [1])
+    assert ei.value.status == P.PAREM_ESTATE
+    with pytest.raises(P.ParemError) as ei:
+        P.parem_compile(np.asarray([[0, 1], [1, 1]], dtype=np.uint8), b"ab", 0, [5])
+    assert ei.value.status == P.PAREM_ESTATE
+    with pytest.raises(P.ParemError) as ei:
+        P.parem_compile(np.asarray([[0, 1], [1, 1]], dtype=np.uint8), b"ab", 0, [1], chunk_len=100)
+    assert ei.value.status == P.PAREM_EINVAL
+
+
+def test_config3_reduced():
+    dfa, text = W.config3(n=64 << 20)
+    run_case("config3 64MiB", dfa, text)
+
+
+def test_config5_sample_pairs():
+    specs = W.config5_specs()
+    rng = np.random.default_rng(0)
+    picks = sorted(rng.choice(len(specs), size=12, replace=False).tolist())
+    for i in picks:
+        s = specs[i]
+        if s.text_len > (8 << 20):
+            s = W.PairSpec(s.index, s.num_states, s.alphabet_size, 8 << 20)
+        dfa, text = W.config5_pair(s)
+        run_case(f"config5 pair {i}", dfa, text)
+
+
+def test_repeat_determinism():
+    dfa, text = W.config2(n=1 << 22)
+    m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting)
+    dev = torch.from_numpy(text).cuda()
+    outs = set()
+    for _ in range(5):
+        r = m.match(dev)
+        outs.add((r.final_state, r.count, r.spec_runs))
+    assert len(outs) == 1
+    m.close()
