@@ -26,6 +26,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+WALK_KERNEL = {1: "k_walk_byte", 2: "k_walk_byte", 3: "k_walk_kgram"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_traffic.json")
 WALK_SOURCE = os.path.join(ROOT, "paper_1412_1741_amd", "csrc", "parem_walk.hip")
 
@@ -74,7 +75,11 @@ def main():
     ap.add_argument("--chunk-len", type=int, default=0)
     ap.add_argument("--group", type=int, default=0)
     ap.add_argument("--layout", type=int, default=0)
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--no-merge", action="store_true", help="walk every speculated run through its whole chunk")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="time a plain device copy of --size bytes instead (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -85,6 +90,24 @@ def main():
     import numpy as np
     import torch
 
+    if args.copy_calibration:
+        src = torch.randint(0, 255, (args.size,), dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(args.warmup):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.steps):
+            dst.copy_(src)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / args.steps
+        print(json.dumps({"copy_bytes": args.size, "read_bytes": args.size, "write_bytes": args.size,
+                          "ms": round(ms, 5), "GBps_read_plus_write": round(2 * args.size / ms / 1e6, 1)}))
+        return
+
     import paper_1412_1741_amd as P
     import workloads as W
 
@@ -93,7 +116,7 @@ def main():
     dev = torch.from_numpy(text).cuda()
     torch.cuda.synchronize()
     m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, chunk_len=args.chunk_len,
-                  group=args.group, layout=args.layout)
+                  group=args.group, layout=args.layout, tile=args.tile, no_merge=args.no_merge)
     desc = m.describe()
     ws = m.workspace(text.size)
     out = torch.empty(P.RESULT_BYTES, dtype=torch.uint8, device="cuda")
@@ -110,21 +133,27 @@ def main():
     first = P.MatchResult.from_bytes(out.cpu().numpy().tobytes())
 
     K = args.steps
-    evb = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-    eve = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-    for e in evb + eve:
-        e.record(stream)  # creates the underlying hipEvent_t
+    # whole-step throughput: K plain launches between two events
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     print(f"[bench] timing {K} steps", file=sys.stderr, flush=True)
     t_start.record(stream)
     for k in range(K):
-        launch(evb[k].cuda_event, eve[k].cuda_event)
+        launch()
     t_end.record(stream)
     torch.cuda.synchronize()
-    total_ms = t_start.elapsed_time(t_end)
-    ms_per_step = total_ms / K
+    ms_per_step = t_start.elapsed_time(t_end) / K
+
+    # walk kernel alone: events recorded around it inside each launch
+    evb = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    eve = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    for e in evb + eve:
+        e.record(stream)  # creates the underlying hipEvent_t
+    torch.cuda.synchronize()
+    for k in range(K):
+        launch(evb[k].cuda_event, eve[k].cuda_event)
+    torch.cuda.synchronize()
     walk_ms = [evb[k].elapsed_time(eve[k]) for k in range(K)]
     walk_avg_ms = statistics.mean(walk_ms)
     res = P.MatchResult.from_bytes(out.cpu().numpy().tobytes())
@@ -162,7 +191,7 @@ def main():
                    "bit_exact_vs_oracle": exact},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(n),
-                     "kernel": "k_walk_byte", "kernel_ms": round(walk_avg_ms, 5),
+                     "kernel": WALK_KERNEL.get(desc["layout"], "walk"), "kernel_ms": round(walk_avg_ms, 5),
                      "alg_bytes_per_launch": alg_bytes},
         "cpu_baseline": cpu,
     }

@@ -57,8 +57,12 @@ typedef struct {
     uint32_t chunk_len;   /* bytes per chunk, multiple of 64; 0 = automatic     */
     uint32_t layout;      /* PAREM_LAYOUT_*; AUTO lets the compile step choose  */
     uint32_t group;       /* speculated states walked in lockstep per lane; 0 = auto */
-    uint32_t kgram;       /* symbols per step for the k-gram layout; 0 = auto   */
-    uint32_t reserved[4]; /* must be zero                                        */
+    uint32_t kgram;       /* reserved for the k-gram step width; must be 0       */
+    uint32_t tile;        /* bytes of each chunk staged per load round: 64 or 128; 0 = auto */
+    uint32_t no_merge;    /* 1: every speculated run walks its whole chunk, as the
+                             paper's Algorithm 1 does; 0 (default): runs that
+                             reach the same state are merged (identical results) */
+    uint32_t reserved[2]; /* must be zero                                        */
 } parem_options;
 
 typedef struct {

@@ -10,6 +10,7 @@
 #include "parem_internal.h"
 
 using parem::DeviceDfa;
+using parem::KgParams;
 
 namespace {
 
@@ -30,6 +31,8 @@ void release(DeviceDfa &d) {
     hipFree(d.d_llist);
     hipFree(d.d_final);
     hipFree(d.d_verify);
+    hipFree(d.d_inv);
+    d.d_inv = nullptr;
     d.d_table = nullptr;
     d.d_cls = nullptr;
     d.d_loff = nullptr;
@@ -49,17 +52,92 @@ uint32_t read_entry(const void *table, int eb, uint64_t k) {
 // Byte-indexed table: entry (q, x) = delta(q, column of x), the sentinel for
 // invalid bytes, with the destination's final flag in the entry's top bit.
 template <typename E>
-std::vector<E> byte_table(const DeviceDfa &d, const std::vector<uint32_t> &t) {
+std::vector<E> byte_table(const DeviceDfa &d, const std::vector<uint32_t> &t, uint32_t row) {
     constexpr uint32_t acc_shift = sizeof(E) * 8 - 1;
-    std::vector<E> out((size_t)(d.Q + 1) * 256);
+    std::vector<E> out(((size_t)(d.Q + 1) * row * sizeof(E) + 15) / 16 * 16 / sizeof(E), (E)0);
     for (uint32_t q = 0; q <= d.Q; ++q) {
         for (uint32_t x = 0; x < 256; ++x) {
             uint32_t nx = d.sent;
             if (q < d.Q && d.cls[x] < d.A) nx = t[(size_t)q * d.A + d.cls[x]];
-            out[(size_t)q * 256 + x] = (E)(nx | ((uint32_t)d.final_flag[nx] << acc_shift));
+            out[(size_t)q * row + x] = (E)(nx | ((uint32_t)d.final_flag[nx] << acc_shift));
         }
     }
     return out;
+}
+
+// k-gram layout. Finds B bits and a shift such that (x >> shift) & (2^B - 1)
+// is distinct over the alphabet, then tabulates K-symbol steps. Returns false
+// when the alphabet has no such code or the table would not fit.
+bool build_kgram(DeviceDfa &d, const std::vector<uint32_t> &t, std::vector<uint8_t> &bytes) {
+    if (d.A > 8) return false;
+    uint32_t need = d.A <= 2 ? 1 : (d.A <= 4 ? 2 : 3);
+    std::vector<uint8_t> alpha(d.A);
+    for (uint32_t x = 0; x < 256; ++x)
+        if (d.cls[x] < d.A) alpha[d.cls[x]] = (uint8_t)x;
+    for (uint32_t B = need; B <= 3; ++B) {
+        const uint32_t mask = (1u << B) - 1u;
+        for (uint32_t shift = 0; shift + B <= 8; ++shift) {
+            std::vector<int> code2col(1u << B, -1);
+            bool ok = true;
+            for (uint32_t j = 0; j < d.A && ok; ++j) {
+                const uint32_t code = (alpha[j] >> shift) & mask;
+                if (code2col[code] != -1) ok = false;
+                else code2col[code] = (int)j;
+            }
+            if (!ok) continue;
+            const uint32_t K = (B == 3) ? 2 : 4;
+            const uint32_t RS = K * B + 1;
+            if (((uint64_t)(d.Q + 1) << RS) > 65536) return false;
+            const uint32_t tk_bytes = (d.Q + 1) << RS;
+            const uint32_t t1_bytes = (d.Q + 1) * (1u << B) * 2;
+            bytes.assign(((size_t)tk_bytes + t1_bytes + 15) / 16 * 16, 0);
+            auto put = [&](size_t off, uint32_t v) {
+                bytes[off] = (uint8_t)(v & 0xff);
+                bytes[off + 1] = (uint8_t)(v >> 8);
+            };
+            auto next = [&](uint32_t s, uint32_t code) -> uint32_t {
+                if (s == d.sent || code2col[code] < 0) return d.sent;
+                return t[(size_t)s * d.A + (uint32_t)code2col[code]];
+            };
+            const uint32_t ncols = 1u << (K * B);
+            for (uint32_t r = 0; r <= d.Q; ++r) {
+                for (uint32_t idx = 0; idx < ncols; ++idx) {
+                    uint32_t s = r, cnt = 0;
+                    for (uint32_t m = 0; m < K; ++m) {
+                        s = next(s, (idx >> (B * m)) & mask);
+                        cnt += d.final_flag[s];
+                    }
+                    put(((size_t)r << RS) + 2 * idx, (s << RS) | cnt);
+                }
+                for (uint32_t code = 0; code <= mask; ++code) {
+                    const uint32_t s = next(r, code);
+                    put(tk_bytes + (((size_t)r << B) | code) * 2, (s << RS) | d.final_flag[s]);
+                }
+            }
+            KgParams kp;
+            kp.shift = shift;
+            kp.cmask4 = mask * 0x01010101u;
+            kp.bits = B;
+            kp.t1_off = tk_bytes;
+            if (B == 1) kp.w0 = 0x10080402u;
+            else if (B == 2) kp.w0 = 0x80200802u;
+            else {
+                kp.w0 = 0x00001002u;
+                kp.w1 = 0x10020000u;
+            }
+            // expected byte of each code; an unused code expects a byte whose
+            // own code differs (alphabet[0]), so it never validates
+            uint8_t v[8];
+            for (uint32_t code = 0; code < 8; ++code)
+                v[code] = (code <= mask && code2col[code] >= 0) ? alpha[(uint32_t)code2col[code]] : alpha[0];
+            kp.vlo = v[0] | (v[1] << 8) | (v[2] << 16) | ((uint32_t)v[3] << 24);
+            kp.vhi = v[4] | (v[5] << 8) | (v[6] << 16) | ((uint32_t)v[7] << 24);
+            d.kg = kp;
+            d.kgram = K;
+            return true;
+        }
+    }
+    return false;
 }
 
 }  // namespace
@@ -94,9 +172,12 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
         o = *opt;
         for (uint32_t r : o.reserved)
             if (r) return PAREM_EINVAL;
-        if (o.chunk_len % 64) return PAREM_EINVAL;
+        if (o.chunk_len % 64 || o.chunk_len > parem::kMaxChunk) return PAREM_EINVAL;
         if (o.group && o.group != 2 && o.group != 4 && o.group != 8 && o.group != 16) return PAREM_EINVAL;
         if (o.layout > PAREM_LAYOUT_SPARSE_LDS) return PAREM_EINVAL;
+        if (o.tile && o.tile != 64 && o.tile != 128) return PAREM_EINVAL;
+        if (o.kgram) return PAREM_EINVAL;
+        if (o.no_merge > 1) return PAREM_EINVAL;
     }
 
     parem_dfa *h = new (std::nothrow) parem_dfa();
@@ -161,26 +242,46 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
     d.loff[d.num_classes] = (uint32_t)d.llist.size();
     d.total_list = (uint32_t)d.llist.size();
 
-    // layout
+    // layout: k-gram when the alphabet has a bit-field code and the table
+    // fits; else the byte table in LDS (Q+1 <= 128) or read through L2
     uint32_t layout = o.layout;
-    if (layout == PAREM_LAYOUT_AUTO) layout = (d.Q + 1 <= 128) ? PAREM_LAYOUT_BYTE_LDS : PAREM_LAYOUT_BYTE_GLOBAL;
-    if (layout == PAREM_LAYOUT_BYTE_LDS && d.Q + 1 > 128) layout = PAREM_LAYOUT_BYTE_GLOBAL;
-    if (layout != PAREM_LAYOUT_BYTE_LDS && layout != PAREM_LAYOUT_BYTE_GLOBAL) layout = PAREM_LAYOUT_BYTE_GLOBAL;
+    std::vector<uint8_t> kgbytes;
+    const bool kg_ok = (layout == PAREM_LAYOUT_AUTO || layout == PAREM_LAYOUT_KGRAM_LDS) && build_kgram(d, t, kgbytes);
+    const bool lds_ok = d.Q + 1 <= 128;
+    if (layout == PAREM_LAYOUT_AUTO || (layout == PAREM_LAYOUT_KGRAM_LDS && !kg_ok))
+        layout = kg_ok ? PAREM_LAYOUT_KGRAM_LDS : (lds_ok ? PAREM_LAYOUT_BYTE_LDS : PAREM_LAYOUT_BYTE_GLOBAL);
+    if (layout == PAREM_LAYOUT_BYTE_LDS && !lds_ok) layout = PAREM_LAYOUT_BYTE_GLOBAL;
+    if (layout == PAREM_LAYOUT_SPARSE_LDS) layout = PAREM_LAYOUT_BYTE_GLOBAL;
     d.layout = layout;
+    if (layout != PAREM_LAYOUT_KGRAM_LDS) {
+        d.kgram = 0;
+        d.kg = parem::KgParams{};
+    }
 
     parem_status st = PAREM_OK;
     if (hipGetDevice(&d.device) != hipSuccess) st = PAREM_EDEVICE;
     if (st == PAREM_OK) {
-        if (layout == PAREM_LAYOUT_BYTE_LDS) {
-            auto bt = byte_table<uint8_t>(d, t);
+        if (layout == PAREM_LAYOUT_KGRAM_LDS) {
+            d.entry_bytes = 2;
+            d.table_bytes = (uint32_t)kgbytes.size();
+            d.lds_bytes = d.table_bytes;
+            uint8_t *p = nullptr;
+            st = upload(kgbytes, &p);
+            d.d_table = p;
+        } else if (layout == PAREM_LAYOUT_BYTE_LDS) {
+            auto bt = byte_table<uint8_t>(d, t, parem::kByteLdsRow);
             d.entry_bytes = 1;
-            d.lds_bytes = (uint32_t)((bt.size() + 15) / 16 * 16);
+            d.row_stride = parem::kByteLdsRow;
+            d.table_bytes = (uint32_t)bt.size();
+            d.lds_bytes = d.table_bytes;
             uint8_t *p = nullptr;
             st = upload(bt, &p);
             d.d_table = p;
         } else {
-            auto bt = byte_table<uint16_t>(d, t);
+            auto bt = byte_table<uint16_t>(d, t, 256);
             d.entry_bytes = 2;
+            d.row_stride = 256;
+            d.table_bytes = (uint32_t)(bt.size() * 2);
             d.lds_bytes = 0;
             uint16_t *p = nullptr;
             st = upload(bt, &p);
@@ -191,6 +292,18 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
     if (st == PAREM_OK) st = upload(d.loff, &d.d_loff);
     if (st == PAREM_OK) st = upload(d.llist, &d.d_llist);
     if (st == PAREM_OK) st = upload(d.final_flag, &d.d_final);
+    // inverse index of the class lists (composition looks up the position of
+    // an end state in the next chunk's list); skipped when it would be huge
+    const uint64_t inv_entries = (uint64_t)d.num_classes * (d.Q + 1);
+    if (st == PAREM_OK && inv_entries * 2 <= (16u << 20)) {
+        std::vector<uint16_t> inv((size_t)((inv_entries + 1) / 2 * 2), (uint16_t)0xffff);
+        for (uint32_t c = 0; c < d.num_classes; ++c)
+            for (uint32_t k = d.loff[c]; k < d.loff[c + 1]; ++k)
+                inv[(size_t)c * (d.Q + 1) + d.llist[k]] = (uint16_t)(k - d.loff[c]);
+        const uint32_t bytes = (uint32_t)(inv.size() * 2);
+        d.inv_lds = bytes <= 16384 ? bytes : 0;
+        st = upload(inv, &d.d_inv);
+    }
     if (st != PAREM_OK) {
         release(d);
         delete h;

@@ -12,6 +12,20 @@
 
 namespace parem {
 
+// k-gram layout: a text byte x maps to the symbol code (x >> shift) & cmask
+// (B bits, B = 1..3, chosen so the alphabet's codes are distinct); one table
+// lookup consumes K = (B == 3 ? 2 : 4) symbols. A state is carried as its
+// table row base (state << RS, RS = K*B + 1 bytes per row of u16 entries);
+// entries hold (next state << RS) | (final destinations among the K steps).
+struct KgParams {
+    uint32_t shift = 0;
+    uint32_t cmask4 = 0;   // cmask in every byte
+    uint32_t w0 = 0, w1 = 0; // dot4 weights giving 2*index of symbols 0..K-1 (w1: second pair, B == 3)
+    uint32_t vlo = 0, vhi = 0; // expected byte of codes 0..3 / 4..7 (validation with v_perm)
+    uint32_t t1_off = 0;   // byte offset of the one-symbol table (tails)
+    uint32_t bits = 0;     // B
+};
+
 // Lists of speculated states are indexed by "class": the column of the byte
 // just before a chunk (0..A-1), the invalid-byte class A (list {SENT}) and the
 // start class A+1 (list {q0}, used by chunk 0).
@@ -27,6 +41,9 @@ struct DeviceDfa {
     uint32_t kgram = 0;          // symbols per k-gram step (k-gram layout)
     uint32_t sym_bits = 0;       // bits per symbol code (k-gram layout)
     uint32_t hash_shift = 0;     // symbol code = (byte >> hash_shift) & mask (k-gram layout)
+    uint32_t table_bytes = 0;    // bytes of d_table (16-byte padded)
+    uint32_t row_stride = 256;   // byte layouts: entries per table row in memory
+    KgParams kg{};
     parem_options opt{};
     int device = 0;
 
@@ -42,7 +59,9 @@ struct DeviceDfa {
     uint32_t *d_loff = nullptr;
     uint32_t *d_llist = nullptr;
     uint8_t *d_final = nullptr;
-    uint8_t *d_verify = nullptr;     // k-gram layout: expected byte per symbol code
+    uint8_t *d_verify = nullptr;     // unused (kept null)
+    uint16_t *d_inv = nullptr;       // [(A+2) * (Q+1)] position of a state in each class list, 0xffff if absent
+    uint32_t inv_lds = 0;            // bytes of d_inv staged in LDS by the compose kernels (0: read from L2)
 };
 
 // Workspace carving for one plain match.
@@ -53,6 +72,8 @@ struct PlainPlan {
     uint32_t RM = 0;         // map width (max_spec)
     uint32_t P = 0;          // maps composed per workgroup in the tree
     uint32_t G = 0;          // lockstep group
+    uint32_t tile = 0;       // staged tile bytes per chunk (64 or 128)
+    uint32_t merge = 1;      // 0: speculated runs are never merged
     std::vector<uint64_t> level_maps; // number of maps after each compose level
     uint64_t bytes = 0;
     // offsets into the workspace
@@ -61,6 +82,9 @@ struct PlainPlan {
     uint64_t off_b_end = 0, off_b_cnt = 0, off_b_cls = 0, off_b_runs = 0;
     uint64_t level_cap = 0;
 };
+
+constexpr uint32_t kByteLdsRow = 260;  // row stride of the LDS byte table
+constexpr uint32_t kMaxChunk = 32768;  // chunk maps pack a count < 2^16 beside the end state
 
 parem_status plan_plain(const DeviceDfa &d, uint64_t len, PlainPlan *p);
 parem_status launch_plain(const DeviceDfa &d, const PlainPlan &p, const uint8_t *d_text,

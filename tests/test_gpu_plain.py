@@ -84,10 +84,61 @@ def test_config2_small_groups(group):
     run_case(f"config2 4MiB G={group}", dfa, text, chunk_len=1024, group=group)
 
 
+
+def all_layouts():
+    return [P.LAYOUT_AUTO, P.LAYOUT_KGRAM_LDS, P.LAYOUT_BYTE_LDS, P.LAYOUT_BYTE_GLOBAL]
+
+
 def test_config2_layouts():
     dfa, text = W.config2(n=1 << 22)
-    run_case("config2 byte-global", dfa, text, chunk_len=2048, layout=P.LAYOUT_BYTE_GLOBAL)
-    run_case("config2 auto", dfa, text)
+    for lay in all_layouts():
+        for g in (4, 16):
+            run_case(f"config2 layout={lay} G={g}", dfa, text, chunk_len=2048, layout=lay, group=g)
+    m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting)
+    assert m.describe()["layout"] == P.LAYOUT_KGRAM_LDS and m.describe()["kgram"] == 4
+    m.close()
+
+
+@pytest.mark.parametrize("alphabet,kgram", [(b"ab", 4), (b"AC", 4), (b"ACG", 4), (b"01234", 2),
+                                             (b"01234567", 2), (b"@ABCDEFG", 2), (b"xyz", 4)])
+def test_kgram_code_widths(alphabet, kgram):
+    rng = np.random.default_rng(len(alphabet) * 7 + alphabet[0])
+    dfa = W.random_dense_dfa(rng, 23, alphabet, num_accepting=5)
+    m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, layout=P.LAYOUT_KGRAM_LDS)
+    d = m.describe()
+    m.close()
+    assert d["layout"] == P.LAYOUT_KGRAM_LDS and d["kgram"] == kgram, d
+    for n in (0, 5, 64, 1000, 65536 + 13):
+        text = W.uniform_text(rng, alphabet, n)
+        for off in (0, 5):
+            run_case(f"kgram {alphabet} n={n}", dfa, text, offset=off, chunk_len=128,
+                     layout=P.LAYOUT_KGRAM_LDS, group=4)
+
+
+def test_kgram_invalid_bytes():
+    rng = np.random.default_rng(8)
+    dfa = W.random_dense_dfa(rng, 9, b"ACGT", num_accepting=2)
+    base = W.uniform_text(rng, b"ACGT", 8192 + 5)
+    # bytes that share a symbol code with a valid byte must still be rejected
+    for pos, bad in ((0, ord("a")), (100, ord("E")), (4095, ord("V")), (8192 + 4, ord("c")), (4096, 0)):
+        text = base.copy()
+        text[pos] = bad
+        m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, chunk_len=64,
+                      layout=P.LAYOUT_KGRAM_LDS)
+        say(f"[case] kgram invalid byte {bad} at {pos}")
+        with pytest.raises(P.ParemError) as ei:
+            m.match(torch.from_numpy(text).cuda())
+        assert ei.value.status == P.PAREM_ESYMBOL
+        m.close()
+
+
+@pytest.mark.parametrize("tile", [64, 128])
+def test_config2_no_merge(tile):
+    """The paper's plain scheme: every speculated run walks its whole chunk."""
+    dfa, text = W.config2(n=1 << 22)
+    for g in (4, 16):
+        run_case(f"config2 no-merge G={g} tile={tile}", dfa, text, chunk_len=4096, group=g, no_merge=True,
+                 tile=tile)
 
 
 def test_config2_full_size():
@@ -119,7 +170,10 @@ def test_random_fuzz():
         L = int(rng.choice([64, 128, 256, 1024]))
         g = int(rng.choice([2, 4, 8, 16]))
         off = int(rng.integers(0, 16))
-        run_case(f"fuzz {i}", dfa, text, offset=off, chunk_len=L, group=g)
+        lay = int(rng.choice(all_layouts()))
+        nm = bool(rng.integers(0, 2))
+        tile = int(rng.choice([0, 64, 128]))
+        run_case(f"fuzz {i}", dfa, text, offset=off, chunk_len=L, group=g, layout=lay, no_merge=nm, tile=tile)
 
 
 def test_large_state_counts():
@@ -203,3 +257,24 @@ def test_repeat_determinism():
         outs.add((r.final_state, r.count, r.spec_runs))
     assert len(outs) == 1
     m.close()
+
+
+def test_nonsynchronizing_dfa():
+    """Permutation columns: speculated runs never meet, so every chunk map is
+    non-uniform and the general composition path runs."""
+    q = 7
+    alphabet = b"abc"
+    table = np.stack([(np.arange(q) + k + 1) % q for k in range(3)], axis=1).astype(np.uint8)
+    dfa = W.Dfa(table, alphabet, 2, np.asarray([0, 3], dtype=np.uint32))
+    rng = np.random.default_rng(17)
+    for n in (1, 100, 4096, 200003):
+        text = W.uniform_text(rng, alphabet, n)
+        for lay in all_layouts():
+            run_case(f"permutation n={n} layout={lay}", dfa, text, chunk_len=64, layout=lay, group=4)
+    # mixed: a synchronizing symbol 'r' resets to state 0
+    table2 = np.concatenate([table, np.zeros((q, 1), dtype=np.uint8)], axis=1)
+    dfa2 = W.Dfa(table2, b"abcr", 0, np.asarray([1, 5], dtype=np.uint32))
+    probs = np.asarray([0.33, 0.33, 0.33, 0.01])
+    text = np.frombuffer(b"abcr", dtype=np.uint8)[rng.choice(4, size=300000, p=probs)]
+    for lay in all_layouts():
+        run_case(f"mixed layout={lay}", dfa2, text, chunk_len=128, layout=lay, group=8)
