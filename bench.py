@@ -78,6 +78,10 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--no-merge", action="store_true", help="walk every speculated run through its whole chunk")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--modes", default="plain,paper,learned",
+                    help="comma list: plain (merged runs), paper (every run walks its chunk), learned")
+    ap.add_argument("--learned-m", default="1,4,16")
+    ap.add_argument("--train-steps", type=int, default=400)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="time a plain device copy of --size bytes instead (counter calibration)")
     args = ap.parse_args()
@@ -160,16 +164,74 @@ def main():
     assert (res.final_state, res.count) == (first.final_state, first.count)
 
     n = text.size
-    alg_bytes = n + res.spec_runs * 8 + res.chunks * 4
+    # per launch: text read + chunk maps written (4-byte packed entries, one
+    # 2-byte class and one 2-byte leader end per chunk)
+    alg_bytes = n + res.spec_runs * 4 + res.chunks * 4
     achieved = alg_bytes / (walk_avg_ms * 1e-3) / 1e9
     value = n / (ms_per_step * 1e-3) / 1e9
+    modes = {"plain_merged": {"GBps": round(value, 2), "ms": round(ms_per_step, 4), "spec_runs": res.spec_runs,
+                              "rerun_share": 0.0}}
+    results = {"plain_merged": res}
+    wanted = set(args.modes.split(","))
+
+    def timed(fn, steps):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(steps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    if "paper" in wanted:
+        print("[bench] paper scheme (no merging)", file=sys.stderr, flush=True)
+        mp = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, chunk_len=args.chunk_len,
+                       group=16, layout=args.layout, tile=args.tile, no_merge=True)
+        outp = torch.empty(P.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+        ms = timed(lambda: mp.match_async(dev, outp), max(3, K // 4))
+        rp = P.MatchResult.from_bytes(outp.cpu().numpy().tobytes())
+        results["plain_paper"] = rp
+        modes["plain_paper"] = {"GBps": round(n / (ms * 1e-3) / 1e9, 2), "ms": round(ms, 4),
+                                "spec_runs": rp.spec_runs, "rerun_share": 0.0}
+        mp.close()
+
+    if "learned" in wanted:
+        print("[bench] training the proposal", file=sys.stderr, flush=True)
+        _, train_text = W.config4_train_text()
+        tdev = torch.from_numpy(train_text).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prop, hist = P.train_proposal(m, tdev, W.mlp_init_params(dfa.num_states), steps=args.train_steps,
+                                      batch=4096, lr=2e-3, log_every=max(1, args.train_steps // 4), seed=1)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t0
+        del tdev
+        for mm in [int(x) for x in args.learned_m.split(",") if x]:
+            print(f"[bench] learned m={mm}", file=sys.stderr, flush=True)
+            outl = torch.empty(P.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+            ms = timed(lambda: m.match_learned_async(prop, dev, mm, outl), K)
+            rl = P.MatchResult.from_bytes(outl.cpu().numpy().tobytes())
+            results[f"learned_m{mm}"] = rl
+            modes[f"learned_m{mm}"] = {"GBps": round(n / (ms * 1e-3) / 1e9, 2), "ms": round(ms, 4),
+                                       "spec_runs": rl.spec_runs,
+                                       "rerun_share": round(rl.rerun_chunks / max(rl.chunks, 1), 6)}
+        modes["learned_training"] = {"text_bytes": int(train_text.size), "steps": args.train_steps,
+                                     "batch": 4096, "seconds": round(train_s, 3),
+                                     "loss": [[a, round(b, 5)] for a, b in hist]}
+        prop.close()
+    agree = all((r.final_state, r.accept, r.count) == (res.final_state, res.accept, res.count)
+                for r in results.values())
 
     cpu = None
     exact = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         ref, cpu = cpu_baseline(dfa, text)
-        exact = (ref.final_state, ref.accept, ref.count) == (res.final_state, res.accept, res.count)
+        exact = all((ref.final_state, ref.accept, ref.count) == (r.final_state, r.accept, r.count)
+                    for r in results.values())
 
     line = {
         "metric": "matched input GB/s & %HBM peak, learned vs plain speculation, bit-exact",
@@ -188,7 +250,7 @@ def main():
                    "alphabet": 4, "mode": "plain", "chunk_len": int(n // max(res.chunks, 1)) if res.chunks else 0,
                    "chunks": res.chunks, "layout": desc["layout"], "max_spec": desc["max_spec"],
                    "spec_runs": res.spec_runs, "rerun_share": 0.0, "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
-                   "bit_exact_vs_oracle": exact},
+                   "bit_exact_vs_oracle": exact, "modes_agree": agree, "modes": modes},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(n),
                      "kernel": WALK_KERNEL.get(desc["layout"], "walk"), "kernel_ms": round(walk_avg_ms, 5),

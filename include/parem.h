@@ -33,6 +33,7 @@ extern "C" {
 #endif
 
 typedef struct parem_dfa *parem_handle;
+typedef struct parem_proposal_s *parem_proposal;
 
 typedef enum {
     PAREM_OK = 0,
@@ -148,6 +149,85 @@ parem_status parem_match_async_timed(parem_handle h, const uint8_t *d_text, uint
  * a byte is not in the alphabet.
  */
 parem_status parem_match(parem_handle h, const uint8_t *text, uint64_t len, parem_result *out);
+
+/*
+ * States at chunk boundaries: the true state of the run after the first
+ * c * chunk_len bytes, for c = 0 .. ceil(len / chunk_len) - 1 (the entry
+ * state of every chunk; Section II-B: chunk c is entered in chunk c-1's
+ * exit). Computed with the plain speculative walk, an up-sweep composition
+ * that keeps every level, and a down-sweep that hands each map its entry.
+ *  d_states     device, u32 per chunk (0xFFFFFFFF after a byte outside the
+ *               alphabet).
+ *  d_workspace  device, parem_boundary_workspace_size bytes.
+ */
+parem_status parem_boundary_workspace_size(parem_handle h, uint64_t len, uint32_t chunk_len, uint64_t *bytes);
+parem_status parem_boundary_states(parem_handle h, const uint8_t *d_text, uint64_t len, uint32_t chunk_len,
+                                   uint32_t *d_states, void *d_workspace, uint64_t workspace_bytes,
+                                   void *stream);
+
+/*
+ * Learned speculation proposal (not in the paper). A small network scores
+ * the states at a chunk boundary from the 32 bytes before it:
+ * 16-d embedding per byte (bytes before the text start embed as zero) ->
+ * 512 -> 256 (GELU) -> 256 (GELU) -> one logit per state. Parameters are one
+ * flat float vector, in this order: emb[256][16], W1[256][512], b1[256],
+ * W2[256][256], b2[256], W3[Q][256], b3[Q]; nparams must equal
+ * 4096 + 131328 + 65792 + 257 * Q. Layers run as bf16 MFMA products with
+ * fp32 accumulation; the fp32 master copy is updated by AdamW
+ * (beta1 0.9, beta2 0.999, eps 1e-8, decoupled weight decay).
+ *
+ * parem_proposal_create   copies the host params; the proposal keeps a
+ *                         pointer to h (free the proposal first).
+ * parem_proposal_train_step
+ *                         one AdamW step on the mean masked softmax
+ *                         cross-entropy of `batch` boundaries: d_positions
+ *                         (u64, device) are byte offsets into d_text, and
+ *                         d_labels (u32, device) the true states there. Only
+ *                         the states of the boundary's speculated set (the
+ *                         image of the column of the byte before it) take
+ *                         part in the softmax; the label must be one of them.
+ *                         lr = 0 and weight_decay = 0 compute the gradient
+ *                         without updating. d_loss (device float, may be
+ *                         NULL) receives the mean loss.
+ * parem_proposal_params   copies the fp32 weights and the last gradient
+ *                         (either pointer may be NULL) to the host.
+ * parem_proposal_logits   logits [batch][Q] (device fp32) at d_positions.
+ */
+parem_status parem_proposal_create(parem_handle h, const float *params, uint64_t nparams, parem_proposal *out);
+void parem_proposal_free(parem_proposal p);
+parem_status parem_proposal_params(parem_proposal p, float *params_out, float *grad_out, uint64_t nparams);
+parem_status parem_proposal_train_step(parem_proposal p, const uint8_t *d_text, uint64_t len,
+                                       const uint64_t *d_positions, const uint32_t *d_labels, uint32_t batch,
+                                       float lr, float weight_decay, void *stream, float *d_loss);
+parem_status parem_proposal_logits(parem_proposal p, const uint8_t *d_text, const uint64_t *d_positions,
+                                   uint32_t batch, float *d_logits, void *stream);
+
+/*
+ * The selection learned speculation walks: for each chunk c of chunk_len
+ * bytes, the positions (within the chunk's speculated list, which is sorted
+ * by state id) of its m best-scored states, ascending, in d_sel[c * m ..];
+ * d_nsel[c] = min(m, |R_c|). Chunk 0 selects {q0}. Ties: the lower state id.
+ * Workspace: parem_proposal_select_size bytes.
+ */
+parem_status parem_proposal_select_size(parem_proposal p, uint64_t len, uint32_t chunk_len, uint64_t *bytes);
+parem_status parem_proposal_select(parem_proposal p, const uint8_t *d_text, uint64_t len, uint32_t chunk_len,
+                                   uint32_t m, uint16_t *d_sel, uint8_t *d_nsel, void *d_workspace,
+                                   uint64_t workspace_bytes, void *stream);
+
+/*
+ * Match with learned speculation: every chunk c >= 1 walks only the m states
+ * of its speculated set R_c that the proposal scores highest (ties: lower
+ * state id; all of R_c when |R_c| <= m). A chunk whose entry states are not
+ * all covered (some end state of its predecessor's walks was not walked
+ * here) is walked again from all of R_c, which holds every possible entry;
+ * this repeats until every chunk is covered, so the result is the sequential
+ * run's, exactly. rerun_chunks counts the chunks walked again. 1 <= m <= 16.
+ * Workspace from parem_learned_workspace_size.
+ */
+parem_status parem_learned_workspace_size(parem_handle h, parem_proposal p, uint64_t len, uint64_t *bytes);
+parem_status parem_match_learned_async(parem_handle h, parem_proposal p, uint32_t m, const uint8_t *d_text,
+                                       uint64_t len, void *d_workspace, uint64_t workspace_bytes, void *stream,
+                                       parem_result *d_out, void *ev_walk_begin, void *ev_walk_end);
 
 #ifdef __cplusplus
 }

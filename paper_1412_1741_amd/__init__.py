@@ -80,6 +80,28 @@ def _load() -> ctypes.CDLL:
     lib.parem_match_async_timed.argtypes = [vp, vp, u64, vp, u64, vp, vp, vp, vp]
     lib.parem_match.restype = i32
     lib.parem_match.argtypes = [vp, vp, u64, ctypes.POINTER(Result)]
+    lib.parem_boundary_workspace_size.restype = i32
+    lib.parem_boundary_workspace_size.argtypes = [vp, u64, u32, ctypes.POINTER(u64)]
+    lib.parem_boundary_states.restype = i32
+    lib.parem_boundary_states.argtypes = [vp, vp, u64, u32, vp, vp, u64, vp]
+    lib.parem_proposal_create.restype = i32
+    lib.parem_proposal_create.argtypes = [vp, vp, u64, ctypes.POINTER(vp)]
+    lib.parem_proposal_free.restype = None
+    lib.parem_proposal_free.argtypes = [vp]
+    lib.parem_proposal_params.restype = i32
+    lib.parem_proposal_params.argtypes = [vp, vp, vp, u64]
+    lib.parem_proposal_train_step.restype = i32
+    lib.parem_proposal_train_step.argtypes = [vp, vp, u64, vp, vp, u32, ctypes.c_float, ctypes.c_float, vp, vp]
+    lib.parem_proposal_logits.restype = i32
+    lib.parem_proposal_logits.argtypes = [vp, vp, vp, u32, vp, vp]
+    lib.parem_proposal_select_size.restype = i32
+    lib.parem_proposal_select_size.argtypes = [vp, u64, u32, ctypes.POINTER(u64)]
+    lib.parem_proposal_select.restype = i32
+    lib.parem_proposal_select.argtypes = [vp, vp, u64, u32, u32, vp, vp, vp, u64, vp]
+    lib.parem_learned_workspace_size.restype = i32
+    lib.parem_learned_workspace_size.argtypes = [vp, vp, u64, ctypes.POINTER(u64)]
+    lib.parem_match_learned_async.restype = i32
+    lib.parem_match_learned_async.argtypes = [vp, vp, u32, vp, u64, vp, u64, vp, vp, vp, vp]
     return lib
 
 
@@ -87,7 +109,11 @@ _lib = None
 
 # every symbol the header declares, for the export check
 EXPORTED = ["parem_compile", "parem_free", "parem_strerror", "parem_describe", "parem_workspace_size",
-            "parem_match_async", "parem_match_async_timed", "parem_match"]
+            "parem_match_async", "parem_match_async_timed", "parem_match", "parem_boundary_workspace_size",
+            "parem_boundary_states", "parem_proposal_create", "parem_proposal_free", "parem_proposal_params",
+            "parem_proposal_train_step", "parem_proposal_logits", "parem_proposal_select_size",
+            "parem_proposal_select", "parem_learned_workspace_size",
+            "parem_match_learned_async"]
 
 
 def lib() -> ctypes.CDLL:
@@ -163,6 +189,82 @@ def parem_match_async_timed(handle: int, d_text_ptr: int, length: int, d_workspa
                                         ev_end or None), "parem_match_async_timed")
 
 
+def parem_boundary_workspace_size(handle: int, length: int, chunk_len: int) -> int:
+    n = ctypes.c_uint64()
+    _check(lib().parem_boundary_workspace_size(handle, int(length), int(chunk_len), ctypes.byref(n)),
+           "parem_boundary_workspace_size")
+    return n.value
+
+
+def parem_boundary_states(handle: int, d_text_ptr: int, length: int, chunk_len: int, d_states_ptr: int,
+                          d_workspace_ptr: int, workspace_bytes: int, stream_ptr: int) -> None:
+    _check(lib().parem_boundary_states(handle, d_text_ptr or None, int(length), int(chunk_len), d_states_ptr or None,
+                                       d_workspace_ptr or None, int(workspace_bytes), stream_ptr or None),
+           "parem_boundary_states")
+
+
+def parem_proposal_create(handle: int, params: np.ndarray) -> int:
+    w = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+    out = ctypes.c_void_p()
+    _check(lib().parem_proposal_create(handle, w.ctypes.data, w.size, ctypes.byref(out)), "parem_proposal_create")
+    return out.value
+
+
+def parem_proposal_free(proposal: int) -> None:
+    lib().parem_proposal_free(proposal)
+
+
+def parem_proposal_params(proposal: int, nparams: int, grad: bool = False) -> np.ndarray:
+    out = np.empty(nparams, dtype=np.float32)
+    if grad:
+        _check(lib().parem_proposal_params(proposal, None, out.ctypes.data, nparams), "parem_proposal_params")
+    else:
+        _check(lib().parem_proposal_params(proposal, out.ctypes.data, None, nparams), "parem_proposal_params")
+    return out
+
+
+def parem_proposal_train_step(proposal: int, d_text_ptr: int, length: int, d_pos_ptr: int, d_labels_ptr: int,
+                              batch: int, lr: float, weight_decay: float, stream_ptr: int, d_loss_ptr: int) -> None:
+    _check(lib().parem_proposal_train_step(proposal, d_text_ptr, int(length), d_pos_ptr, d_labels_ptr, int(batch),
+                                           float(lr), float(weight_decay), stream_ptr or None, d_loss_ptr or None),
+           "parem_proposal_train_step")
+
+
+def parem_proposal_logits(proposal: int, d_text_ptr: int, d_pos_ptr: int, batch: int, d_logits_ptr: int,
+                          stream_ptr: int) -> None:
+    _check(lib().parem_proposal_logits(proposal, d_text_ptr, d_pos_ptr, int(batch), d_logits_ptr,
+                                       stream_ptr or None), "parem_proposal_logits")
+
+
+def parem_proposal_select_size(proposal: int, length: int, chunk_len: int) -> int:
+    n = ctypes.c_uint64()
+    _check(lib().parem_proposal_select_size(proposal, int(length), int(chunk_len), ctypes.byref(n)),
+           "parem_proposal_select_size")
+    return n.value
+
+
+def parem_proposal_select(proposal: int, d_text_ptr: int, length: int, chunk_len: int, m: int, d_sel_ptr: int,
+                          d_nsel_ptr: int, d_workspace_ptr: int, workspace_bytes: int, stream_ptr: int) -> None:
+    _check(lib().parem_proposal_select(proposal, d_text_ptr, int(length), int(chunk_len), int(m), d_sel_ptr,
+                                       d_nsel_ptr, d_workspace_ptr, int(workspace_bytes), stream_ptr or None),
+           "parem_proposal_select")
+
+
+def parem_learned_workspace_size(handle: int, proposal: int, length: int) -> int:
+    n = ctypes.c_uint64()
+    _check(lib().parem_learned_workspace_size(handle, proposal, int(length), ctypes.byref(n)),
+           "parem_learned_workspace_size")
+    return n.value
+
+
+def parem_match_learned_async(handle: int, proposal: int, m: int, d_text_ptr: int, length: int,
+                              d_workspace_ptr: int, workspace_bytes: int, stream_ptr: int, d_out_ptr: int,
+                              ev_begin: int = 0, ev_end: int = 0) -> None:
+    _check(lib().parem_match_learned_async(handle, proposal, int(m), d_text_ptr or None, int(length),
+                                           d_workspace_ptr or None, int(workspace_bytes), stream_ptr or None,
+                                           d_out_ptr, ev_begin or None, ev_end or None), "parem_match_learned_async")
+
+
 def parem_match(handle: int, text_ptr: int, length: int) -> Result:
     """Synchronous match on a host or device address."""
     r = Result()
@@ -198,7 +300,9 @@ class Matcher:
 
     def __init__(self, table, alphabet, start, accepting, **opts):
         self.handle = parem_compile(table, alphabet, start, accepting, **opts)
+        self.num_states = int(np.asarray(table).shape[0])
         self._ws = None
+        self._lws = None
 
     def close(self):
         if self.handle:
@@ -213,6 +317,34 @@ class Matcher:
 
     def describe(self) -> dict:
         return parem_describe(self.handle)
+
+    def describe_states(self) -> int:
+        return self.num_states
+
+    def learned_workspace(self, proposal: "Proposal", length: int):
+        import torch
+        need = parem_learned_workspace_size(self.handle, proposal.handle, length)
+        if self._lws is None or self._lws.numel() < need:
+            self._lws = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
+        return self._lws
+
+    def match_learned_async(self, proposal: "Proposal", text, m: int, out=None, ev_begin=0, ev_end=0):
+        import torch
+        assert text.is_cuda and text.dtype == torch.uint8 and text.is_contiguous()
+        ws = self.learned_workspace(proposal, text.numel())
+        if out is None:
+            out = torch.empty(RESULT_BYTES, dtype=torch.uint8, device=text.device)
+        parem_match_learned_async(self.handle, proposal.handle, m, text.data_ptr(), text.numel(), ws.data_ptr(),
+                                  ws.numel(), torch.cuda.current_stream().cuda_stream, out.data_ptr(), ev_begin,
+                                  ev_end)
+        return out
+
+    def match_learned(self, proposal: "Proposal", text, m: int) -> MatchResult:
+        out = self.match_learned_async(proposal, text, m)
+        res = MatchResult.from_bytes(out.cpu().numpy().tobytes())
+        if res.final_state == INVALID_STATE:
+            raise ParemError(PAREM_ESYMBOL, "parem_match_learned_async")
+        return res
 
     def workspace(self, length: int):
         import torch
@@ -252,3 +384,113 @@ class Matcher:
         arr = np.ascontiguousarray(np.frombuffer(text, dtype=np.uint8) if isinstance(text, (bytes, bytearray))
                                    else text, dtype=np.uint8).reshape(-1)
         return MatchResult.from_struct(parem_match(self.handle, arr.ctypes.data, arr.size))
+
+
+# ---------------------------------------------------------------------------
+# learned proposal
+# ---------------------------------------------------------------------------
+
+MLP_WINDOW = 32
+
+
+def proposal_param_count(states: int) -> int:
+    """4096 (embedding) + 131328 (layer 1) + 65792 (layer 2) + 257 per state."""
+    return 256 * 16 + 256 * 512 + 256 + 256 * 256 + 256 + 257 * states
+
+
+class Proposal:
+    """Owns a proposal network on the device (fp32 master weights, bf16 copy)."""
+
+    def __init__(self, matcher: "Matcher", params):
+        self.matcher = matcher
+        self.states = int(matcher.describe_states())
+        self.nparams = proposal_param_count(self.states)
+        p = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+        if p.size != self.nparams:
+            raise ValueError(f"expected {self.nparams} parameters, got {p.size}")
+        self.handle = parem_proposal_create(matcher.handle, p)
+
+    def close(self):
+        if self.handle:
+            parem_proposal_free(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        return parem_proposal_params(self.handle, self.nparams)
+
+    def grad(self) -> np.ndarray:
+        return parem_proposal_params(self.handle, self.nparams, grad=True)
+
+    def logits(self, text, positions):
+        import torch
+        pos = torch.as_tensor(np.asarray(positions, dtype=np.uint64).view(np.int64), device=text.device)
+        out = torch.empty((pos.numel(), self.states), dtype=torch.float32, device=text.device)
+        parem_proposal_logits(self.handle, text.data_ptr(), pos.data_ptr(), pos.numel(), out.data_ptr(),
+                              torch.cuda.current_stream().cuda_stream)
+        return out
+
+    def select(self, text, chunk_len: int, m: int):
+        """(positions [chunks, m] within each chunk's speculated list, counts)"""
+        import torch
+        n = text.numel()
+        chunks = (n + chunk_len - 1) // chunk_len
+        ws = torch.empty(parem_proposal_select_size(self.handle, n, chunk_len), dtype=torch.uint8,
+                         device=text.device)
+        sel = torch.zeros((chunks, m), dtype=torch.int16, device=text.device)
+        nsel = torch.zeros(chunks, dtype=torch.uint8, device=text.device)
+        parem_proposal_select(self.handle, text.data_ptr(), n, chunk_len, m, sel.data_ptr(), nsel.data_ptr(),
+                              ws.data_ptr(), ws.numel(), torch.cuda.current_stream().cuda_stream)
+        return sel, nsel
+
+    def train_step(self, text, positions, labels, lr: float, weight_decay: float = 0.01):
+        """positions / labels: int64 / int32 device tensors. Returns the loss
+        as a device tensor (no synchronisation)."""
+        import torch
+        loss = torch.zeros(1, dtype=torch.float32, device=text.device)
+        parem_proposal_train_step(self.handle, text.data_ptr(), text.numel(), positions.data_ptr(),
+                                  labels.data_ptr(), positions.numel(), lr, weight_decay,
+                                  torch.cuda.current_stream().cuda_stream, loss.data_ptr())
+        return loss
+
+
+def boundary_states(matcher: "Matcher", text, chunk_len: int):
+    """True state at every multiple of chunk_len (device u32 tensor, one per
+    chunk), computed by the HIP walk + composition + down-sweep."""
+    import torch
+    n = text.numel()
+    chunks = (n + chunk_len - 1) // chunk_len
+    need = parem_boundary_workspace_size(matcher.handle, n, chunk_len)
+    ws = torch.empty(max(need, 256), dtype=torch.uint8, device=text.device)
+    out = torch.empty(max(chunks, 1), dtype=torch.int32, device=text.device)
+    parem_boundary_states(matcher.handle, text.data_ptr(), n, chunk_len, out.data_ptr(), ws.data_ptr(), ws.numel(),
+                          torch.cuda.current_stream().cuda_stream)
+    return out[:chunks]
+
+
+def train_proposal(matcher: "Matcher", text, params, *, steps: int, batch: int = 4096, lr: float = 1e-3,
+                   weight_decay: float = 0.01, label_stride: int = 64, seed: int = 0, log_every: int = 0):
+    """Train a proposal on the states at every label_stride bytes of `text`
+    (a device uint8 tensor). Labels come from boundary_states (the HIP path).
+    Returns (Proposal, list of (step, loss))."""
+    import torch
+    prop = Proposal(matcher, params)
+    states = boundary_states(matcher, text, label_stride)
+    n_lab = states.numel()
+    pos_all = torch.arange(n_lab, dtype=torch.int64, device=text.device) * label_stride
+    keep = pos_all > 0  # the first boundary (q0, no window) teaches nothing
+    pos_all, states = pos_all[keep], states[keep]
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    history = []
+    n = pos_all.numel()
+    for step in range(steps):
+        idx = torch.randint(0, n, (batch,), generator=g).to(text.device)
+        loss = prop.train_step(text, pos_all[idx].contiguous(), states[idx].contiguous(), lr, weight_decay)
+        if log_every and (step % log_every == 0 or step == steps - 1):
+            history.append((step, float(loss.item())))
+    return prop, history

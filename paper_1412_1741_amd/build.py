@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libparem.so")
 
-SOURCES = ["parem_api.cpp", "parem_walk.hip"]
+SOURCES = ["parem_api.cpp", "parem_walk.hip", "parem_mlp.hip"]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",

@@ -360,6 +360,47 @@ parem_status parem_match_async_timed(parem_handle h, const uint8_t *d_text, uint
                                reinterpret_cast<hipEvent_t>(ev_walk_begin), reinterpret_cast<hipEvent_t>(ev_walk_end));
 }
 
+parem_status parem_boundary_workspace_size(parem_handle h, uint64_t len, uint32_t chunk_len, uint64_t *bytes) {
+    if (!h || !bytes || chunk_len == 0) return PAREM_EINVAL;
+    parem::PlainPlan p;
+    parem_status st = parem::plan_boundary(h->dev, len, chunk_len, &p);
+    if (st != PAREM_OK) return st;
+    *bytes = p.bytes;
+    return PAREM_OK;
+}
+
+parem_status parem_boundary_states(parem_handle h, const uint8_t *d_text, uint64_t len, uint32_t chunk_len,
+                                   uint32_t *d_states, void *d_workspace, uint64_t workspace_bytes, void *stream) {
+    if (!h || (len && (!d_text || !d_states)) || chunk_len == 0) return PAREM_EINVAL;
+    parem::PlainPlan p;
+    parem_status st = parem::plan_boundary(h->dev, len, chunk_len, &p);
+    if (st != PAREM_OK) return st;
+    if (len && (!d_workspace || workspace_bytes < p.bytes)) return PAREM_EINVAL;
+    return parem::launch_boundary(h->dev, p, d_text, d_states, d_workspace, reinterpret_cast<hipStream_t>(stream));
+}
+
+parem_status parem_learned_workspace_size(parem_handle h, parem_proposal pr, uint64_t len, uint64_t *bytes) {
+    if (!h || !pr || !bytes) return PAREM_EINVAL;
+    parem::PlainPlan p;
+    parem_status st = parem::plan_learned(h->dev, *pr, len, 16, &p);
+    if (st != PAREM_OK) return st;
+    *bytes = p.bytes;
+    return PAREM_OK;
+}
+
+parem_status parem_match_learned_async(parem_handle h, parem_proposal pr, uint32_t m, const uint8_t *d_text,
+                                       uint64_t len, void *d_workspace, uint64_t workspace_bytes, void *stream,
+                                       parem_result *d_out, void *ev_walk_begin, void *ev_walk_end) {
+    if (!h || !pr || !d_out || (len && !d_text) || m == 0 || m > 16) return PAREM_EINVAL;
+    if (pr->dfa != &h->dev) return PAREM_EINVAL;
+    parem::PlainPlan p;
+    parem_status st = parem::plan_learned(h->dev, *pr, len, m, &p);
+    if (st != PAREM_OK) return st;
+    if (len && (!d_workspace || workspace_bytes < p.bytes)) return PAREM_EINVAL;
+    return parem::launch_learned(h->dev, *pr, p, d_text, d_workspace, reinterpret_cast<hipStream_t>(stream), d_out,
+                                 reinterpret_cast<hipEvent_t>(ev_walk_begin), reinterpret_cast<hipEvent_t>(ev_walk_end));
+}
+
 parem_status parem_match(parem_handle h, const uint8_t *text, uint64_t len, parem_result *out) {
     if (!h || !out || (len && !text)) return PAREM_EINVAL;
     parem::PlainPlan p;

@@ -64,35 +64,82 @@ struct DeviceDfa {
     uint32_t inv_lds = 0;            // bytes of d_inv staged in LDS by the compose kernels (0: read from L2)
 };
 
-// Workspace carving for one plain match.
+// learned proposal network dimensions (32-byte window, 16-d embeddings)
+constexpr uint32_t kMlpWindow = 32;
+constexpr uint32_t kMlpEmb = 16;
+constexpr uint32_t kMlpIn = kMlpWindow * kMlpEmb;
+constexpr uint32_t kMlpHid = 256;
+
+// end state of an entry that was not walked (learned speculation)
+constexpr uint32_t kAbsent16 = 0xffffu;
+constexpr uint32_t kAbsent32 = 0xffffffffu;
+
+struct Proposal {
+    const DeviceDfa *dfa = nullptr;
+    uint32_t S = 0;              // head rows (= Q)
+    size_t nparams = 0;
+    size_t o_emb = 0, o_W1 = 0, o_b1 = 0, o_W2 = 0, o_b2 = 0, o_W3 = 0, o_b3 = 0;
+    float *d_params = nullptr;   // fp32 master weights
+    uint16_t *d_params16 = nullptr;
+    float *d_grad = nullptr, *d_m = nullptr, *d_v = nullptr;
+    uint64_t step = 0;
+    // training scratch (grown on demand)
+    void *t_buf = nullptr;
+    uint32_t cap_batch = 0;
+    size_t t_pos = 0, t_lab = 0, t_win = 0, t_cls = 0, t_X = 0, t_pre1 = 0, t_H1 = 0, t_pre2 = 0, t_H2 = 0,
+           t_Z = 0, t_dZ32 = 0, t_dZ16 = 0, t_dA2_32 = 0, t_dA2_16 = 0, t_dA1_32 = 0, t_dA1_16 = 0, t_dX = 0,
+           t_loss = 0;
+};
+
+void proposal_layout(Proposal &p);
+size_t proposal_infer_bytes(const Proposal &p, uint64_t rows);
+parem_status proposal_select(const Proposal &p, const uint8_t *d_text, uint64_t L, uint32_t chunks, uint32_t m,
+                             uint32_t RM, void *scratch, hipStream_t s, uint16_t *sel, uint8_t *nsel);
+
+// Workspace carving for one match.
 struct PlainPlan {
     uint64_t n = 0;
     uint32_t L = 0;          // chunk length
     uint64_t chunks = 0;
     uint32_t RM = 0;         // map width (max_spec)
-    uint32_t P = 0;          // maps composed per workgroup in the tree
+    uint32_t P = 0;          // maps composed per workgroup
     uint32_t G = 0;          // lockstep group
     uint32_t tile = 0;       // staged tile bytes per chunk (64 or 128)
     uint32_t merge = 1;      // 0: speculated runs are never merged
-    std::vector<uint64_t> level_maps; // number of maps after each compose level
+    uint32_t m = 0;          // learned: states walked per chunk
+    bool keep = false;       // keep every composition level (down-sweep)
+    std::vector<uint64_t> levels;  // maps after each composition level
+    struct Seg {
+        uint64_t end = 0, cnt = 0, cls = 0, runs = 0, lead = 0;
+    };
+    std::vector<Seg> seg;          // per kept level, or two ping-pong buffers
+    std::vector<uint64_t> entries; // boundary states: entry states per level
     uint64_t bytes = 0;
-    // offsets into the workspace
-    uint64_t off_cend = 0, off_ccnt = 0, off_ccls = 0;
-    uint64_t off_a_end = 0, off_a_cnt = 0, off_a_cls = 0, off_a_runs = 0;
-    uint64_t off_b_end = 0, off_b_cnt = 0, off_b_cls = 0, off_b_runs = 0;
-    uint64_t level_cap = 0;
+    uint64_t off_map = 0, off_mcls = 0, off_mlead = 0, off_dummy = 0;
+    uint64_t off_sel = 0, off_nsel = 0, off_redo = 0, off_done = 0, off_flags = 0, off_mlp = 0;
 };
 
 constexpr uint32_t kByteLdsRow = 260;  // row stride of the LDS byte table
 constexpr uint32_t kMaxChunk = 32768;  // chunk maps pack a count < 2^16 beside the end state
 
+constexpr int kCoverRounds = 3;         // coverage rounds before every incomplete chunk is walked again
+
 parem_status plan_plain(const DeviceDfa &d, uint64_t len, PlainPlan *p);
 parem_status launch_plain(const DeviceDfa &d, const PlainPlan &p, const uint8_t *d_text,
                           void *d_ws, hipStream_t stream, parem_result *d_out,
                           hipEvent_t ev_begin = nullptr, hipEvent_t ev_end = nullptr);
+parem_status plan_boundary(const DeviceDfa &d, uint64_t len, uint32_t L, PlainPlan *p);
+parem_status launch_boundary(const DeviceDfa &d, const PlainPlan &p, const uint8_t *d_text, uint32_t *d_states,
+                             void *d_ws, hipStream_t stream);
+parem_status plan_learned(const DeviceDfa &d, const Proposal &pr, uint64_t len, uint32_t m, PlainPlan *p);
+parem_status launch_learned(const DeviceDfa &d, const Proposal &pr, const PlainPlan &p, const uint8_t *d_text,
+                            void *d_ws, hipStream_t stream, parem_result *d_out, hipEvent_t ev_begin,
+                            hipEvent_t ev_end);
 
 }  // namespace parem
 
 struct parem_dfa {
     parem::DeviceDfa dev;
 };
+
+struct parem_proposal_s : parem::Proposal {};

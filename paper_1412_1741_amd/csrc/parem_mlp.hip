@@ -1,0 +1,713 @@
+// Learned speculation proposal: a small MLP that scores the DFA states at a
+// chunk boundary from the 32 bytes before it (not part of the paper; it
+// replaces the full speculated set R_c by its m best-scored members, and the
+// verify-and-re-run step keeps the match exact).
+//
+//   x  = concat(emb[w_0..w_31])          512   (a pad byte embeds as 0)
+//   h1 = gelu(W1 x + b1)                  256
+//   h2 = gelu(W2 h1 + b2)                 256
+//   z  = W3 h2 + b3                       one logit per state (S = Q rows)
+//   loss = masked softmax cross-entropy over the states of R_c
+//
+// Dense layers run on MFMA (v_mfma_f32_32x32x8_bf16): bf16 operands, fp32
+// accumulation, fp32 master weights updated by AdamW, a bf16 copy feeding the
+// next forward pass. GELU is the erf form.
+#include "parem_internal.h"
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+namespace parem {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    // round to nearest, ties to even (finite inputs)
+    uint32_t u = __float_as_uint(f);
+    u += ((u >> 16) & 1u) + 0x7fffu;
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ float gelu(float u) { return 0.5f * u * (1.0f + erff(u * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float u) {
+    return 0.5f * (1.0f + erff(u * 0.70710678118654752f)) + u * 0.39894228040143268f * expf(-0.5f * u * u);
+}
+
+// ---------------------------------------------------------------------------
+// GEMM: C[M,N] = sum_k A[M,K] B[K,N], bf16 operands, fp32 accumulation.
+// A is stored [M][K] (TA = false) or [K][M] (TA = true); B is stored [N][K]
+// (TB = true) or [K][N] (TB = false). 64 x 64 output tile per workgroup of
+// four waves (each a 32 x 32 MFMA block), K consumed 32 at a time through
+// LDS tiles kept k-contiguous for both operands.
+// ---------------------------------------------------------------------------
+
+enum Epi : int {
+    EPI_F32 = 0,        // out32[m*ldc+n] = acc
+    EPI_BIAS_GELU = 1,  // pre = acc + bias[n]; out32 = pre; out16 = bf16(gelu(pre))
+    EPI_BIAS_F32 = 2,   // out32 = acc + bias[n]
+    EPI_GELU_BWD = 3,   // d = acc * gelu'(aux32[m*ldc+n]); out32 = d; out16 = bf16(d)
+    EPI_BIAS_BF16 = 4   // out16 = bf16(gelu(acc + bias[n])) (inference, no pre-activation kept)
+};
+
+constexpr int kGemmT = 256;
+constexpr int kKT = 32;
+constexpr int kLdsK = kKT + 8;  // padded row (elements) against bank conflicts
+
+template <bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(kGemmT) void k_gemm(const uint16_t *__restrict__ A, int lda,
+                                                 const uint16_t *__restrict__ B, int ldb, int M, int N, int K,
+                                                 const float *__restrict__ bias, const float *__restrict__ aux,
+                                                 float *__restrict__ out32, uint16_t *__restrict__ out16,
+                                                 int ldc) {
+    __shared__ __align__(16) uint16_t As[64][kLdsK];
+    __shared__ __align__(16) uint16_t Bs[64][kLdsK];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    f32x16 acc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+
+    for (int k0 = 0; k0 < K; k0 += kKT) {
+        // each thread stages 8 elements of each operand
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = tid + u * kGemmT;  // 0..2047 over a 64 x 32 tile
+            int r, kk;
+            if (TA) { r = e & 63; kk = e >> 6; }   // consecutive threads walk m (contiguous when TA)
+            else { r = e >> 5; kk = e & 31; }      // consecutive threads walk k
+            const int gm = m0 + r, gk = k0 + kk;
+            uint16_t v = 0;
+            if (gm < M && gk < K) v = TA ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk];
+            As[r][kk] = v;
+            int rn, kn;
+            if (TB) { rn = e >> 5; kn = e & 31; }  // B stored [N][K]: walk k
+            else { rn = e & 63; kn = e >> 6; }     // B stored [K][N]: walk n
+            const int gn = n0 + rn, gk2 = k0 + kn;
+            uint16_t w = 0;
+            if (gn < N && gk2 < K) w = TB ? B[(size_t)gn * ldb + gk2] : B[(size_t)gk2 * ldb + gn];
+            Bs[rn][kn] = w;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kKT; ks += 8) {
+            // lane l holds A[m = l % 32][k = 4 (l / 32) + i] and B[k = 4 (l / 32) + i][n = l % 32]
+            const int kk = ks + 4 * (lane >> 5);
+            const bf16x4 a = *reinterpret_cast<const bf16x4 *>(&As[wm + (lane & 31)][kk]);
+            const bf16x4 b = *reinterpret_cast<const bf16x4 *>(&Bs[wn + (lane & 31)][kk]);
+            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // lane l, register r holds C[m = 8 (r / 4) + 4 (l / 32) + r % 4][n = l % 32]
+    const int n = n0 + wn + (lane & 31);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int m = m0 + wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (m >= M || n >= N) continue;
+        const size_t o = (size_t)m * ldc + n;
+        const float v = acc[r];
+        if constexpr (EPI == EPI_F32) {
+            out32[o] = v;
+        } else if constexpr (EPI == EPI_BIAS_GELU) {
+            const float pre = v + bias[n];
+            out32[o] = pre;
+            out16[o] = f2bf(gelu(pre));
+        } else if constexpr (EPI == EPI_BIAS_F32) {
+            out32[o] = v + bias[n];
+        } else if constexpr (EPI == EPI_GELU_BWD) {
+            const float d = v * gelu_grad(aux[o]);
+            out32[o] = d;
+            out16[o] = f2bf(d);
+        } else {
+            out16[o] = f2bf(gelu(v + bias[n]));
+        }
+    }
+}
+
+// Forward-layer GEMM, both operands K-contiguous: C[M,N] = A[M,K] B[N,K]^T.
+// 128 x 128 output tile per workgroup; each wave computes a 64 x 64 block as
+// 2 x 2 MFMA 32 x 32 tiles. K advances 32 per stage through double-buffered
+// LDS tiles filled with 16-byte loads (rows padded to 40 elements). K must be
+// a multiple of 32 and lda/ldb multiples of 8.
+constexpr int kNtRow = 40;
+
+template <int EPI>
+__global__ __launch_bounds__(kGemmT) void k_gemm_nt(const uint16_t *__restrict__ A, int lda,
+                                                    const uint16_t *__restrict__ B, int ldb, int M, int N, int K,
+                                                    const float *__restrict__ bias, const float *__restrict__ aux,
+                                                    float *__restrict__ out32, uint16_t *__restrict__ out16,
+                                                    int ldc) {
+    __shared__ __align__(16) uint16_t As[2][128][kNtRow];
+    __shared__ __align__(16) uint16_t Bs[2][128][kNtRow];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int m0 = blockIdx.y * 128, n0 = blockIdx.x * 128;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    // staging: thread loads rows r and r + 64 (r = tid / 4) at k offset 8 (tid % 4)
+    const int lr = tid >> 2, lk = (tid & 3) * 8;
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+    auto load = [&](int k0, uint4 (&ra)[2], uint4 (&rb)[2]) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int gm = m0 + lr + 64 * h, gn = n0 + lr + 64 * h;
+            ra[h] = gm < M ? *reinterpret_cast<const uint4 *>(A + (size_t)gm * lda + k0 + lk) : make_uint4(0, 0, 0, 0);
+            rb[h] = gn < N ? *reinterpret_cast<const uint4 *>(B + (size_t)gn * ldb + k0 + lk) : make_uint4(0, 0, 0, 0);
+        }
+    };
+    auto store = [&](int buf, const uint4 (&ra)[2], const uint4 (&rb)[2]) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            *reinterpret_cast<uint4 *>(&As[buf][lr + 64 * h][lk]) = ra[h];
+            *reinterpret_cast<uint4 *>(&Bs[buf][lr + 64 * h][lk]) = rb[h];
+        }
+    };
+    uint4 ra[2], rb[2];
+    load(0, ra, rb);
+    store(0, ra, rb);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = 0; k0 < K; k0 += kKT) {
+        const bool more = k0 + kKT < K;
+        if (more) load(k0 + kKT, ra, rb);
+#pragma unroll
+        for (int ks = 0; ks < kKT; ks += 8) {
+            const int kk = ks + 4 * (lane >> 5);
+            bf16x4 a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                a[i] = *reinterpret_cast<const bf16x4 *>(&As[buf][wm + 32 * i + (lane & 31)][kk]);
+                b[i] = *reinterpret_cast<const bf16x4 *>(&Bs[buf][wn + 32 * i + (lane & 31)][kk]);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        if (more) store(buf ^ 1, ra, rb);
+        __syncthreads();
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int n = n0 + wn + 32 * j + (lane & 31);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int m = m0 + wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                if (m >= M || n >= N) continue;
+                const size_t o = (size_t)m * ldc + n;
+                const float v = acc[i][j][r];
+                if constexpr (EPI == EPI_F32) {
+                    out32[o] = v;
+                } else if constexpr (EPI == EPI_BIAS_GELU) {
+                    const float pre = v + bias[n];
+                    out32[o] = pre;
+                    out16[o] = f2bf(gelu(pre));
+                } else if constexpr (EPI == EPI_BIAS_F32) {
+                    out32[o] = v + bias[n];
+                } else if constexpr (EPI == EPI_GELU_BWD) {
+                    const float d = v * gelu_grad(aux[o]);
+                    out32[o] = d;
+                    out16[o] = f2bf(d);
+                } else {
+                    out16[o] = f2bf(gelu(v + bias[n]));
+                }
+            }
+        }
+    }
+}
+
+template <bool TA, bool TB, int EPI>
+static void gemm(hipStream_t s, const uint16_t *A, int lda, const uint16_t *B, int ldb, int M, int N, int K,
+                 const float *bias, const float *aux, float *out32, uint16_t *out16, int ldc) {
+    if (!TA && TB && K % kKT == 0 && lda % 8 == 0 && ldb % 8 == 0 &&
+        (reinterpret_cast<uintptr_t>(A) & 15u) == 0 && (reinterpret_cast<uintptr_t>(B) & 15u) == 0) {
+        dim3 grid((N + 127) / 128, (M + 127) / 128);
+        hipLaunchKernelGGL((k_gemm_nt<EPI>), grid, dim3(kGemmT), 0, s, A, lda, B, ldb, M, N, K, bias, aux, out32,
+                           out16, ldc);
+        return;
+    }
+    dim3 grid((N + 63) / 64, (M + 63) / 64);
+    hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(kGemmT), 0, s, A, lda, B, ldb, M, N, K, bias, aux, out32,
+                       out16, ldc);
+}
+
+// ---------------------------------------------------------------------------
+// elementwise / reduction kernels
+// ---------------------------------------------------------------------------
+
+// window of the 32 bytes before each position (256 = pad before the text
+// start) and the class of the byte just before it
+__global__ void k_windows(const uint8_t *__restrict__ text, const uint64_t *__restrict__ pos, uint32_t B,
+                          const uint8_t *__restrict__ cls, uint32_t start_class, uint16_t *__restrict__ win,
+                          uint16_t *__restrict__ wcls) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B * kMlpWindow) return;
+    const uint32_t b = i / kMlpWindow, k = i % kMlpWindow;
+    const uint64_t p = pos[b];
+    const int64_t q = (int64_t)p - (int64_t)kMlpWindow + (int64_t)k;
+    win[i] = q < 0 ? (uint16_t)256 : (uint16_t)text[q];
+    if (k == 0) wcls[b] = p == 0 ? (uint16_t)start_class : (uint16_t)cls[text[p - 1]];
+}
+
+// windows of chunk boundaries c * L (c = 0..chunks-1)
+__global__ void k_windows_chunks(const uint8_t *__restrict__ text, uint64_t L, uint32_t chunks,
+                                 const uint8_t *__restrict__ cls, uint32_t start_class, uint16_t *__restrict__ win,
+                                 uint16_t *__restrict__ wcls) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= chunks * kMlpWindow) return;
+    const uint32_t b = i / kMlpWindow, k = i % kMlpWindow;
+    const uint64_t p = (uint64_t)b * L;
+    const int64_t q = (int64_t)p - (int64_t)kMlpWindow + (int64_t)k;
+    win[i] = q < 0 ? (uint16_t)256 : (uint16_t)text[q];
+    if (k == 0) wcls[b] = p == 0 ? (uint16_t)start_class : (uint16_t)cls[text[p - 1]];
+}
+
+__global__ void k_embed(const uint16_t *__restrict__ win, uint32_t B, const uint16_t *__restrict__ emb16,
+                        uint16_t *__restrict__ X) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;  // over B * 512
+    if (i >= B * kMlpIn) return;
+    const uint32_t b = i / kMlpIn, r = i % kMlpIn;
+    const uint32_t w = win[b * kMlpWindow + r / kMlpEmb];
+    X[i] = w >= 256 ? (uint16_t)0 : emb16[w * kMlpEmb + r % kMlpEmb];
+}
+
+// one wave per row: masked softmax cross-entropy; writes dZ = (p - onehot) / B
+// (fp32 and bf16) and accumulates the mean loss. A state is allowed when it
+// belongs to the speculated list of the row's class (inverse index hit).
+__global__ void k_softmax_ce(const float *__restrict__ Z, uint32_t B, uint32_t S, const uint32_t *__restrict__ label,
+                             const uint16_t *__restrict__ wcls, const uint16_t *__restrict__ inv, uint32_t Q1,
+                             float *__restrict__ dZ32, uint16_t *__restrict__ dZ16, float *__restrict__ loss) {
+    const uint32_t row = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63;
+    if (row >= B) return;
+    const float *z = Z + (size_t)row * S;
+    const uint16_t *iv = inv + (size_t)wcls[row] * Q1;
+    float mx = -INFINITY;
+    for (uint32_t s = lane; s < S; s += 64)
+        if (iv[s] != 0xffffu) mx = fmaxf(mx, z[s]);
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    float sum = 0.0f;
+    for (uint32_t s = lane; s < S; s += 64)
+        if (iv[s] != 0xffffu) sum += expf(z[s] - mx);
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+    const uint32_t lab = label[row];
+    const float invB = 1.0f / (float)B;
+    for (uint32_t s = lane; s < S; s += 64) {
+        float g = 0.0f;
+        if (iv[s] != 0xffffu) g = expf(z[s] - mx) / sum;
+        if (s == lab) g -= 1.0f;
+        g *= invB;
+        dZ32[(size_t)row * S + s] = g;
+        dZ16[(size_t)row * S + s] = f2bf(g);
+    }
+    if (lane == 0) atomicAdd(loss, (logf(sum) + mx - z[lab]) * invB);
+}
+
+// column sums of an fp32 [B][N] matrix into out[N]
+__global__ void k_colsum(const float *__restrict__ A, uint32_t B, uint32_t N, float *__restrict__ out) {
+    const uint32_t n = blockIdx.x;
+    float s = 0.0f;
+    for (uint32_t b = threadIdx.x; b < B; b += blockDim.x) s += A[(size_t)b * N + n];
+    __shared__ float red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (uint32_t w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[n] = red[0];
+}
+
+__global__ void k_zero(float *__restrict__ p, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+// embedding gradient: scatter-add the input gradient rows by byte value.
+// Each workgroup accumulates its rows into an LDS copy of the table, then
+// adds the non-zero entries to the global gradient (few, uncontended atomics).
+constexpr uint32_t kEmbRowsPerBlock = 64;
+
+__global__ __launch_bounds__(256) void k_embed_bwd(const uint16_t *__restrict__ win, uint32_t B,
+                                                   const float *__restrict__ dX, float *__restrict__ demb) {
+    __shared__ float acc[256 * kMlpEmb];
+    for (uint32_t i = threadIdx.x; i < 256 * kMlpEmb; i += blockDim.x) acc[i] = 0.0f;
+    __syncthreads();
+    const uint32_t r0 = blockIdx.x * kEmbRowsPerBlock;
+    const uint32_t r1 = min(B, r0 + kEmbRowsPerBlock);
+    for (uint32_t i = r0 * kMlpIn + threadIdx.x; i < r1 * kMlpIn; i += blockDim.x) {
+        const uint32_t b = i / kMlpIn, r = i % kMlpIn;
+        const uint32_t w = win[b * kMlpWindow + r / kMlpEmb];
+        if (w < 256) atomicAdd(&acc[w * kMlpEmb + r % kMlpEmb], dX[i]);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < 256 * kMlpEmb; i += blockDim.x)
+        if (acc[i] != 0.0f) atomicAdd(&demb[i], acc[i]);
+}
+
+__global__ void k_adamw(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
+                        float *__restrict__ v, uint16_t *__restrict__ w16, size_t n, float lr, float b1, float b2,
+                        float eps, float wd, float bc1, float bc2) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / bc1, vh = vi / bc2;
+    const float wi = w[i] - lr * (mh / (sqrtf(vh) + eps) + wd * w[i]);
+    w[i] = wi;
+    w16[i] = f2bf(wi);
+}
+
+__global__ void k_to_bf16(const float *__restrict__ w, uint16_t *__restrict__ w16, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) w16[i] = f2bf(w[i]);
+}
+
+// Top-m of each row's logits among the states of its class list (ties: the
+// lower state id). Writes the chosen states' positions in the class list,
+// ascending, and their number. The first chunk (start class) keeps {q0}.
+__global__ void k_topm(const float *__restrict__ Z, uint32_t rows, uint32_t S, const uint16_t *__restrict__ wcls,
+                       const uint32_t *__restrict__ loff, const uint32_t *__restrict__ llist, uint32_t m,
+                       uint32_t RM, uint16_t *__restrict__ sel, uint8_t *__restrict__ nsel) {
+    const uint32_t row = blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= rows) return;
+    const uint32_t c = wcls[row];
+    const uint32_t lo = loff[c], sz = loff[c + 1] - lo;
+    uint16_t *out = sel + (size_t)row * RM;
+    if (sz <= m) {
+        for (uint32_t j = 0; j < sz; ++j) out[j] = (uint16_t)j;
+        nsel[row] = (uint8_t)sz;
+        return;
+    }
+    // m passes; pass t takes the best item strictly after pass t-1's pick in
+    // the order (logit descending, position ascending). Lists are sorted by
+    // state id, so position order is state-id order.
+    const float *z = Z + (size_t)row * S;
+    uint32_t picked[16];
+    float last_v = INFINITY;
+    uint32_t last_j = 0xffffffffu;
+    for (uint32_t t = 0; t < m; ++t) {
+        float best = -INFINITY;
+        uint32_t bj = 0xffffffffu;
+        for (uint32_t j = 0; j < sz; ++j) {
+            const uint32_t s = llist[lo + j];
+            const float v = s < S ? z[s] : -INFINITY;
+            const bool after = t == 0 || v < last_v || (v == last_v && j > last_j);
+            if (!after) continue;
+            if (bj == 0xffffffffu || v > best) {  // strict: the lower position wins ties
+                best = v;
+                bj = j;
+            }
+        }
+        picked[t] = bj;
+        last_v = best;
+        last_j = bj;
+    }
+    for (uint32_t a = 1; a < m; ++a)
+        for (uint32_t b = a; b > 0 && picked[b - 1] > picked[b]; --b) {
+            const uint32_t x = picked[b];
+            picked[b] = picked[b - 1];
+            picked[b - 1] = x;
+        }
+    for (uint32_t t = 0; t < m; ++t) out[t] = (uint16_t)picked[t];
+    nsel[row] = (uint8_t)m;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+static size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+void proposal_layout(Proposal &p) {
+    size_t k = 0;
+    p.o_emb = k; k += 256 * kMlpEmb;
+    p.o_W1 = k; k += (size_t)kMlpHid * kMlpIn;
+    p.o_b1 = k; k += kMlpHid;
+    p.o_W2 = k; k += (size_t)kMlpHid * kMlpHid;
+    p.o_b2 = k; k += kMlpHid;
+    p.o_W3 = k; k += (size_t)p.S * kMlpHid;
+    p.o_b3 = k; k += p.S;
+    p.nparams = k;
+}
+
+static parem_status ensure_train(Proposal &p, uint32_t B) {
+    if (p.cap_batch >= B) return PAREM_OK;
+    hipFree(p.t_buf);
+    p.t_buf = nullptr;
+    const size_t S = p.S;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = round_up(off + bytes, 256); return o; };
+    p.t_pos = take((size_t)B * 8);
+    p.t_lab = take((size_t)B * 4);
+    p.t_win = take((size_t)B * kMlpWindow * 2);
+    p.t_cls = take((size_t)B * 2);
+    p.t_X = take((size_t)B * kMlpIn * 2);
+    p.t_pre1 = take((size_t)B * kMlpHid * 4);
+    p.t_H1 = take((size_t)B * kMlpHid * 2);
+    p.t_pre2 = take((size_t)B * kMlpHid * 4);
+    p.t_H2 = take((size_t)B * kMlpHid * 2);
+    p.t_Z = take((size_t)B * S * 4);
+    p.t_dZ32 = take((size_t)B * S * 4);
+    p.t_dZ16 = take((size_t)B * S * 2);
+    p.t_dA2_32 = take((size_t)B * kMlpHid * 4);
+    p.t_dA2_16 = take((size_t)B * kMlpHid * 2);
+    p.t_dA1_32 = take((size_t)B * kMlpHid * 4);
+    p.t_dA1_16 = take((size_t)B * kMlpHid * 2);
+    p.t_dX = take((size_t)B * kMlpIn * 4);
+    p.t_loss = take(256);
+    if (hipMalloc(&p.t_buf, off) != hipSuccess) {
+        p.t_buf = nullptr;
+        p.cap_batch = 0;
+        return PAREM_ENOMEM;
+    }
+    p.cap_batch = B;
+    return PAREM_OK;
+}
+
+template <typename T>
+static T *at(void *base, size_t off) {
+    return reinterpret_cast<T *>(reinterpret_cast<uint8_t *>(base) + off);
+}
+
+// forward over B rows whose windows/classes are already in place; fills Z
+static void forward_rows(const Proposal &p, hipStream_t s, const uint16_t *win, uint32_t B, uint16_t *X,
+                         float *pre1, uint16_t *H1, float *pre2, uint16_t *H2, float *Z) {
+    const uint16_t *w16 = p.d_params16;
+    const float *w32 = p.d_params;
+    const uint32_t nb = (B * kMlpIn + 255) / 256;
+    hipLaunchKernelGGL(k_embed, dim3(nb), dim3(256), 0, s, win, B, w16 + p.o_emb, X);
+    if (pre1) {
+        gemm<false, true, EPI_BIAS_GELU>(s, X, kMlpIn, w16 + p.o_W1, kMlpIn, B, kMlpHid, kMlpIn, w32 + p.o_b1,
+                                         nullptr, pre1, H1, kMlpHid);
+        gemm<false, true, EPI_BIAS_GELU>(s, H1, kMlpHid, w16 + p.o_W2, kMlpHid, B, kMlpHid, kMlpHid, w32 + p.o_b2,
+                                         nullptr, pre2, H2, kMlpHid);
+    } else {
+        gemm<false, true, EPI_BIAS_BF16>(s, X, kMlpIn, w16 + p.o_W1, kMlpIn, B, kMlpHid, kMlpIn, w32 + p.o_b1,
+                                         nullptr, nullptr, H1, kMlpHid);
+        gemm<false, true, EPI_BIAS_BF16>(s, H1, kMlpHid, w16 + p.o_W2, kMlpHid, B, kMlpHid, kMlpHid,
+                                         w32 + p.o_b2, nullptr, nullptr, H2, kMlpHid);
+    }
+    gemm<false, true, EPI_BIAS_F32>(s, H2, kMlpHid, w16 + p.o_W3, kMlpHid, B, (int)p.S, kMlpHid, w32 + p.o_b3,
+                                    nullptr, Z, nullptr, (int)p.S);
+}
+
+parem_status proposal_train_step(Proposal &p, const uint8_t *d_text, uint64_t len, const uint64_t *d_pos,
+                                 const uint32_t *d_labels, uint32_t B, float lr, float wd, hipStream_t s,
+                                 float *d_loss_out) {
+    if (B == 0) return PAREM_EINVAL;
+    parem_status st = ensure_train(p, B);
+    if (st != PAREM_OK) return st;
+    const DeviceDfa &d = *p.dfa;
+    void *T = p.t_buf;
+    uint16_t *win = at<uint16_t>(T, p.t_win), *wcls = at<uint16_t>(T, p.t_cls);
+    const uint32_t S = p.S;
+    const uint32_t nw = (B * kMlpWindow + 255) / 256;
+    hipLaunchKernelGGL(k_windows, dim3(nw), dim3(256), 0, s, d_text, d_pos, B, d.d_cls, d.A + 1, win, wcls);
+    float *loss = d_loss_out ? d_loss_out : at<float>(T, p.t_loss);
+    hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, loss, (size_t)1);
+    uint16_t *X = at<uint16_t>(T, p.t_X), *H1 = at<uint16_t>(T, p.t_H1), *H2 = at<uint16_t>(T, p.t_H2);
+    float *pre1 = at<float>(T, p.t_pre1), *pre2 = at<float>(T, p.t_pre2), *Z = at<float>(T, p.t_Z);
+    forward_rows(p, s, win, B, X, pre1, H1, pre2, H2, Z);
+    float *dZ32 = at<float>(T, p.t_dZ32);
+    uint16_t *dZ16 = at<uint16_t>(T, p.t_dZ16);
+    hipLaunchKernelGGL(k_softmax_ce, dim3((B + 3) / 4), dim3(256), 0, s, Z, B, S, d_labels, wcls, d.d_inv, d.Q + 1,
+                       dZ32, dZ16, loss);
+    // backward
+    float *g = p.d_grad;
+    const uint16_t *w16 = p.d_params16;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)((256 * kMlpEmb + 255) / 256)), dim3(256), 0, s, g + p.o_emb,
+                       (size_t)256 * kMlpEmb);
+    // head: dW3 = dZ^T H2, db3 = colsum dZ, dA2 = (dZ W3) * gelu'(pre2)
+    gemm<true, false, EPI_F32>(s, dZ16, (int)S, H2, kMlpHid, (int)S, kMlpHid, (int)B, nullptr, nullptr, g + p.o_W3,
+                               nullptr, kMlpHid);
+    hipLaunchKernelGGL(k_colsum, dim3(S), dim3(256), 0, s, dZ32, B, S, g + p.o_b3);
+    float *dA2_32 = at<float>(T, p.t_dA2_32), *dA1_32 = at<float>(T, p.t_dA1_32);
+    uint16_t *dA2_16 = at<uint16_t>(T, p.t_dA2_16), *dA1_16 = at<uint16_t>(T, p.t_dA1_16);
+    gemm<false, false, EPI_GELU_BWD>(s, dZ16, (int)S, w16 + p.o_W3, kMlpHid, (int)B, kMlpHid, (int)S, nullptr, pre2,
+                                     dA2_32, dA2_16, kMlpHid);
+    // layer 2
+    gemm<true, false, EPI_F32>(s, dA2_16, kMlpHid, H1, kMlpHid, kMlpHid, kMlpHid, (int)B, nullptr, nullptr,
+                               g + p.o_W2, nullptr, kMlpHid);
+    hipLaunchKernelGGL(k_colsum, dim3(kMlpHid), dim3(256), 0, s, dA2_32, B, kMlpHid, g + p.o_b2);
+    gemm<false, false, EPI_GELU_BWD>(s, dA2_16, kMlpHid, w16 + p.o_W2, kMlpHid, (int)B, kMlpHid, kMlpHid, nullptr,
+                                     pre1, dA1_32, dA1_16, kMlpHid);
+    // layer 1
+    gemm<true, false, EPI_F32>(s, dA1_16, kMlpHid, X, kMlpIn, kMlpHid, kMlpIn, (int)B, nullptr, nullptr,
+                               g + p.o_W1, nullptr, kMlpIn);
+    hipLaunchKernelGGL(k_colsum, dim3(kMlpHid), dim3(256), 0, s, dA1_32, B, kMlpHid, g + p.o_b1);
+    float *dX = at<float>(T, p.t_dX);
+    gemm<false, false, EPI_F32>(s, dA1_16, kMlpHid, w16 + p.o_W1, kMlpIn, (int)B, kMlpIn, kMlpHid, nullptr, nullptr,
+                                dX, nullptr, kMlpIn);
+    hipLaunchKernelGGL(k_embed_bwd, dim3((B + kEmbRowsPerBlock - 1) / kEmbRowsPerBlock), dim3(256), 0, s, win, B, dX,
+                       g + p.o_emb);
+    if (lr > 0.0f || wd > 0.0f) {
+        p.step += 1;
+        const float b1 = 0.9f, b2 = 0.999f;
+        const float bc1 = 1.0f - powf(b1, (float)p.step), bc2 = 1.0f - powf(b2, (float)p.step);
+        hipLaunchKernelGGL(k_adamw, dim3((unsigned)((p.nparams + 255) / 256)), dim3(256), 0, s, p.d_params, g, p.d_m,
+                           p.d_v, p.d_params16, p.nparams, lr, b1, b2, 1e-8f, wd, bc1, bc2);
+    }
+    return hipGetLastError() == hipSuccess ? PAREM_OK : PAREM_EDEVICE;
+}
+
+size_t proposal_infer_bytes(const Proposal &p, uint64_t rows) {
+    size_t b = 0;
+    b += round_up(rows * kMlpWindow * 2, 256);
+    b += round_up(rows * 2, 256);
+    b += round_up(rows * kMlpIn * 2, 256);
+    b += 2 * round_up(rows * kMlpHid * 2, 256);
+    b += round_up(rows * p.S * 4, 256);
+    return b;
+}
+
+// logits of the chunk boundaries c * L and the top-m selection per chunk
+parem_status proposal_select(const Proposal &p, const uint8_t *d_text, uint64_t L, uint32_t chunks, uint32_t m,
+                             uint32_t RM, void *scratch, hipStream_t s, uint16_t *sel, uint8_t *nsel) {
+    const DeviceDfa &d = *p.dfa;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = round_up(off + bytes, 256); return o; };
+    uint16_t *win = at<uint16_t>(scratch, take((size_t)chunks * kMlpWindow * 2));
+    uint16_t *wcls = at<uint16_t>(scratch, take((size_t)chunks * 2));
+    uint16_t *X = at<uint16_t>(scratch, take((size_t)chunks * kMlpIn * 2));
+    uint16_t *H1 = at<uint16_t>(scratch, take((size_t)chunks * kMlpHid * 2));
+    uint16_t *H2 = at<uint16_t>(scratch, take((size_t)chunks * kMlpHid * 2));
+    float *Z = at<float>(scratch, take((size_t)chunks * p.S * 4));
+    hipLaunchKernelGGL(k_windows_chunks, dim3((chunks * kMlpWindow + 255) / 256), dim3(256), 0, s, d_text, L, chunks,
+                       d.d_cls, d.A + 1, win, wcls);
+    forward_rows(p, s, win, chunks, X, nullptr, H1, nullptr, H2, Z);
+    hipLaunchKernelGGL(k_topm, dim3((chunks + 255) / 256), dim3(256), 0, s, Z, chunks, p.S, wcls, d.d_loff,
+                       d.d_llist, m, RM, sel, nsel);
+    return hipGetLastError() == hipSuccess ? PAREM_OK : PAREM_EDEVICE;
+}
+
+parem_status proposal_logits(const Proposal &p, const uint8_t *d_text, const uint64_t *d_pos, uint32_t B,
+                             float *d_logits, hipStream_t s) {
+    Proposal &q = const_cast<Proposal &>(p);
+    parem_status st = ensure_train(q, B);
+    if (st != PAREM_OK) return st;
+    const DeviceDfa &d = *p.dfa;
+    void *T = q.t_buf;
+    uint16_t *win = at<uint16_t>(T, q.t_win), *wcls = at<uint16_t>(T, q.t_cls);
+    hipLaunchKernelGGL(k_windows, dim3((B * kMlpWindow + 255) / 256), dim3(256), 0, s, d_text, d_pos, B, d.d_cls,
+                       d.A + 1, win, wcls);
+    forward_rows(p, s, win, B, at<uint16_t>(T, q.t_X), at<float>(T, q.t_pre1), at<uint16_t>(T, q.t_H1),
+                 at<float>(T, q.t_pre2), at<uint16_t>(T, q.t_H2), d_logits);
+    return hipGetLastError() == hipSuccess ? PAREM_OK : PAREM_EDEVICE;
+}
+
+}  // namespace parem
+
+using parem::Proposal;
+
+extern "C" {
+
+parem_status parem_proposal_create(parem_handle h, const float *params, uint64_t nparams, parem_proposal *out) {
+    if (!h || !out || !params) return PAREM_EINVAL;
+    *out = nullptr;
+    parem_proposal_s *p = new (std::nothrow) parem_proposal_s();
+    if (!p) return PAREM_ENOMEM;
+    p->dfa = &h->dev;
+    p->S = h->dev.Q;
+    parem::proposal_layout(*p);
+    if (nparams != p->nparams) {
+        delete p;
+        return PAREM_EINVAL;
+    }
+    if (!h->dev.d_inv) {
+        delete p;
+        return PAREM_EUNSUPPORTED;
+    }
+    const size_t n = p->nparams;
+    bool ok = hipMalloc(&p->d_params, n * 4) == hipSuccess && hipMalloc(&p->d_params16, n * 2) == hipSuccess &&
+              hipMalloc(&p->d_grad, n * 4) == hipSuccess && hipMalloc(&p->d_m, n * 4) == hipSuccess &&
+              hipMalloc(&p->d_v, n * 4) == hipSuccess;
+    ok = ok && hipMemcpy(p->d_params, params, n * 4, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemset(p->d_m, 0, n * 4) == hipSuccess && hipMemset(p->d_v, 0, n * 4) == hipSuccess &&
+         hipMemset(p->d_grad, 0, n * 4) == hipSuccess;
+    if (ok) {
+        hipLaunchKernelGGL(parem::k_to_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, 0, p->d_params,
+                           p->d_params16, n);
+        ok = hipDeviceSynchronize() == hipSuccess;
+    }
+    if (!ok) {
+        parem_proposal_free(p);
+        return PAREM_ENOMEM;
+    }
+    *out = p;
+    return PAREM_OK;
+}
+
+void parem_proposal_free(parem_proposal p) {
+    if (!p) return;
+    hipFree(p->d_params);
+    hipFree(p->d_params16);
+    hipFree(p->d_grad);
+    hipFree(p->d_m);
+    hipFree(p->d_v);
+    hipFree(p->t_buf);
+    delete p;
+}
+
+parem_status parem_proposal_params(parem_proposal p, float *params_out, float *grad_out, uint64_t nparams) {
+    if (!p || nparams != p->nparams) return PAREM_EINVAL;
+    if (hipDeviceSynchronize() != hipSuccess) return PAREM_EDEVICE;
+    if (params_out && hipMemcpy(params_out, p->d_params, nparams * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return PAREM_EDEVICE;
+    if (grad_out && hipMemcpy(grad_out, p->d_grad, nparams * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return PAREM_EDEVICE;
+    return PAREM_OK;
+}
+
+parem_status parem_proposal_train_step(parem_proposal p, const uint8_t *d_text, uint64_t len,
+                                       const uint64_t *d_positions, const uint32_t *d_labels, uint32_t batch,
+                                       float lr, float weight_decay, void *stream, float *d_loss) {
+    if (!p || !d_text || !d_positions || !d_labels || batch == 0) return PAREM_EINVAL;
+    return parem::proposal_train_step(*p, d_text, len, d_positions, d_labels, batch, lr, weight_decay,
+                                      reinterpret_cast<hipStream_t>(stream), d_loss);
+}
+
+parem_status parem_proposal_select_size(parem_proposal p, uint64_t len, uint32_t chunk_len, uint64_t *bytes) {
+    if (!p || !bytes || chunk_len == 0) return PAREM_EINVAL;
+    const uint64_t chunks = (len + chunk_len - 1) / chunk_len;
+    *bytes = parem::proposal_infer_bytes(*p, chunks ? chunks : 1);
+    return PAREM_OK;
+}
+
+parem_status parem_proposal_select(parem_proposal p, const uint8_t *d_text, uint64_t len, uint32_t chunk_len,
+                                   uint32_t m, uint16_t *d_sel, uint8_t *d_nsel, void *d_workspace,
+                                   uint64_t workspace_bytes, void *stream) {
+    if (!p || !d_text || !d_sel || !d_nsel || chunk_len == 0 || m == 0 || m > 16) return PAREM_EINVAL;
+    const uint64_t chunks = (len + chunk_len - 1) / chunk_len;
+    if (chunks == 0 || chunks > 0xffffffffull) return PAREM_EINVAL;
+    if (!d_workspace || workspace_bytes < parem::proposal_infer_bytes(*p, chunks)) return PAREM_EINVAL;
+    return parem::proposal_select(*p, d_text, chunk_len, (uint32_t)chunks, m, m, d_workspace,
+                                  reinterpret_cast<hipStream_t>(stream), d_sel, d_nsel);
+}
+
+parem_status parem_proposal_logits(parem_proposal p, const uint8_t *d_text, const uint64_t *d_positions,
+                                   uint32_t batch, float *d_logits, void *stream) {
+    if (!p || !d_text || !d_positions || !d_logits || batch == 0) return PAREM_EINVAL;
+    return parem::proposal_logits(*p, d_text, d_positions, batch, d_logits, reinterpret_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

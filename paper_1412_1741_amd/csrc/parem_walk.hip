@@ -221,16 +221,24 @@ __device__ __forceinline__ uint4 load16(const uint8_t *p) {
     }
 }
 
+// Walk index idx (0 = leader) starts in the state at list position
+// pos(idx): idx itself for the whole speculated set, sel[idx] for a learned
+// selection.
+struct Positions {
+    const uint16_t *sel;  // null: identity
+    __device__ __forceinline__ uint32_t operator()(uint32_t idx) const { return sel ? (uint32_t)sel[idx] : idx; }
+};
+
 template <int G, typename ST>
 __device__ __forceinline__ void walks_init(const ST &st, Walks<G> &w, const uint32_t *__restrict__ list,
-                                           uint32_t nlist, uint32_t first) {
-    const uint32_t lead = st.init(list[0]);
+                                           const Positions &pos, uint32_t nwalk, uint32_t first) {
+    const uint32_t lead = st.init(list[pos(0)]);
     w.pending = 0;
 #pragma unroll
     for (int j = 0; j < G; ++j) {
         const uint32_t idx = first + (uint32_t)j - 1u;
-        const bool real = j > 0 && idx < nlist;
-        w.R[j] = real ? st.init(list[idx]) : lead;
+        const bool real = j > 0 && idx < nwalk;
+        w.R[j] = real ? st.init(list[pos(idx)]) : lead;
         w.S[j] = 0;
         w.c[j] = 0;
         w.off[j] = 0;
@@ -328,6 +336,29 @@ template <int G, typename ST, bool ALIGNED>
 __device__ __forceinline__ void walk_direct(const ST &st, Walks<G> &w, const uint8_t *__restrict__ p, uint32_t pos,
                                             uint32_t len, bool full, uint32_t &bad) {
     const uint32_t len16 = len & ~15u;
+    if constexpr (ALIGNED) {
+        // 64-byte blocks with the next block loaded before the current one is
+        // walked (a full pass reads a whole chunk through this path when it
+        // is walked again alone)
+        const uint32_t len64 = pos + ((len16 - pos) & ~63u);
+        if (pos < len64 && (full || w.wave_pending)) {
+            uint4 n0 = load16<true>(p + pos), n1 = load16<true>(p + pos + 16), n2 = load16<true>(p + pos + 32),
+                  n3 = load16<true>(p + pos + 48);
+            for (; pos < len64; pos += 64) {
+                if (!full && !w.wave_pending) return;
+                const uint4 c0 = n0, c1 = n1, c2 = n2, c3 = n3;
+                const uint32_t nx = min(pos + 64, len64 - 64);  // unconditional: reloads the last block at the end
+                n0 = load16<true>(p + nx);
+                n1 = load16<true>(p + nx + 16);
+                n2 = load16<true>(p + nx + 32);
+                n3 = load16<true>(p + nx + 48);
+                piece<G>(st, w, c0, bad);
+                piece<G>(st, w, c1, bad);
+                piece<G>(st, w, c2, bad);
+                piece<G>(st, w, c3, bad);
+            }
+        }
+    }
     for (; pos < len16; pos += 16) {
         if (!full && !w.wave_pending) return;
         piece<G>(st, w, load16<ALIGNED>(p + pos), bad);
@@ -349,19 +380,19 @@ __device__ __forceinline__ void walk_direct(const ST &st, Walks<G> &w, const uin
 
 // returns true when some walk of the pass ends in another state than the leader
 template <int G, typename ST>
-__device__ __forceinline__ bool store_pass(const ST &st, const Walks<G> &w, uint32_t first, uint32_t nlist,
-                                           bool full, uint32_t &lead_end, uint32_t &lead_cnt,
+__device__ __forceinline__ bool store_pass(const ST &st, const Walks<G> &w, const Positions &pos, uint32_t first,
+                                           uint32_t nwalk, bool full, uint32_t &lead_end, uint32_t &lead_cnt,
                                            uint32_t *__restrict__ out, uint64_t stride) {
     bool differs = false;
     if (full) {
         lead_end = st.id(w.R[0]);
         lead_cnt = w.c[0];
-        out[0] = lead_end | (lead_cnt << 16);
+        out[(uint64_t)pos(0) * stride] = lead_end | (lead_cnt << 16);
     }
 #pragma unroll
     for (int j = 1; j < G; ++j) {
         const uint32_t idx = first + (uint32_t)j - 1u;
-        if (idx < nlist) {
+        if (idx < nwalk) {
             uint32_t e, cn;
             if ((w.pending >> j) & 1u) {
                 e = st.id(w.R[j]);
@@ -371,31 +402,63 @@ __device__ __forceinline__ bool store_pass(const ST &st, const Walks<G> &w, uint
                 e = lead_end;
                 cn = (uint32_t)((int32_t)lead_cnt + w.off[j]);
             }
-            out[(uint64_t)idx * stride] = e | (cn << 16);
+            out[(uint64_t)pos(idx) * stride] = e | (cn << 16);
         }
     }
     return differs;
 }
 
-template <int G, typename ST, bool ALIGNED, uint32_t TILE>
-__device__ __forceinline__ void walk_chunk(const ST &st, const uint8_t *__restrict__ text, uint64_t n, uint32_t L,
-                                           uint64_t nchunks, const uint8_t *__restrict__ g_cls,
-                                           const uint32_t *__restrict__ g_loff, const uint32_t *__restrict__ g_llist,
-                                           uint32_t start_class, uint32_t sent, bool merge, uint8_t *stage,
-                                           uint32_t *__restrict__ map, uint16_t *__restrict__ map_cls) {
+// Arguments of a walk launch.
+struct WalkArgs {
+    const uint8_t *text;
+    uint64_t n;
+    uint32_t L;
+    uint64_t nchunks;
+    const uint8_t *cls;
+    const uint32_t *loff;
+    const uint32_t *llist;
+    uint32_t start_class;
+    uint32_t sent;
+    uint32_t merge;
+    uint32_t *map;        // [RM][nchunks] packed end | count << 16 (end 0xffff: not walked)
+    uint16_t *map_cls;    // [nchunks] class, bit 15 = ends differ
+    uint16_t *map_lead;   // [nchunks] end state of the leader walk
+    const uint16_t *sel;  // learned selection: positions [nchunks][sel_stride] (null: whole set)
+    const uint8_t *nsel;  // [nchunks] number of selected positions
+    uint32_t sel_stride;
+    const uint8_t *redo;  // re-walk mode: only chunks with redo[c] != 0, from the whole set
+};
+
+enum WalkMode : int { WALK_ALL = 0, WALK_SELECTED = 1, WALK_REDO = 2 };
+
+template <int G, typename ST, bool ALIGNED, uint32_t TILE, int MODE>
+__device__ __forceinline__ void walk_chunk(const ST &st, const WalkArgs &a, uint8_t *stage) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t c = (uint64_t)blockIdx.x * kWalkThreads + threadIdx.x;
-    const bool active = c < nchunks;
-    const uint64_t b = c * (uint64_t)L;
-    const uint32_t len = active ? (uint32_t)min((uint64_t)L, n - b) : 0u;
-    const uint32_t cls = !active ? start_class : (c == 0 ? start_class : (uint32_t)g_cls[text[b - 1]]);
-    const uint32_t lo = g_loff[cls];
-    const uint32_t nlist = g_loff[cls + 1] - lo;
-    const uint32_t *list = g_llist + lo;
+    bool active = c < a.nchunks;
+    if constexpr (MODE == WALK_REDO) {
+        if (!active || a.redo[c] == 0) return;  // no wave-wide staging in this mode
+    }
+    const uint64_t b = c * (uint64_t)a.L;
+    const uint32_t len = active ? (uint32_t)min((uint64_t)a.L, a.n - b) : 0u;
+    const uint32_t cls = (!active || c == 0) ? a.start_class : (uint32_t)a.cls[a.text[b - 1]];
+    const uint32_t lo = a.loff[cls];
+    const uint32_t nlist = a.loff[cls + 1] - lo;
+    const uint32_t *list = a.llist + lo;
+    Positions pos{nullptr};
+    uint32_t nwalk = nlist;
+    if constexpr (MODE == WALK_SELECTED) {
+        if (active) {
+            pos.sel = a.sel + c * a.sel_stride;
+            nwalk = a.nsel[c];
+        } else {
+            nwalk = 1;
+        }
+    }
 
     // tiles every chunk of this wave holds in full
     uint32_t ntiles = 0;
-    if constexpr (ALIGNED) {
+    if constexpr (ALIGNED && MODE != WALK_REDO) {
         uint32_t m = len;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) m = min(m, (uint32_t)__shfl_xor((int)m, o, 64));
@@ -404,31 +467,37 @@ __device__ __forceinline__ void walk_chunk(const ST &st, const uint8_t *__restri
 
     Walks<G> w;
     uint32_t bad = 0, lead_end = 0, lead_cnt = 0;
-    walks_init<G>(st, w, list, nlist, 1);
-    w.merge = merge;
+    walks_init<G>(st, w, list, pos, nwalk, 1);
+    w.merge = a.merge != 0;
     if (ntiles) {
         const uint64_t wave_first = c - lane;
-        walk_staged<G, ST, TILE>(st, w, text + wave_first * L, L, ntiles, lane,
+        walk_staged<G, ST, TILE>(st, w, a.text + wave_first * a.L, a.L, ntiles, lane,
                                  stage + (threadIdx.x >> 6) * Stage<TILE>::kWave, bad);
     }
     if (!active) return;
-    const uint8_t *p = text + b;
+    const uint8_t *p = a.text + b;
+    uint32_t *out = a.map + c;
+    if constexpr (MODE == WALK_SELECTED) {
+        // entries not walked are marked absent
+        for (uint32_t j = 0; j < nlist; ++j) out[(uint64_t)j * a.nchunks] = kAbsent16;
+    }
     walk_direct<G, ST, ALIGNED>(st, w, p, ntiles * TILE, len, true, bad);
-    uint32_t *out = map + c;
-    bool nonuni = store_pass<G>(st, w, 1, nlist, true, lead_end, lead_cnt, out, nchunks);
-    for (uint32_t first = G; first < nlist; first += G - 1) {
-        walks_init<G>(st, w, list, nlist, first);
-        w.merge = merge;
+    bool nonuni = store_pass<G>(st, w, pos, 1, nwalk, true, lead_end, lead_cnt, out, a.nchunks);
+    for (uint32_t first = G; first < nwalk; first += G - 1) {
+        walks_init<G>(st, w, list, pos, nwalk, first);
+        w.merge = a.merge != 0;
         walk_direct<G, ST, ALIGNED>(st, w, p, 0, len, false, bad);
-        nonuni |= store_pass<G>(st, w, first, nlist, false, lead_end, lead_cnt, out, nchunks);
+        nonuni |= store_pass<G>(st, w, pos, first, nwalk, false, lead_end, lead_cnt, out, a.nchunks);
     }
     if (bad) {
-        // a byte outside the alphabet: every run of this chunk ends in the sentinel
-        for (uint32_t j = 0; j < nlist; ++j) out[(uint64_t)j * nchunks] = sent;
-        nonuni = 0;
+        // a byte outside the alphabet: every walk of this chunk ends in the sentinel
+        for (uint32_t j = 0; j < nwalk; ++j) out[(uint64_t)pos(j) * a.nchunks] = a.sent;
+        nonuni = false;
+        lead_end = a.sent;
     }
-    // bit 15: the map is not uniform (its runs end in more than one state)
-    map_cls[c] = (uint16_t)(cls | (nonuni ? 0x8000u : 0u));
+    // bit 15: the walks end in more than one state
+    a.map_cls[c] = (uint16_t)(cls | (nonuni ? 0x8000u : 0u));
+    a.map_lead[c] = (uint16_t)lead_end;
 }
 
 // copy the table into LDS with four 16-byte loads in flight per thread
@@ -449,41 +518,28 @@ __device__ __forceinline__ void stage_table(uint4 *dst, const uint4 *__restrict_
 }
 
 // at least 4 waves per SIMD (at most 128 VGPRs) for groups up to 8 walks
-template <typename E, uint32_t ROW, int G, bool LDS_TABLE, bool ALIGNED, uint32_t TILE>
-__global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_walk_byte(
-    const uint8_t *__restrict__ text, uint64_t n, uint32_t L, uint64_t nchunks, const E *__restrict__ g_table,
-    uint32_t table_bytes, const uint8_t *__restrict__ g_cls, const uint32_t *__restrict__ g_loff,
-    const uint32_t *__restrict__ g_llist, uint32_t start_class, uint32_t sent, uint32_t merge,
-    uint32_t *__restrict__ map, uint16_t *__restrict__ map_cls) {
+template <typename E, uint32_t ROW, int G, bool LDS_TABLE, bool ALIGNED, uint32_t TILE, int MODE>
+__global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_walk_byte(WalkArgs a, const E *__restrict__ g_table,
+                                                                              uint32_t table_bytes) {
     extern __shared__ __align__(16) uint8_t smem[];
     ByteStep<E, ROW> st{g_table};
     uint32_t tb = 0;
     if constexpr (LDS_TABLE) {
-        uint4 *dst = reinterpret_cast<uint4 *>(smem);
-        const uint4 *src = reinterpret_cast<const uint4 *>(g_table);
-        stage_table(dst, src, table_bytes / 16u);
+        stage_table(reinterpret_cast<uint4 *>(smem), reinterpret_cast<const uint4 *>(g_table), table_bytes / 16u);
         st.T = reinterpret_cast<const E *>(smem);
         tb = table_bytes;
     }
-    walk_chunk<G, ByteStep<E, ROW>, ALIGNED, TILE>(st, text, n, L, nchunks, g_cls, g_loff, g_llist, start_class,
-                                                   sent, merge != 0, smem + tb, map, map_cls);
+    walk_chunk<G, ByteStep<E, ROW>, ALIGNED, TILE, MODE>(st, a, smem + tb);
 }
 
-template <int G, int B, bool ALIGNED, uint32_t TILE>
-__global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_walk_kgram(
-    const uint8_t *__restrict__ text, uint64_t n, uint32_t L, uint64_t nchunks, const uint8_t *__restrict__ g_table,
-    uint32_t table_bytes, KgParams kp, const uint8_t *__restrict__ g_cls, const uint32_t *__restrict__ g_loff,
-    const uint32_t *__restrict__ g_llist, uint32_t start_class, uint32_t sent, uint32_t merge,
-    uint32_t *__restrict__ map, uint16_t *__restrict__ map_cls) {
+template <int G, int B, bool ALIGNED, uint32_t TILE, int MODE>
+__global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_walk_kgram(WalkArgs a,
+                                                                               const uint8_t *__restrict__ g_table,
+                                                                               uint32_t table_bytes, KgParams kp) {
     extern __shared__ __align__(16) uint8_t smem[];
-    {
-        uint4 *dst = reinterpret_cast<uint4 *>(smem);
-        const uint4 *src = reinterpret_cast<const uint4 *>(g_table);
-        stage_table(dst, src, table_bytes / 16u);
-    }
+    stage_table(reinterpret_cast<uint4 *>(smem), reinterpret_cast<const uint4 *>(g_table), table_bytes / 16u);
     KgStep<B> st{smem, kp};
-    walk_chunk<G, KgStep<B>, ALIGNED, TILE>(st, text, n, L, nchunks, g_cls, g_loff, g_llist, start_class, sent,
-                                            merge != 0, smem + table_bytes, map, map_cls);
+    walk_chunk<G, KgStep<B>, ALIGNED, TILE, MODE>(st, a, smem + table_bytes);
 }
 
 // ---------------------------------------------------------------------------
@@ -503,7 +559,7 @@ __device__ __forceinline__ int find_state(const uint32_t *__restrict__ list, uin
 struct ComposeArgs {
     const uint32_t *loff;
     const uint32_t *llist;
-    const uint16_t *inv;   // [(A+2) * (Q+1)] index of a state in a class list, 0xffff if absent; may be null
+    const uint16_t *inv;   // [(A+2) * (Q+1)] position of a state in a class list, 0xffff if absent; may be null
     uint32_t inv_bytes;    // staged in LDS when non-zero
     uint32_t Q1;           // Q + 1
     uint32_t sent;
@@ -513,10 +569,10 @@ struct ComposeArgs {
     uint64_t chunks;
 };
 
-// LDS image of P maps. A map m has entries j < sz[m] with end[m][j] and
-// count base[m] + cnt[m][j]. A uniform map (uni[m] != 0) sends every entry
-// to the same end state, stored in end[m][0]; composing a uniform map on the
-// left with any map costs one lookup, and the result is uniform again.
+// LDS image of P maps. Map m has entries j < sz[m]: end[m][j] (kAbsent32:
+// not walked) and count base[m] + cnt[m][j]. A uniform map (uni[m] != 0)
+// sends every present entry to the same state lead[m]; composing a uniform
+// map on the left with any map costs one lookup and yields a uniform map.
 struct Tree {
     uint64_t *cnt;
     uint64_t *base;
@@ -524,10 +580,12 @@ struct Tree {
     uint32_t *cls;
     uint32_t *sz;
     uint32_t *uni;
+    uint32_t *lead;
     const uint16_t *inv;
 };
 
 __device__ __forceinline__ int lookup(const ComposeArgs &a, const Tree &t, uint32_t cls, uint32_t sz, uint32_t e) {
+    if (e >= a.Q1) return -1;
     if (t.inv) {
         const uint32_t v = t.inv[cls * a.Q1 + e];
         return v == 0xffffu ? -1 : (int)v;
@@ -535,7 +593,6 @@ __device__ __forceinline__ int lookup(const ComposeArgs &a, const Tree &t, uint3
     return find_state(a.llist + a.loff[cls], sz, e);
 }
 
-// carve the dynamic LDS of a compose workgroup
 __device__ __forceinline__ Tree carve(uint8_t *smem, const ComposeArgs &a) {
     Tree t;
     const size_t pr = (size_t)a.P * a.RM;
@@ -545,7 +602,8 @@ __device__ __forceinline__ Tree carve(uint8_t *smem, const ComposeArgs &a) {
     t.cls = t.end + pr;
     t.sz = t.cls + a.P;
     t.uni = t.sz + a.P;
-    uint16_t *inv = reinterpret_cast<uint16_t *>(t.uni + a.P);
+    t.lead = t.uni + a.P;
+    uint16_t *inv = reinterpret_cast<uint16_t *>(t.lead + a.P);
     if (a.inv_bytes) {
         const uint32_t nw = a.inv_bytes / 4;
         const uint32_t *src = reinterpret_cast<const uint32_t *>(a.inv);
@@ -556,6 +614,13 @@ __device__ __forceinline__ Tree carve(uint8_t *smem, const ComposeArgs &a) {
         t.inv = a.inv;
     }
     return t;
+}
+
+// end of map r's entry x (kAbsent32 when that entry was not walked)
+__device__ __forceinline__ uint32_t end_at(const Tree &t, uint32_t RM, uint32_t r, uint32_t x) {
+    const uint32_t e = t.end[r * RM + x];
+    if (e == kAbsent32) return kAbsent32;
+    return t.uni[r] ? t.lead[r] : e;
 }
 
 // binary tree over np maps already in LDS; the result is map 0
@@ -571,14 +636,12 @@ __device__ __forceinline__ void tree(const ComposeArgs &a, const Tree &t, uint32
                 general = 1;
                 continue;
             }
-            const uint32_t e = t.end[left * RM];
+            const uint32_t e = t.lead[left];
             const int x = lookup(a, t, t.cls[right], t.sz[right], e);
-            if (x < 0) {
-                t.end[left * RM] = a.sent;  // only the sentinel leaves the lists
-            } else {
-                t.base[left] += t.base[right] + t.cnt[right * RM + (uint32_t)x];
-                t.end[left * RM] = t.uni[right] ? t.end[right * RM] : t.end[right * RM + (uint32_t)x];
-            }
+            const uint32_t ex = x < 0 ? a.sent : end_at(t, RM, right, (uint32_t)x);
+            if (x >= 0 && ex != kAbsent32) t.base[left] += t.base[right] + t.cnt[right * RM + (uint32_t)x];
+            // a missing entry (sentinel, or a state not walked: off the true run) ends the map there
+            t.lead[left] = ex == kAbsent32 ? a.sent : ex;
         }
         if (__syncthreads_or(general)) {
             for (uint32_t k = threadIdx.x; k < npairs * RM; k += kComposeThreads) {
@@ -586,42 +649,63 @@ __device__ __forceinline__ void tree(const ComposeArgs &a, const Tree &t, uint32
                 const uint32_t left = i * 2 * w, right = left + w;
                 if (right < np && !t.uni[left] && j < t.sz[left]) {
                     const uint32_t e = t.end[left * RM + j];
+                    if (e == kAbsent32) continue;
                     const int x = lookup(a, t, t.cls[right], t.sz[right], e);
                     if (x < 0) {
-                        t.end[left * RM + j] = a.sent;
+                        t.end[left * RM + j] = a.sent;  // only the sentinel leaves the lists
                     } else {
-                        t.cnt[left * RM + j] += t.base[right] + t.cnt[right * RM + (uint32_t)x];
-                        t.end[left * RM + j] = t.uni[right] ? t.end[right * RM] : t.end[right * RM + (uint32_t)x];
+                        const uint32_t ex = end_at(t, RM, right, (uint32_t)x);
+                        if (ex != kAbsent32)
+                            t.cnt[left * RM + j] += t.base[right] + t.cnt[right * RM + (uint32_t)x];
+                        t.end[left * RM + j] = ex;
                     }
                 }
             }
             __syncthreads();
             for (uint32_t i = threadIdx.x; i < npairs; i += kComposeThreads) {
                 const uint32_t left = i * 2 * w, right = left + w;
-                if (right < np && !t.uni[left]) t.uni[left] = t.uni[right];
+                if (right < np && !t.uni[left] && t.uni[right]) {
+                    // every present entry now ends where the right map's walks end
+                    t.uni[left] = 1;
+                    t.lead[left] = t.lead[right];
+                    for (uint32_t j = 0; j < t.sz[left]; ++j) {
+                        const uint32_t e = t.end[left * RM + j];
+                        if (e != kAbsent32 && e != t.lead[right]) t.uni[left] = 0;
+                    }
+                }
             }
         }
         __syncthreads();
     }
 }
 
-__device__ __forceinline__ void emit(const ComposeArgs &a, const Tree &t, uint64_t runs_total,
-                                     uint32_t *__restrict__ out_end, uint64_t *__restrict__ out_cnt,
-                                     uint32_t *__restrict__ out_cls, uint64_t *__restrict__ out_runs,
+// segment map outputs of one workgroup
+struct SegOut {
+    uint32_t *end;
+    uint64_t *cnt;
+    uint32_t *cls;   // bit 31: not uniform
+    uint64_t *runs;
+    uint32_t *lead;
+};
+
+__device__ __forceinline__ void emit(const ComposeArgs &a, const Tree &t, uint64_t runs_total, const SegOut &o,
                                      parem_result *__restrict__ result) {
     const bool uni = t.uni[0] != 0;
     const uint64_t base = t.base[0];
     for (uint32_t j = threadIdx.x; j < t.sz[0]; j += kComposeThreads) {
-        out_end[(uint64_t)blockIdx.x * a.RM + j] = uni ? t.end[0] : t.end[j];
-        out_cnt[(uint64_t)blockIdx.x * a.RM + j] = base + t.cnt[j];
+        const uint32_t e = t.end[j];
+        o.end[(uint64_t)blockIdx.x * a.RM + j] = e == kAbsent32 ? kAbsent32 : (uni ? t.lead[0] : e);
+        o.cnt[(uint64_t)blockIdx.x * a.RM + j] = base + t.cnt[j];
     }
     if (threadIdx.x == 0) {
-        out_cls[blockIdx.x] = t.cls[0] | (uni ? 0u : 0x80000000u);
-        out_runs[blockIdx.x] = runs_total;
+        o.cls[blockIdx.x] = t.cls[0] | (uni ? 0u : 0x80000000u);
+        o.runs[blockIdx.x] = runs_total;
+        o.lead[blockIdx.x] = t.lead[0];
         if (result != nullptr && gridDim.x == 1) {
-            const uint32_t e = t.end[0];
+            // the last map: domain {q0}, entry 0
+            const uint32_t e = uni ? t.lead[0] : t.end[0];
             parem_result r;
-            if (e == a.sent) {
+            if (e >= a.sent) {
                 r.final_state = 0xffffffffu;
                 r.accept = 0;
                 r.count = 0;
@@ -650,60 +734,53 @@ __device__ __forceinline__ uint64_t block_sum(uint64_t v) {
     return s;
 }
 
-// All P maps of a workgroup uniform: map i (i >= 1) is entered in the single
-// end state of map i-1, so it contributes the count of that one entry and no
-// tree is needed: one lookup per map and a block sum. The segment map keeps
-// the first map's entries, each raised by that sum, and ends where the last
-// map ends (in the sentinel if some end state is missing from the next list,
-// which only the sentinel can be).
-struct Uniform {
-    uint32_t end;
-    uint64_t sum;
-    int fail;
-};
-
-template <typename EndOf, typename CntOf>
-__device__ __forceinline__ Uniform uniform_chain(const ComposeArgs &a, const Tree &t, uint32_t np, EndOf end_of,
-                                                 CntOf cnt_of) {
+// All maps of the workgroup uniform: map i (i >= 1) is entered in map i-1's
+// lead state, so it contributes the count of that one entry and no tree is
+// needed (one lookup per map, a block sum). The workgroup's map keeps the
+// first map's entries raised by that sum and ends in the last map's lead
+// (the sentinel if a state is missing from the next list).
+template <typename CntOf, typename PresentOf>
+__device__ __forceinline__ void uniform_chain(const ComposeArgs &a, const Tree &t, uint32_t np, CntOf cnt_of,
+                                              PresentOf present_of, uint64_t &sum, uint32_t &end) {
     const uint32_t i = threadIdx.x;
-    if (i < np) t.end[i] = end_of(i);
-    __syncthreads();
     uint64_t contrib = 0;
     int fail = 0;
     if (i < np && i > 0) {
-        const int x = lookup(a, t, t.cls[i], t.sz[i], t.end[i - 1]);
-        if (x < 0) fail = 1;
+        const int x = lookup(a, t, t.cls[i], t.sz[i], t.lead[i - 1]);
+        if (x < 0 || !present_of(i, (uint32_t)x)) fail = 1;
         else contrib = cnt_of(i, (uint32_t)x);
     }
-    Uniform u;
-    u.sum = block_sum(contrib);
-    u.fail = __syncthreads_or(fail);
-    u.end = u.fail ? a.sent : t.end[np - 1];
-    return u;
+    sum = block_sum(contrib);
+    fail = __syncthreads_or(fail);
+    end = fail ? a.sent : t.lead[np - 1];
 }
 
-template <typename CntOf>
-__device__ __forceinline__ void emit_uniform(const ComposeArgs &a, const Tree &t, const Uniform &u,
-                                             uint64_t runs_total, CntOf first_cnt, uint32_t *__restrict__ out_end,
-                                             uint64_t *__restrict__ out_cnt, uint32_t *__restrict__ out_cls,
-                                             uint64_t *__restrict__ out_runs, parem_result *__restrict__ result) {
+template <typename FirstOf>
+__device__ __forceinline__ void emit_uniform(const ComposeArgs &a, const Tree &t, uint64_t sum, uint32_t end,
+                                             uint64_t runs_total, FirstOf first_of, const SegOut &o,
+                                             parem_result *__restrict__ result) {
     for (uint32_t j = threadIdx.x; j < t.sz[0]; j += kComposeThreads) {
-        out_end[(uint64_t)blockIdx.x * a.RM + j] = u.end;
-        out_cnt[(uint64_t)blockIdx.x * a.RM + j] = first_cnt(j) + u.sum;
+        uint64_t c;
+        const bool present = first_of(j, c);
+        o.end[(uint64_t)blockIdx.x * a.RM + j] = present ? end : kAbsent32;
+        o.cnt[(uint64_t)blockIdx.x * a.RM + j] = c + sum;
     }
     if (threadIdx.x == 0) {
-        out_cls[blockIdx.x] = t.cls[0];
-        out_runs[blockIdx.x] = runs_total;
+        o.cls[blockIdx.x] = t.cls[0];
+        o.runs[blockIdx.x] = runs_total;
+        o.lead[blockIdx.x] = end;
         if (result != nullptr && gridDim.x == 1) {
+            uint64_t c0;
+            first_of(0, c0);
             parem_result r;
-            if (u.end == a.sent) {
+            if (end >= a.sent) {
                 r.final_state = 0xffffffffu;
                 r.accept = 0;
                 r.count = 0;
             } else {
-                r.final_state = u.end;
-                r.accept = a.final_flag[u.end];
-                r.count = first_cnt(0) + u.sum;
+                r.final_state = end;
+                r.accept = a.final_flag[end];
+                r.count = c0 + sum;
             }
             r.chunks = a.chunks;
             r.spec_runs = runs_total;
@@ -714,10 +791,11 @@ __device__ __forceinline__ void emit_uniform(const ComposeArgs &a, const Tree &t
 }
 
 // level 1: chunk maps, entry-major packed (end | count << 16)
-__global__ __launch_bounds__(kComposeThreads) void k_compose_chunks(
-    const uint32_t *__restrict__ map, const uint16_t *__restrict__ map_cls, ComposeArgs a,
-    uint32_t *__restrict__ out_end, uint64_t *__restrict__ out_cnt, uint32_t *__restrict__ out_cls,
-    uint64_t *__restrict__ out_runs, parem_result *__restrict__ result) {
+__global__ __launch_bounds__(kComposeThreads) void k_compose_chunks(const uint32_t *__restrict__ map,
+                                                                     const uint16_t *__restrict__ map_cls,
+                                                                     const uint16_t *__restrict__ map_lead,
+                                                                     ComposeArgs a, SegOut o,
+                                                                     parem_result *__restrict__ result) {
     extern __shared__ __align__(16) uint8_t smem[];
     Tree t = carve(smem, a);
     const uint64_t g0 = (uint64_t)blockIdx.x * a.P;
@@ -731,18 +809,27 @@ __global__ __launch_bounds__(kComposeThreads) void k_compose_chunks(
         t.cls[i] = cl;
         t.sz[i] = sz;
         t.uni[i] = (v & 0x8000u) ? 0u : 1u;
+        t.lead[i] = map_lead[g0 + i];
         t.base[i] = 0;
         nonuni |= (v & 0x8000u) ? 1 : 0;
         runs += sz;
     }
     const uint64_t runs_total = block_sum(runs);  // contains a barrier
+    const uint64_t C = a.chunks;
     if (!__syncthreads_or(nonuni) && np <= (uint32_t)kComposeThreads) {
-        const uint64_t C = a.chunks;
-        auto end_of = [&](uint32_t i) { return map[g0 + i] & 0xffffu; };
         auto cnt_of = [&](uint32_t i, uint32_t x) { return (uint64_t)(map[(uint64_t)x * C + g0 + i] >> 16); };
-        auto first = [&](uint32_t j) { return (uint64_t)(map[(uint64_t)j * C + g0] >> 16); };
-        const Uniform u = uniform_chain(a, t, np, end_of, cnt_of);
-        emit_uniform(a, t, u, runs_total, first, out_end, out_cnt, out_cls, out_runs, result);
+        auto present_of = [&](uint32_t i, uint32_t x) {
+            return (map[(uint64_t)x * C + g0 + i] & 0xffffu) != kAbsent16;
+        };
+        auto first_of = [&](uint32_t j, uint64_t &c) {
+            const uint32_t v = map[(uint64_t)j * C + g0];
+            c = v >> 16;
+            return (v & 0xffffu) != kAbsent16;
+        };
+        uint64_t sum;
+        uint32_t end;
+        uniform_chain(a, t, np, cnt_of, present_of, sum, end);
+        emit_uniform(a, t, sum, end, runs_total, first_of, o, result);
         return;
     }
     // 8 loads in flight per thread before the LDS stores; i fastest: coalesced
@@ -756,7 +843,7 @@ __global__ __launch_bounds__(kComposeThreads) void k_compose_chunks(
             if (k < total) {
                 const uint32_t j = k / np, i = k - j * np;
                 if (j < t.sz[i]) {
-                    v[u] = map[(uint64_t)j * a.chunks + g0 + i];
+                    v[u] = map[(uint64_t)j * C + g0 + i];
                     slot[u] = i * a.RM + j;
                 }
             }
@@ -764,26 +851,30 @@ __global__ __launch_bounds__(kComposeThreads) void k_compose_chunks(
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             if (slot[u] != 0xffffffffu) {
-                t.end[slot[u]] = v[u] & 0xffffu;
+                const uint32_t e = v[u] & 0xffffu;
+                t.end[slot[u]] = e == kAbsent16 ? kAbsent32 : e;
                 t.cnt[slot[u]] = v[u] >> 16;
             }
         }
     }
     __syncthreads();
     tree(a, t, np);
-    emit(a, t, runs_total, out_end, out_cnt, out_cls, out_runs, result);
+    emit(a, t, runs_total, o, result);
 }
 
 // levels >= 2: segment maps, row-major (end u32, count u64)
-__global__ __launch_bounds__(kComposeThreads) void k_compose_segs(
-    const uint32_t *__restrict__ in_end, const uint64_t *__restrict__ in_cnt, const uint32_t *__restrict__ in_cls,
-    const uint64_t *__restrict__ in_runs, uint64_t nin, ComposeArgs a, uint32_t *__restrict__ out_end,
-    uint64_t *__restrict__ out_cnt, uint32_t *__restrict__ out_cls, uint64_t *__restrict__ out_runs,
-    parem_result *__restrict__ result) {
+__global__ __launch_bounds__(kComposeThreads) void k_compose_segs(const uint32_t *__restrict__ in_end,
+                                                                   const uint64_t *__restrict__ in_cnt,
+                                                                   const uint32_t *__restrict__ in_cls,
+                                                                   const uint64_t *__restrict__ in_runs,
+                                                                   const uint32_t *__restrict__ in_lead, uint64_t nin,
+                                                                   ComposeArgs a, SegOut o,
+                                                                   parem_result *__restrict__ result) {
     extern __shared__ __align__(16) uint8_t smem[];
     Tree t = carve(smem, a);
     const uint64_t g0 = (uint64_t)blockIdx.x * a.P;
     const uint32_t np = (uint32_t)min((uint64_t)a.P, nin - g0);
+    const uint32_t RM = a.RM;
     uint64_t runs = 0;
     int nonuni = 0;
     for (uint32_t i = threadIdx.x; i < np; i += kComposeThreads) {
@@ -792,21 +883,26 @@ __global__ __launch_bounds__(kComposeThreads) void k_compose_segs(
         t.cls[i] = cl;
         t.sz[i] = a.loff[cl + 1] - a.loff[cl];
         t.uni[i] = (v & 0x80000000u) ? 0u : 1u;
+        t.lead[i] = in_lead[g0 + i];
         t.base[i] = 0;
         nonuni |= (v & 0x80000000u) ? 1 : 0;
         runs += in_runs[g0 + i];
     }
     const uint64_t runs_total = block_sum(runs);
     if (!__syncthreads_or(nonuni) && np <= (uint32_t)kComposeThreads) {
-        const uint32_t RM = a.RM;
-        auto end_of = [&](uint32_t i) { return in_end[(g0 + i) * RM]; };
         auto cnt_of = [&](uint32_t i, uint32_t x) { return in_cnt[(g0 + i) * RM + x]; };
-        auto first = [&](uint32_t j) { return in_cnt[g0 * RM + j]; };
-        const Uniform u = uniform_chain(a, t, np, end_of, cnt_of);
-        emit_uniform(a, t, u, runs_total, first, out_end, out_cnt, out_cls, out_runs, result);
+        auto present_of = [&](uint32_t i, uint32_t x) { return in_end[(g0 + i) * RM + x] != kAbsent32; };
+        auto first_of = [&](uint32_t j, uint64_t &c) {
+            c = in_cnt[g0 * RM + j];
+            return in_end[g0 * RM + j] != kAbsent32;
+        };
+        uint64_t sum;
+        uint32_t end;
+        uniform_chain(a, t, np, cnt_of, present_of, sum, end);
+        emit_uniform(a, t, sum, end, runs_total, first_of, o, result);
         return;
     }
-    const uint32_t total = np * a.RM;
+    const uint32_t total = np * RM;
     for (uint32_t k0 = threadIdx.x; k0 < total; k0 += 4 * kComposeThreads) {
         uint32_t e[4];
         uint64_t cn[4];
@@ -816,10 +912,10 @@ __global__ __launch_bounds__(kComposeThreads) void k_compose_segs(
             const uint32_t k = k0 + (uint32_t)u * kComposeThreads;
             ok[u] = false;
             if (k < total) {
-                const uint32_t i = k / a.RM, j = k - i * a.RM;
+                const uint32_t i = k / RM, j = k - i * RM;
                 if (j < t.sz[i]) {
-                    e[u] = in_end[g0 * a.RM + k];
-                    cn[u] = in_cnt[g0 * a.RM + k];
+                    e[u] = in_end[g0 * RM + k];
+                    cn[u] = in_cnt[g0 * RM + k];
                     ok[u] = true;
                 }
             }
@@ -834,7 +930,7 @@ __global__ __launch_bounds__(kComposeThreads) void k_compose_segs(
     }
     __syncthreads();
     tree(a, t, np);
-    emit(a, t, runs_total, out_end, out_cnt, out_cls, out_runs, result);
+    emit(a, t, runs_total, o, result);
 }
 
 __global__ void k_empty_result(uint32_t start, const uint8_t *__restrict__ final_flag,
@@ -852,20 +948,201 @@ __global__ void k_empty_result(uint32_t start, const uint8_t *__restrict__ final
 }
 
 // ---------------------------------------------------------------------------
+// learned speculation: coverage check and statistics
+// ---------------------------------------------------------------------------
+
+// position of state e in chunk c's map, or -1 (not in the list, or not walked)
+__device__ __forceinline__ int chunk_present(const uint32_t *__restrict__ map, uint64_t C, uint64_t c,
+                                             uint32_t cls, const uint16_t *__restrict__ inv, uint32_t Q1, uint32_t e) {
+    if (e >= Q1) return -1;
+    const uint32_t v = inv[cls * Q1 + e];
+    if (v == 0xffffu) return -1;
+    if ((map[(uint64_t)v * C + c] & 0xffffu) == kAbsent16) return -1;
+    return (int)v;
+}
+
+// Chunk c (>= 1) is covered when every end state of chunk c-1's walks is one
+// of chunk c's walked entries; then, by induction from chunk 0 (entered in
+// q0, always walked), every chunk's true entry state was walked. Uncovered
+// chunks get redo[c] = 1 and are walked again from their whole speculated
+// set (which holds every possible entry). `escalate` != 0: if any chunk is
+// uncovered, every chunk not yet complete is marked.
+__global__ void k_cover(const uint32_t *__restrict__ map, const uint16_t *__restrict__ map_cls,
+                        const uint16_t *__restrict__ map_lead, uint64_t C, const uint32_t *__restrict__ loff,
+                        const uint16_t *__restrict__ inv, uint32_t Q1, uint32_t sent, uint8_t *__restrict__ redo,
+                        uint8_t *__restrict__ done, uint32_t *__restrict__ flags, uint32_t escalate) {
+    const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    redo[c] = 0;
+    if (c == 0 || done[c]) return;
+    const uint32_t pv = map_cls[c - 1], cv = map_cls[c];
+    const uint32_t pcls = pv & 0x7fffu, ccls = cv & 0x7fffu;
+    bool covered = true;
+    if (!(pv & 0x8000u)) {
+        const uint32_t e = map_lead[c - 1];
+        covered = e == sent || chunk_present(map, C, c, ccls, inv, Q1, e) >= 0;
+    } else {
+        const uint32_t sz = loff[pcls + 1] - loff[pcls];
+        for (uint32_t j = 0; j < sz && covered; ++j) {
+            const uint32_t v = map[(uint64_t)j * C + c - 1];
+            const uint32_t e = v & 0xffffu;
+            if (e == kAbsent16 || e == sent) continue;
+            covered = chunk_present(map, C, c, ccls, inv, Q1, e) >= 0;
+        }
+    }
+    if (!covered) {
+        if (escalate) {
+            atomicOr(&flags[1], 1u);
+        } else {
+            redo[c] = 1;
+            done[c] = 1;
+            atomicAdd(&flags[0], 1u);
+        }
+    }
+}
+
+// second half of an escalation: if some chunk is still uncovered, every
+// chunk not yet walked from its whole set is marked
+__global__ void k_escalate(uint64_t C, uint8_t *__restrict__ redo, uint8_t *__restrict__ done,
+                           uint32_t *__restrict__ flags) {
+    const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C || flags[1] == 0 || c == 0) return;
+    if (!done[c]) {
+        redo[c] = 1;
+        done[c] = 1;
+        atomicAdd(&flags[0], 1u);
+    }
+}
+
+// walks started and chunks walked again: block partial sums, then the
+// result is written by k_learned_total
+__global__ void k_learned_stats(const uint8_t *__restrict__ nsel, const uint8_t *__restrict__ done,
+                                const uint16_t *__restrict__ map_cls, const uint32_t *__restrict__ loff, uint64_t C,
+                                unsigned long long *__restrict__ acc) {
+    const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long runs = 0, redo = 0;
+    if (c < C) {
+        runs = nsel[c];
+        if (done[c]) {
+            const uint32_t cl = map_cls[c] & 0x7fffu;
+            runs += loff[cl + 1] - loff[cl];
+            redo = 1;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        runs += (unsigned long long)__shfl_xor((long long)runs, o, 64);
+        redo += (unsigned long long)__shfl_xor((long long)redo, o, 64);
+    }
+    __shared__ unsigned long long part[2][4];
+    if ((threadIdx.x & 63u) == 0) {
+        part[0][threadIdx.x >> 6] = runs;
+        part[1][threadIdx.x >> 6] = redo;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(&acc[0], part[0][0] + part[0][1] + part[0][2] + part[0][3]);
+        atomicAdd(&acc[1], part[1][0] + part[1][1] + part[1][2] + part[1][3]);
+    }
+}
+
+__global__ void k_learned_total(const unsigned long long *__restrict__ acc, parem_result *__restrict__ result) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        result->spec_runs = acc[0];
+        result->rerun_chunks = acc[1];
+    }
+}
+
+__global__ void k_clear_u8(uint8_t *__restrict__ p, uint64_t n) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+__global__ void k_clear_u32(uint32_t *__restrict__ p, uint32_t n) {
+    if (threadIdx.x < n) p[threadIdx.x] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// boundary states: down-sweep of entry states through the kept levels
+// ---------------------------------------------------------------------------
+
+// entry state of map i at a level whose maps are grouped P to a parent;
+// parent entries are known. Walk from the nearest uniform map before i in
+// the group (its lead is the exit of whatever entered it) or from the group
+// start, applying each map to the state.
+template <bool CHUNKS>
+__global__ void k_entries(uint64_t nmaps, uint32_t P, const uint32_t *__restrict__ parent_entry,
+                          const uint32_t *__restrict__ seg_end, const uint32_t *__restrict__ seg_cls,
+                          const uint32_t *__restrict__ seg_lead, const uint32_t *__restrict__ cmap,
+                          const uint16_t *__restrict__ cmap_cls, const uint16_t *__restrict__ cmap_lead,
+                          const uint16_t *__restrict__ inv, uint32_t Q1, uint32_t RM, uint32_t sent,
+                          uint32_t *__restrict__ entry) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nmaps) return;
+    const uint64_t g0 = i / P * P;
+    auto uniform = [&](uint64_t k) {
+        return CHUNKS ? !(cmap_cls[k] & 0x8000u) : !(seg_cls[k] & 0x80000000u);
+    };
+    auto lead = [&](uint64_t k) { return CHUNKS ? (uint32_t)cmap_lead[k] : seg_lead[k]; };
+    auto apply = [&](uint64_t k, uint32_t e) -> uint32_t {
+        if (e >= Q1) return sent;
+        const uint32_t cl = CHUNKS ? (cmap_cls[k] & 0x7fffu) : (seg_cls[k] & 0x7fffffffu);
+        const uint32_t x = inv[cl * Q1 + e];
+        if (x == 0xffffu) return sent;
+        uint32_t ex;
+        if (CHUNKS) {
+            ex = cmap[(uint64_t)x * nmaps + k] & 0xffffu;
+            if (ex == kAbsent16) return sent;
+        } else {
+            ex = seg_end[k * RM + x];
+            if (ex == kAbsent32) return sent;
+        }
+        return uniform(k) ? lead(k) : ex;
+    };
+    uint64_t k = i;
+    while (k > g0 && !uniform(k - 1)) --k;
+    uint32_t e;
+    if (k > g0) {
+        e = lead(k - 1);  // a uniform map ends in its lead whatever entered it
+    } else {
+        e = parent_entry[i / P];
+    }
+    for (uint64_t j = k; j < i; ++j) e = apply(j, e);
+    entry[i] = e >= sent ? 0xffffffffu : e;
+}
+
+// The down-sweep shortcut above trusts a uniform map's lead, which holds
+// only when its entry state is in its list; the sentinel (after a byte
+// outside the alphabet) is in none. The first chunk whose walks end in the
+// sentinel contains the first such byte: every later boundary is invalid.
+__global__ void k_first_bad(const uint16_t *__restrict__ map_lead, uint64_t C, uint32_t sent,
+                            uint32_t *__restrict__ first_bad) {
+    const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < C && map_lead[c] == sent) atomicMin(first_bad, (uint32_t)c);
+}
+
+__global__ void k_after_bad(uint32_t *__restrict__ states, uint64_t C, const uint32_t *__restrict__ first_bad) {
+    const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < C && c > *first_bad) states[c] = 0xffffffffu;
+}
+
+__global__ void k_set_u32(uint32_t *__restrict__ p, uint32_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+// ---------------------------------------------------------------------------
 // host side: plan and launches
 // ---------------------------------------------------------------------------
 
 static uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
 
 static uint32_t compose_lds(uint32_t P, uint32_t RM, uint32_t inv_lds) {
-    return P * RM * 12u + P * 20u + inv_lds;
+    return P * RM * 12u + P * 24u + inv_lds;
 }
 
-parem_status plan_plain(const DeviceDfa &d, uint64_t len, PlainPlan *p) {
+static parem_status plan_common(const DeviceDfa &d, uint64_t len, uint32_t L, bool keep, PlainPlan *p) {
     PlainPlan q;
     q.n = len;
     q.RM = d.max_spec;
-    uint32_t L = d.opt.chunk_len;
     if (L == 0) {
         // about 2^17 chunks for large texts (two 256-lane workgroups per CU
         // on a 1 GiB text), at least 256 bytes each
@@ -886,7 +1163,6 @@ parem_status plan_plain(const DeviceDfa &d, uint64_t len, PlainPlan *p) {
     while (P > 2 && compose_lds(P, q.RM, d.inv_lds) > 64 * 1024) P >>= 1;
     if (compose_lds(P, q.RM, d.inv_lds) > 150 * 1024) return PAREM_EUNSUPPORTED;
     q.P = P;
-    q.level_cap = q.chunks > 1 ? (q.chunks + P - 1) / P : 1;
     uint64_t off = 0;
     auto take = [&](uint64_t bytes) {
         uint64_t o = off;
@@ -894,35 +1170,63 @@ parem_status plan_plain(const DeviceDfa &d, uint64_t len, PlainPlan *p) {
         return o;
     };
     const uint64_t ch = std::max<uint64_t>(q.chunks, 1);
-    q.off_cend = take(ch * q.RM * 4);   // packed chunk maps
-    q.off_ccls = take(ch * 2);
-    const uint64_t lm = q.level_cap * q.RM;
-    q.off_a_end = take(lm * 4);
-    q.off_a_cnt = take(lm * 8);
-    q.off_a_cls = take(q.level_cap * 4);
-    q.off_a_runs = take(q.level_cap * 8);
-    q.off_b_end = take(lm * 4);
-    q.off_b_cnt = take(lm * 8);
-    q.off_b_cls = take(q.level_cap * 4);
-    q.off_b_runs = take(q.level_cap * 8);
+    q.off_map = take(ch * q.RM * 4);  // packed chunk maps
+    q.off_mcls = take(ch * 2);
+    q.off_mlead = take(ch * 2);
+    // segment levels: kept separately (down-sweep) or two ping-pong buffers
+    uint64_t m = q.chunks;
+    q.levels.clear();
+    do {
+        m = (m + P - 1) / P;
+        q.levels.push_back(m);
+    } while (m > 1);
+    const size_t nbuf = keep ? q.levels.size() : std::min<size_t>(2, q.levels.size());
+    q.seg.assign(nbuf, PlainPlan::Seg{});
+    for (size_t l = 0; l < nbuf; ++l) {
+        const uint64_t cap = keep ? q.levels[l] : q.levels[0];
+        PlainPlan::Seg &g = q.seg[l];
+        g.end = take(cap * q.RM * 4);
+        g.cnt = take(cap * q.RM * 8);
+        g.cls = take(cap * 4);
+        g.runs = take(cap * 8);
+        g.lead = take(cap * 4);
+    }
+    q.keep = keep;
     q.bytes = off;
     *p = q;
     return PAREM_OK;
 }
 
-template <typename E, uint32_t ROW, bool LDS, bool ALIGNED, uint32_t TILE>
-static void launch_walk_byte(const DeviceDfa &d, const PlainPlan &p, const uint8_t *text, uint8_t *ws,
-                             hipStream_t stream) {
+parem_status plan_plain(const DeviceDfa &d, uint64_t len, PlainPlan *p) {
+    return plan_common(d, len, d.opt.chunk_len, false, p);
+}
+
+static WalkArgs walk_args(const DeviceDfa &d, const PlainPlan &p, const uint8_t *text, uint8_t *ws) {
+    WalkArgs a{};
+    a.text = text;
+    a.n = p.n;
+    a.L = p.L;
+    a.nchunks = p.chunks;
+    a.cls = d.d_cls;
+    a.loff = d.d_loff;
+    a.llist = d.d_llist;
+    a.start_class = d.A + 1;
+    a.sent = d.sent;
+    a.merge = p.merge;
+    a.map = reinterpret_cast<uint32_t *>(ws + p.off_map);
+    a.map_cls = reinterpret_cast<uint16_t *>(ws + p.off_mcls);
+    a.map_lead = reinterpret_cast<uint16_t *>(ws + p.off_mlead);
+    return a;
+}
+
+template <typename E, uint32_t ROW, bool LDS, bool ALIGNED, uint32_t TILE, int MODE>
+static void launch_walk_byte(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, hipStream_t stream) {
     const uint32_t grid = (uint32_t)((p.chunks + kWalkThreads - 1) / kWalkThreads);
-    const size_t lds = (LDS ? d.table_bytes : 0) + (ALIGNED ? Stage<TILE>::kBytes : 0);
-    auto *map = reinterpret_cast<uint32_t *>(ws + p.off_cend);
-    auto *mcl = reinterpret_cast<uint16_t *>(ws + p.off_ccls);
+    const size_t lds = (LDS ? d.table_bytes : 0) + ((ALIGNED && MODE != WALK_REDO) ? Stage<TILE>::kBytes : 0);
     const E *tab = reinterpret_cast<const E *>(d.d_table);
-    const uint32_t start_class = d.A + 1;
-#define PAREM_WALK(GG)                                                                                       \
-    hipLaunchKernelGGL((k_walk_byte<E, ROW, GG, LDS, ALIGNED, TILE>), dim3(grid), dim3(kWalkThreads), lds,  \
-                       stream, text, p.n, p.L, p.chunks, tab, d.table_bytes, d.d_cls, d.d_loff, d.d_llist,   \
-                       start_class, d.sent, p.merge, map, mcl)
+#define PAREM_WALK(GG)                                                                                            \
+    hipLaunchKernelGGL((k_walk_byte<E, ROW, GG, LDS, ALIGNED, TILE, MODE>), dim3(grid), dim3(kWalkThreads), lds, \
+                       stream, a, tab, d.table_bytes)
     switch (p.G) {
         case 2: PAREM_WALK(2); break;
         case 4: PAREM_WALK(4); break;
@@ -932,19 +1236,14 @@ static void launch_walk_byte(const DeviceDfa &d, const PlainPlan &p, const uint8
 #undef PAREM_WALK
 }
 
-template <int B, bool ALIGNED, uint32_t TILE>
-static void launch_kgram_b(const DeviceDfa &d, const PlainPlan &p, const uint8_t *text, uint8_t *ws,
-                           hipStream_t stream) {
+template <int B, bool ALIGNED, uint32_t TILE, int MODE>
+static void launch_kgram_b(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, hipStream_t stream) {
     const uint32_t grid = (uint32_t)((p.chunks + kWalkThreads - 1) / kWalkThreads);
-    const size_t lds = d.table_bytes + (ALIGNED ? Stage<TILE>::kBytes : 0);
-    auto *map = reinterpret_cast<uint32_t *>(ws + p.off_cend);
-    auto *mcl = reinterpret_cast<uint16_t *>(ws + p.off_ccls);
+    const size_t lds = d.table_bytes + ((ALIGNED && MODE != WALK_REDO) ? Stage<TILE>::kBytes : 0);
     const uint8_t *tab = reinterpret_cast<const uint8_t *>(d.d_table);
-    const uint32_t start_class = d.A + 1;
-#define PAREM_KG(GG)                                                                                         \
-    hipLaunchKernelGGL((k_walk_kgram<GG, B, ALIGNED, TILE>), dim3(grid), dim3(kWalkThreads), lds, stream,  \
-                       text, p.n, p.L, p.chunks, tab, d.table_bytes, d.kg, d.d_cls, d.d_loff, d.d_llist,    \
-                       start_class, d.sent, p.merge, map, mcl)
+#define PAREM_KG(GG)                                                                                              \
+    hipLaunchKernelGGL((k_walk_kgram<GG, B, ALIGNED, TILE, MODE>), dim3(grid), dim3(kWalkThreads), lds, stream, a, \
+                       tab, d.table_bytes, d.kg)
     switch (p.G) {
         case 2: PAREM_KG(2); break;
         case 4: PAREM_KG(4); break;
@@ -954,42 +1253,30 @@ static void launch_kgram_b(const DeviceDfa &d, const PlainPlan &p, const uint8_t
 #undef PAREM_KG
 }
 
-template <bool ALIGNED, uint32_t TILE>
-static void launch_walk_t(const DeviceDfa &d, const PlainPlan &p, const uint8_t *text, uint8_t *ws,
-                          hipStream_t stream) {
+template <bool ALIGNED, uint32_t TILE, int MODE>
+static void launch_walk_t(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, hipStream_t stream) {
     if (d.layout == PAREM_LAYOUT_KGRAM_LDS) {
         switch (d.kg.bits) {
-            case 1: launch_kgram_b<1, ALIGNED, TILE>(d, p, text, ws, stream); break;
-            case 2: launch_kgram_b<2, ALIGNED, TILE>(d, p, text, ws, stream); break;
-            default: launch_kgram_b<3, ALIGNED, TILE>(d, p, text, ws, stream); break;
+            case 1: launch_kgram_b<1, ALIGNED, TILE, MODE>(d, p, a, stream); break;
+            case 2: launch_kgram_b<2, ALIGNED, TILE, MODE>(d, p, a, stream); break;
+            default: launch_kgram_b<3, ALIGNED, TILE, MODE>(d, p, a, stream); break;
         }
     } else if (d.layout == PAREM_LAYOUT_BYTE_LDS) {
-        launch_walk_byte<uint8_t, kByteLdsRow, true, ALIGNED, TILE>(d, p, text, ws, stream);
+        launch_walk_byte<uint8_t, kByteLdsRow, true, ALIGNED, TILE, MODE>(d, p, a, stream);
     } else {
-        launch_walk_byte<uint16_t, 256, false, ALIGNED, TILE>(d, p, text, ws, stream);
+        launch_walk_byte<uint16_t, 256, false, ALIGNED, TILE, MODE>(d, p, a, stream);
     }
 }
 
-static void launch_walk(const DeviceDfa &d, const PlainPlan &p, const uint8_t *text, uint8_t *ws,
-                        hipStream_t stream, bool aligned) {
-    if (!aligned) launch_walk_t<false, 64>(d, p, text, ws, stream);
-    else if (p.tile == 128) launch_walk_t<true, 128>(d, p, text, ws, stream);
-    else launch_walk_t<true, 64>(d, p, text, ws, stream);
+template <int MODE>
+static void launch_walk(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, hipStream_t stream,
+                        bool aligned) {
+    if (!aligned) launch_walk_t<false, 64, MODE>(d, p, a, stream);
+    else if (p.tile == 128 || MODE == WALK_REDO) launch_walk_t<true, 128, MODE>(d, p, a, stream);
+    else launch_walk_t<true, 64, MODE>(d, p, a, stream);
 }
 
-parem_status launch_plain(const DeviceDfa &d, const PlainPlan &p, const uint8_t *d_text, void *d_ws,
-                          hipStream_t stream, parem_result *d_out, hipEvent_t ev_begin, hipEvent_t ev_end) {
-    if (p.n == 0) {
-        hipLaunchKernelGGL(k_empty_result, dim3(1), dim3(64), 0, stream, d.start, d.d_final, d_out);
-        return hipGetLastError() == hipSuccess ? PAREM_OK : PAREM_EDEVICE;
-    }
-    uint8_t *ws = reinterpret_cast<uint8_t *>(d_ws);
-    const bool aligned = (reinterpret_cast<uintptr_t>(d_text) & 15u) == 0;
-    if (ev_begin && hipEventRecord(ev_begin, stream) != hipSuccess) return PAREM_EDEVICE;
-    launch_walk(d, p, d_text, ws, stream, aligned);
-    if (hipGetLastError() != hipSuccess) return PAREM_EDEVICE;
-    if (ev_end && hipEventRecord(ev_end, stream) != hipSuccess) return PAREM_EDEVICE;
-
+static ComposeArgs compose_args(const DeviceDfa &d, const PlainPlan &p) {
     ComposeArgs a;
     a.loff = d.d_loff;
     a.llist = d.d_llist;
@@ -1001,6 +1288,24 @@ parem_status launch_plain(const DeviceDfa &d, const PlainPlan &p, const uint8_t 
     a.P = p.P;
     a.final_flag = d.d_final;
     a.chunks = p.chunks;
+    return a;
+}
+
+static SegOut seg_out(const PlainPlan &p, uint8_t *ws, size_t k) {
+    const PlainPlan::Seg &g = p.seg[k];
+    SegOut o;
+    o.end = reinterpret_cast<uint32_t *>(ws + g.end);
+    o.cnt = reinterpret_cast<uint64_t *>(ws + g.cnt);
+    o.cls = reinterpret_cast<uint32_t *>(ws + g.cls);
+    o.runs = reinterpret_cast<uint64_t *>(ws + g.runs);
+    o.lead = reinterpret_cast<uint32_t *>(ws + g.lead);
+    return o;
+}
+
+// the composition levels after the walk; the last writes *d_out
+static parem_status launch_compose(const DeviceDfa &d, const PlainPlan &p, uint8_t *ws, hipStream_t stream,
+                                   parem_result *d_out) {
+    const ComposeArgs a = compose_args(d, p);
     const size_t lds = compose_lds(p.P, p.RM, d.inv_lds);
     if (lds > 64 * 1024) {
         if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_compose_chunks),
@@ -1009,36 +1314,165 @@ parem_status launch_plain(const DeviceDfa &d, const PlainPlan &p, const uint8_t 
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
             return PAREM_EDEVICE;
     }
-    const uint32_t *map = reinterpret_cast<const uint32_t *>(ws + p.off_cend);
-    const uint16_t *mcl = reinterpret_cast<const uint16_t *>(ws + p.off_ccls);
-    uint64_t nin = (p.chunks + p.P - 1) / p.P;
-    {
-        uint32_t *oe = reinterpret_cast<uint32_t *>(ws + p.off_a_end);
-        uint64_t *oc = reinterpret_cast<uint64_t *>(ws + p.off_a_cnt);
-        uint32_t *ol = reinterpret_cast<uint32_t *>(ws + p.off_a_cls);
-        uint64_t *orr = reinterpret_cast<uint64_t *>(ws + p.off_a_runs);
-        hipLaunchKernelGGL(k_compose_chunks, dim3((uint32_t)nin), dim3(kComposeThreads), lds, stream, map, mcl, a,
-                           oe, oc, ol, orr, nin == 1 ? d_out : nullptr);
-        if (hipGetLastError() != hipSuccess) return PAREM_EDEVICE;
-    }
-    bool in_a = true;
-    while (nin > 1) {
-        const uint64_t nout = (nin + p.P - 1) / p.P;
-        const uint32_t *ie = reinterpret_cast<const uint32_t *>(ws + (in_a ? p.off_a_end : p.off_b_end));
-        const uint64_t *ic = reinterpret_cast<const uint64_t *>(ws + (in_a ? p.off_a_cnt : p.off_b_cnt));
-        const uint32_t *il = reinterpret_cast<const uint32_t *>(ws + (in_a ? p.off_a_cls : p.off_b_cls));
-        const uint64_t *ir = reinterpret_cast<const uint64_t *>(ws + (in_a ? p.off_a_runs : p.off_b_runs));
-        uint32_t *oe = reinterpret_cast<uint32_t *>(ws + (in_a ? p.off_b_end : p.off_a_end));
-        uint64_t *oc = reinterpret_cast<uint64_t *>(ws + (in_a ? p.off_b_cnt : p.off_a_cnt));
-        uint32_t *ol = reinterpret_cast<uint32_t *>(ws + (in_a ? p.off_b_cls : p.off_a_cls));
-        uint64_t *orr = reinterpret_cast<uint64_t *>(ws + (in_a ? p.off_b_runs : p.off_a_runs));
-        hipLaunchKernelGGL(k_compose_segs, dim3((uint32_t)nout), dim3(kComposeThreads), lds, stream, ie, ic, il, ir,
-                           nin, a, oe, oc, ol, orr, nout == 1 ? d_out : nullptr);
+    const uint32_t *map = reinterpret_cast<const uint32_t *>(ws + p.off_map);
+    const uint16_t *mcl = reinterpret_cast<const uint16_t *>(ws + p.off_mcls);
+    const uint16_t *mld = reinterpret_cast<const uint16_t *>(ws + p.off_mlead);
+    uint64_t nin = p.levels[0];
+    hipLaunchKernelGGL(k_compose_chunks, dim3((uint32_t)nin), dim3(kComposeThreads), lds, stream, map, mcl, mld, a,
+                       seg_out(p, ws, 0), nin == 1 ? d_out : nullptr);
+    if (hipGetLastError() != hipSuccess) return PAREM_EDEVICE;
+    for (size_t l = 1; l < p.levels.size(); ++l) {
+        const size_t src = p.keep ? l - 1 : (l - 1) % 2, dst = p.keep ? l : l % 2;
+        const SegOut in = seg_out(p, ws, src);
+        const uint64_t nout = p.levels[l];
+        hipLaunchKernelGGL(k_compose_segs, dim3((uint32_t)nout), dim3(kComposeThreads), lds, stream, in.end, in.cnt,
+                           in.cls, in.runs, in.lead, nin, a, seg_out(p, ws, dst), nout == 1 ? d_out : nullptr);
         if (hipGetLastError() != hipSuccess) return PAREM_EDEVICE;
         nin = nout;
-        in_a = !in_a;
     }
     return PAREM_OK;
+}
+
+parem_status launch_plain(const DeviceDfa &d, const PlainPlan &p, const uint8_t *d_text, void *d_ws,
+                          hipStream_t stream, parem_result *d_out, hipEvent_t ev_begin, hipEvent_t ev_end) {
+    if (p.n == 0) {
+        hipLaunchKernelGGL(k_empty_result, dim3(1), dim3(64), 0, stream, d.start, d.d_final, d_out);
+        return hipGetLastError() == hipSuccess ? PAREM_OK : PAREM_EDEVICE;
+    }
+    uint8_t *ws = reinterpret_cast<uint8_t *>(d_ws);
+    const bool aligned = (reinterpret_cast<uintptr_t>(d_text) & 15u) == 0;
+    if (ev_begin && hipEventRecord(ev_begin, stream) != hipSuccess) return PAREM_EDEVICE;
+    const WalkArgs a = walk_args(d, p, d_text, ws);
+    launch_walk<WALK_ALL>(d, p, a, stream, aligned);
+    if (hipGetLastError() != hipSuccess) return PAREM_EDEVICE;
+    if (ev_end && hipEventRecord(ev_end, stream) != hipSuccess) return PAREM_EDEVICE;
+    return launch_compose(d, p, ws, stream, d_out);
+}
+
+// ---- boundary states ----
+
+parem_status plan_boundary(const DeviceDfa &d, uint64_t len, uint32_t L, PlainPlan *p) {
+    parem_status st = plan_common(d, len, L, true, p);
+    if (st != PAREM_OK) return st;
+    // entry arrays per level (level 0 is the caller's output)
+    uint64_t off = p->bytes;
+    p->entries.clear();
+    for (size_t l = 0; l < p->levels.size(); ++l) {
+        p->entries.push_back(off);
+        off = align256(off + p->levels[l] * 4);
+    }
+    p->off_dummy = off;
+    off = align256(off + sizeof(parem_result) + 16);
+    p->bytes = off;
+    return PAREM_OK;
+}
+
+parem_status launch_boundary(const DeviceDfa &d, const PlainPlan &p, const uint8_t *d_text, uint32_t *d_states,
+                             void *d_ws, hipStream_t stream) {
+    if (p.n == 0) return PAREM_OK;
+    if (!d.d_inv) return PAREM_EUNSUPPORTED;
+    uint8_t *ws = reinterpret_cast<uint8_t *>(d_ws);
+    const bool aligned = (reinterpret_cast<uintptr_t>(d_text) & 15u) == 0;
+    const WalkArgs a = walk_args(d, p, d_text, ws);
+    launch_walk<WALK_ALL>(d, p, a, stream, aligned);
+    parem_status st = launch_compose(d, p, ws, stream, reinterpret_cast<parem_result *>(ws + p.off_dummy));
+    if (st != PAREM_OK) return st;
+    // down-sweep: the top map is entered in q0
+    const size_t top = p.levels.size() - 1;
+    uint32_t *top_entry = reinterpret_cast<uint32_t *>(ws + p.entries[top]);
+    if (hipMemcpyAsync(top_entry, &d.start, 4, hipMemcpyHostToDevice, stream) != hipSuccess) return PAREM_EDEVICE;
+    for (size_t l = top; l-- > 0;) {
+        const SegOut s = seg_out(p, ws, l);
+        const uint64_t nmaps = p.levels[l];
+        hipLaunchKernelGGL(k_entries<false>, dim3((uint32_t)((nmaps + 255) / 256)), dim3(256), 0, stream, nmaps, p.P,
+                           reinterpret_cast<const uint32_t *>(ws + p.entries[l + 1]), s.end, s.cls, s.lead, nullptr,
+                           nullptr, nullptr, d.d_inv, d.Q + 1, p.RM, d.sent,
+                           reinterpret_cast<uint32_t *>(ws + p.entries[l]));
+    }
+    const uint32_t g = (uint32_t)((p.chunks + 255) / 256);
+    hipLaunchKernelGGL(k_entries<true>, dim3(g), dim3(256), 0, stream, p.chunks, p.P,
+                       reinterpret_cast<const uint32_t *>(ws + p.entries[0]), nullptr, nullptr, nullptr, a.map,
+                       a.map_cls, a.map_lead, d.d_inv, d.Q + 1, p.RM, d.sent, d_states);
+    uint32_t *first_bad = reinterpret_cast<uint32_t *>(ws + p.off_dummy + sizeof(parem_result));
+    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(64), 0, stream, first_bad, 0xffffffffu);
+    hipLaunchKernelGGL(k_first_bad, dim3(g), dim3(256), 0, stream, a.map_lead, p.chunks, d.sent, first_bad);
+    hipLaunchKernelGGL(k_after_bad, dim3(g), dim3(256), 0, stream, d_states, p.chunks, first_bad);
+    return hipGetLastError() == hipSuccess ? PAREM_OK : PAREM_EDEVICE;
+}
+
+// ---- learned speculation ----
+
+parem_status plan_learned(const DeviceDfa &d, const Proposal &pr, uint64_t len, uint32_t m, PlainPlan *p) {
+    parem_status st = plan_common(d, len, d.opt.chunk_len, false, p);
+    if (st != PAREM_OK) return st;
+    uint64_t off = p->bytes;
+    const uint64_t ch = std::max<uint64_t>(p->chunks, 1);
+    p->off_sel = off;
+    off = align256(off + ch * m * 2);
+    p->off_nsel = off;
+    off = align256(off + ch);
+    p->off_redo = off;
+    off = align256(off + ch);
+    p->off_done = off;
+    off = align256(off + ch);
+    p->off_flags = off;
+    off = align256(off + 64);
+    p->off_mlp = off;
+    off = align256(off + proposal_infer_bytes(pr, ch));
+    p->bytes = off;
+    p->m = m;
+    return PAREM_OK;
+}
+
+parem_status launch_learned(const DeviceDfa &d, const Proposal &pr, const PlainPlan &p, const uint8_t *d_text,
+                            void *d_ws, hipStream_t stream, parem_result *d_out, hipEvent_t ev_begin,
+                            hipEvent_t ev_end) {
+    if (p.n == 0) {
+        hipLaunchKernelGGL(k_empty_result, dim3(1), dim3(64), 0, stream, d.start, d.d_final, d_out);
+        return hipGetLastError() == hipSuccess ? PAREM_OK : PAREM_EDEVICE;
+    }
+    if (!d.d_inv) return PAREM_EUNSUPPORTED;
+    uint8_t *ws = reinterpret_cast<uint8_t *>(d_ws);
+    const bool aligned = (reinterpret_cast<uintptr_t>(d_text) & 15u) == 0;
+    uint16_t *sel = reinterpret_cast<uint16_t *>(ws + p.off_sel);
+    uint8_t *nsel = ws + p.off_nsel;
+    uint8_t *redo = ws + p.off_redo;
+    uint8_t *done = ws + p.off_done;
+    uint32_t *flags = reinterpret_cast<uint32_t *>(ws + p.off_flags);
+    const uint32_t C = (uint32_t)p.chunks;
+    const uint32_t g = (C + 255) / 256;
+    if (ev_begin && hipEventRecord(ev_begin, stream) != hipSuccess) return PAREM_EDEVICE;
+    // 1. proposal: top-m of each chunk's speculated set
+    parem_status st = proposal_select(pr, d_text, p.L, C, p.m, p.m, ws + p.off_mlp, stream, sel, nsel);
+    if (st != PAREM_OK) return st;
+    // 2. walk the selected states
+    WalkArgs a = walk_args(d, p, d_text, ws);
+    a.sel = sel;
+    a.nsel = nsel;
+    a.sel_stride = p.m;
+    launch_walk<WALK_SELECTED>(d, p, a, stream, aligned);
+    if (hipGetLastError() != hipSuccess) return PAREM_EDEVICE;
+    // 3. verify coverage, walk uncovered chunks again from their whole set
+    hipLaunchKernelGGL(k_clear_u8, dim3(g), dim3(256), 0, stream, done, (uint64_t)C);
+    hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(64), 0, stream, flags, 8u);
+    WalkArgs r = walk_args(d, p, d_text, ws);
+    r.redo = redo;
+    for (int it = 0; it <= kCoverRounds; ++it) {
+        const uint32_t escalate = it == kCoverRounds ? 1u : 0u;
+        hipLaunchKernelGGL(k_cover, dim3(g), dim3(256), 0, stream, a.map, a.map_cls, a.map_lead, (uint64_t)C, d.d_loff,
+                           d.d_inv, d.Q + 1, d.sent, redo, done, flags, escalate);
+        if (escalate) hipLaunchKernelGGL(k_escalate, dim3(g), dim3(256), 0, stream, (uint64_t)C, redo, done, flags);
+        launch_walk<WALK_REDO>(d, p, r, stream, aligned);
+    }
+    if (ev_end && hipEventRecord(ev_end, stream) != hipSuccess) return PAREM_EDEVICE;
+    // 4. compose, then the learned statistics
+    st = launch_compose(d, p, ws, stream, d_out);
+    if (st != PAREM_OK) return st;
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(flags + 4);
+    hipLaunchKernelGGL(k_learned_stats, dim3(g), dim3(256), 0, stream, nsel, done, a.map_cls, d.d_loff,
+                       (uint64_t)C, acc);  // 256 threads: four waves per partial
+    hipLaunchKernelGGL(k_learned_total, dim3(1), dim3(64), 0, stream, acc, d_out);
+    return hipGetLastError() == hipSuccess ? PAREM_OK : PAREM_EDEVICE;
 }
 
 }  // namespace parem

@@ -347,3 +347,32 @@ def random_case(rng: np.random.Generator, max_states: int = 64, max_alpha: int =
     n = int(rng.integers(0, max_len + 1))
     text = uniform_text(rng, alphabet, n)
     return dfa, text
+
+
+# ---------------------------------------------------------------------------
+# initial weights of the learned proposal (an input like any other)
+# ---------------------------------------------------------------------------
+
+MLP_WINDOW, MLP_EMB, MLP_HID = 32, 16, 256
+
+
+def mlp_param_shapes(states: int):
+    """Flat parameter layout: emb [256,16], W1 [256,512], b1 [256],
+    W2 [256,256], b2 [256], W3 [states,256], b3 [states]."""
+    return [("emb", (256, MLP_EMB)), ("W1", (MLP_HID, MLP_WINDOW * MLP_EMB)), ("b1", (MLP_HID,)),
+            ("W2", (MLP_HID, MLP_HID)), ("b2", (MLP_HID,)), ("W3", (states, MLP_HID)), ("b3", (states,))]
+
+
+def mlp_init_params(states: int, seed: int = 11) -> np.ndarray:
+    """Seeded initial weights (float32): N(0, 1/fan_in) matrices, N(0, 1)
+    embedding, zero biases."""
+    rng = np.random.default_rng([seed, 0x3117])
+    parts = []
+    for name, shape in mlp_param_shapes(states):
+        if name.startswith("b"):
+            parts.append(np.zeros(shape))
+        elif name == "emb":
+            parts.append(rng.standard_normal(shape))
+        else:
+            parts.append(rng.standard_normal(shape) / math.sqrt(shape[1]))
+    return np.concatenate([x.reshape(-1) for x in parts]).astype(np.float32)
