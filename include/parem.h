@@ -34,6 +34,7 @@ extern "C" {
 
 typedef struct parem_dfa *parem_handle;
 typedef struct parem_proposal_s *parem_proposal;
+typedef struct parem_batch_s *parem_batch;
 
 typedef enum {
     PAREM_OK = 0,
@@ -228,6 +229,75 @@ parem_status parem_learned_workspace_size(parem_handle h, parem_proposal p, uint
 parem_status parem_match_learned_async(parem_handle h, parem_proposal p, uint32_t m, const uint8_t *d_text,
                                        uint64_t len, void *d_workspace, uint64_t workspace_bytes, void *stream,
                                        parem_result *d_out, void *ev_walk_begin, void *ev_walk_end);
+
+/*
+ * Batched matching of many (DFA, text) pairs (each pair is Algorithm 1 on its
+ * own text, as above). The plan fixes, per pair, the handle, the text length
+ * and the options (chunk_len, group, tile, no_merge; the layout is the
+ * handle's); every run then matches a new set of texts of those lengths.
+ *
+ * Execution: the chunks of all pairs are cut into work items of 256 chunks;
+ * one persistent walk kernel per (table layout, group, tile) combination
+ * takes items from a queue in descending cost order, staging each pair's
+ * table in LDS when its layout does; then one launch per composition level
+ * joins the chunk maps of every pair still holding more than one map. The
+ * launches are enqueued without host synchronisation, so a run can be
+ * captured in a HIP graph: with use_graph = 1 the first run on a plan
+ * captures and instantiates the graph and every run replays it.
+ *
+ * parem_batch_create   dfas[n], lens[n] (bytes of each pair's text), opts
+ *                      (n entries, or NULL for each handle's own options).
+ *                      Allocates the plan's device memory (workspace for
+ *                      every pair). Pairs with lens[i] == 0 are allowed.
+ *                      The handles must outlive the plan.
+ * parem_batch_run      d_texts: host array of n device pointers, each
+ *                      16-byte aligned (PAREM_EINVAL otherwise), holding
+ *                      lens[i] bytes. d_out: device array of n results.
+ *                      Asynchronous on `stream`; the texts must stay valid
+ *                      until the stream reaches the end of the run. Calls on
+ *                      one plan must not overlap (they share its workspace).
+ *                      A text byte outside its pair's alphabet gives that
+ *                      pair final_state 0xffffffff, accept 0, count 0 (the
+ *                      other pairs are unaffected).
+ * parem_batch_describe plan statistics (any pointer may be NULL).
+ * parem_match_batch    create + run (graph) + synchronize + free; on a byte
+ *                      outside an alphabet returns PAREM_ESYMBOL after
+ *                      writing every result.
+ */
+typedef struct {
+    uint32_t pairs;
+    uint32_t walk_launches;  /* persistent walk kernels (layout x group x tile)   */
+    uint64_t walk_items;     /* work items of 256 chunks                          */
+    uint32_t levels;         /* composition launches                              */
+    uint32_t graph_nodes;    /* nodes of the captured graph (0 before capture)    */
+    uint64_t chunks;         /* chunks over all pairs                             */
+    uint64_t text_bytes;     /* bytes over all pairs                              */
+    uint64_t workspace_bytes;
+} parem_batch_info;
+
+parem_status parem_batch_create(const parem_handle *dfas, const uint64_t *lens, uint32_t n,
+                                const parem_options *opts, parem_batch *out);
+parem_status parem_batch_run(parem_batch b, const uint8_t *const *d_texts, void *stream, parem_result *d_out,
+                             int use_graph);
+parem_status parem_batch_describe(parem_batch b, parem_batch_info *info);
+void parem_batch_free(parem_batch b);
+parem_status parem_match_batch(const parem_handle *dfas, const uint8_t *const *d_texts, const uint64_t *lens,
+                               uint32_t n, void *stream, parem_result *d_out);
+
+/*
+ * Autotuner measurement: for each candidate option set (chunk_len, group,
+ * tile, no_merge; chunk_len 0 = the batch default), plans a batch of up to
+ * `copies` pairs that all match d_sample (sample_len bytes, device, 16-byte
+ * aligned) with handle h (fewer copies when their workspace would pass
+ * 4 GiB), times `reps` graph replays after one warm-up run, and writes the
+ * milliseconds per copy (replay time / copies) to ms_out[ncand] (host).
+ * *best receives the index of the fastest candidate. Candidates that the
+ * handle cannot run (e.g. group 2, a chunk length above the maximum) get
+ * ms_out = -1; PAREM_EUNSUPPORTED when none can.
+ */
+parem_status parem_tune(parem_handle h, const uint8_t *d_sample, uint64_t sample_len, uint32_t copies,
+                        const parem_options *cands, uint32_t ncand, uint32_t reps, void *stream, float *ms_out,
+                        uint32_t *best);
 
 #ifdef __cplusplus
 }

@@ -57,6 +57,12 @@ class Result(ctypes.Structure):
 assert ctypes.sizeof(Result) == RESULT_BYTES
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("pairs", ctypes.c_uint32), ("walk_launches", ctypes.c_uint32), ("walk_items", ctypes.c_uint64),
+                ("levels", ctypes.c_uint32), ("graph_nodes", ctypes.c_uint32), ("chunks", ctypes.c_uint64),
+                ("text_bytes", ctypes.c_uint64), ("workspace_bytes", ctypes.c_uint64)]
+
+
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1412_1741_amd.build`")
@@ -102,6 +108,18 @@ def _load() -> ctypes.CDLL:
     lib.parem_learned_workspace_size.argtypes = [vp, vp, u64, ctypes.POINTER(u64)]
     lib.parem_match_learned_async.restype = i32
     lib.parem_match_learned_async.argtypes = [vp, vp, u32, vp, u64, vp, u64, vp, vp, vp, vp]
+    lib.parem_batch_create.restype = i32
+    lib.parem_batch_create.argtypes = [vp, vp, u32, vp, ctypes.POINTER(vp)]
+    lib.parem_batch_run.restype = i32
+    lib.parem_batch_run.argtypes = [vp, vp, vp, vp, i32]
+    lib.parem_batch_describe.restype = i32
+    lib.parem_batch_describe.argtypes = [vp, ctypes.POINTER(BatchInfo)]
+    lib.parem_batch_free.restype = None
+    lib.parem_batch_free.argtypes = [vp]
+    lib.parem_match_batch.restype = i32
+    lib.parem_match_batch.argtypes = [vp, vp, vp, u32, vp, vp]
+    lib.parem_tune.restype = i32
+    lib.parem_tune.argtypes = [vp, vp, u64, u32, vp, u32, u32, vp, vp, ctypes.POINTER(u32)]
     return lib
 
 
@@ -113,7 +131,8 @@ EXPORTED = ["parem_compile", "parem_free", "parem_strerror", "parem_describe", "
             "parem_boundary_states", "parem_proposal_create", "parem_proposal_free", "parem_proposal_params",
             "parem_proposal_train_step", "parem_proposal_logits", "parem_proposal_select_size",
             "parem_proposal_select", "parem_learned_workspace_size",
-            "parem_match_learned_async"]
+            "parem_match_learned_async", "parem_batch_create", "parem_batch_run", "parem_batch_describe",
+            "parem_batch_free", "parem_match_batch", "parem_tune"]
 
 
 def lib() -> ctypes.CDLL:
@@ -265,6 +284,68 @@ def parem_match_learned_async(handle: int, proposal: int, m: int, d_text_ptr: in
                                            d_out_ptr, ev_begin or None, ev_end or None), "parem_match_learned_async")
 
 
+def _options_array(opts):
+    if opts is None:
+        return None
+    arr = (Options * len(opts))()
+    for i, o in enumerate(opts):
+        arr[i] = o if isinstance(o, Options) else Options(**o)
+    return arr
+
+
+def _u64_array(values):
+    return np.ascontiguousarray(np.asarray(values, dtype=np.uint64).reshape(-1))
+
+
+def parem_batch_create(handles, lens, opts=None) -> int:
+    """Plan a batch; ``opts`` is None or one Options (or dict of its fields) per pair."""
+    n = len(handles)
+    hs = (ctypes.c_void_p * max(n, 1))(*handles)
+    ln = _u64_array(lens)
+    if ln.size != n:
+        raise ValueError("one length per pair")
+    oa = _options_array(opts)
+    b = ctypes.c_void_p()
+    _check(lib().parem_batch_create(hs, ln.ctypes.data, n, oa, ctypes.byref(b)), "parem_batch_create")
+    return b.value
+
+
+def parem_batch_run(batch: int, d_text_ptrs, stream_ptr: int, d_out_ptr: int, use_graph: bool = True) -> None:
+    ptrs = _u64_array(d_text_ptrs)
+    _check(lib().parem_batch_run(batch, ptrs.ctypes.data, stream_ptr or None, d_out_ptr, 1 if use_graph else 0),
+           "parem_batch_run")
+
+
+def parem_batch_describe(batch: int) -> dict:
+    info = BatchInfo()
+    _check(lib().parem_batch_describe(batch, ctypes.byref(info)), "parem_batch_describe")
+    return {f: int(getattr(info, f)) for f, _ in BatchInfo._fields_}
+
+
+def parem_batch_free(batch: int) -> None:
+    lib().parem_batch_free(batch)
+
+
+def parem_match_batch(handles, d_text_ptrs, lens, stream_ptr: int, d_out_ptr: int) -> None:
+    n = len(handles)
+    hs = (ctypes.c_void_p * max(n, 1))(*handles)
+    ptrs = _u64_array(d_text_ptrs)
+    ln = _u64_array(lens)
+    _check(lib().parem_match_batch(hs, ptrs.ctypes.data, ln.ctypes.data, n, stream_ptr or None, d_out_ptr),
+           "parem_match_batch")
+
+
+def parem_tune(handle: int, d_sample_ptr: int, sample_len: int, copies: int, cands, reps: int,
+               stream_ptr: int):
+    """Times candidate options (Options or dicts); returns (ms per copy list, best index)."""
+    oa = _options_array(cands)
+    ms = np.zeros(len(cands), dtype=np.float32)
+    best = ctypes.c_uint32()
+    _check(lib().parem_tune(handle, d_sample_ptr, int(sample_len), int(copies), oa, len(cands), int(reps),
+                            stream_ptr or None, ms.ctypes.data, ctypes.byref(best)), "parem_tune")
+    return [float(x) for x in ms], int(best.value)
+
+
 def parem_match(handle: int, text_ptr: int, length: int) -> Result:
     """Synchronous match on a host or device address."""
     r = Result()
@@ -384,6 +465,52 @@ class Matcher:
         arr = np.ascontiguousarray(np.frombuffer(text, dtype=np.uint8) if isinstance(text, (bytes, bytearray))
                                    else text, dtype=np.uint8).reshape(-1)
         return MatchResult.from_struct(parem_match(self.handle, arr.ctypes.data, arr.size))
+
+
+class Batch:
+    """A planned batch of (Matcher, text length) pairs; ``run`` matches one
+    set of uint8 device tensors of those lengths (16-byte aligned)."""
+
+    def __init__(self, matchers, lens, opts=None):
+        self.handles = [m.handle for m in matchers]
+        self._matchers = list(matchers)  # the handles must outlive the plan
+        self.lens = [int(x) for x in lens]
+        self.handle = parem_batch_create(self.handles, self.lens, opts)
+
+    def close(self):
+        if self.handle:
+            parem_batch_free(self.handle)
+            self.handle = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def describe(self) -> dict:
+        return parem_batch_describe(self.handle)
+
+    def run_async(self, texts, out=None, use_graph: bool = True, stream=None):
+        import torch
+        if len(texts) != len(self.lens):
+            raise ValueError("one text per pair")
+        for t, n in zip(texts, self.lens):
+            assert t.is_cuda and t.dtype == torch.uint8 and t.is_contiguous() and t.numel() == n
+        if out is None:
+            out = torch.empty(max(len(texts), 1) * RESULT_BYTES, dtype=torch.uint8, device="cuda")
+        s = stream if stream is not None else torch.cuda.current_stream()
+        parem_batch_run(self.handle, [t.data_ptr() for t in texts], s.cuda_stream, out.data_ptr(), use_graph)
+        return out
+
+    @staticmethod
+    def results(out, n: int):
+        raw = out[: n * RESULT_BYTES].cpu().numpy().tobytes()
+        return [MatchResult.from_bytes(raw[i * RESULT_BYTES:(i + 1) * RESULT_BYTES]) for i in range(n)]
+
+    def run(self, texts, use_graph: bool = True):
+        out = self.run_async(texts, use_graph=use_graph)
+        return self.results(out, len(texts))
 
 
 # ---------------------------------------------------------------------------

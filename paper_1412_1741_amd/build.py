@@ -1,25 +1,40 @@
 """Build ``libparem.so`` (HIP for gfx950) in-tree with hipcc.
 
-Run as ``python -m paper_1412_1741_amd.build``. Every call compiles.
+Run as ``python -m paper_1412_1741_amd.build``. Every call compiles: each
+source becomes an object under ``_build/`` (in parallel), then one link.
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
 import os
 import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libparem.so")
 
-SOURCES = ["parem_api.cpp", "parem_walk.hip", "parem_mlp.hip"]
+SOURCES = [
+    "parem_api.cpp",
+    "parem_walk.hip",
+    "parem_walk_kgram_all.hip",
+    "parem_walk_kgram_sel.hip",
+    "parem_walk_kgram_redo.hip",
+    "parem_walk_byte_all.hip",
+    "parem_walk_byte_sel.hip",
+    "parem_walk_byte_redo.hip",
+    "parem_mlp.hip",
+    "parem_batch.hip",
+    "parem_batch_t64.hip",
+    "parem_batch_t128.hip",
+]
 
 HIP_FLAGS = [
     "--offload-arch=gfx950",
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     "-Wall",
     "-Wno-unused-function",
     # packed FP32 instructions are kept out of every HIP build
@@ -34,16 +49,40 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIP_FLAGS, "-I", os.path.join(HERE, "..", "include"), "-o", tmp, *srcs]
+def _jobs() -> int:
+    for var in ("MAX_JOBS", "CMAKE_BUILD_PARALLEL_LEVEL"):
+        v = os.environ.get(var)
+        if v and v.isdigit() and int(v) > 0:
+            return min(int(v), 16)
+    return max(1, min(os.cpu_count() or 1, 16))
+
+
+def _compile(src: str, verbose: bool) -> str:
+    obj = os.path.join(OBJ, os.path.basename(src) + ".o")
+    cmd = [hipcc(), *HIP_FLAGS, "-I", os.path.join(HERE, "..", "include"), "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libparem.so")
+        raise RuntimeError(f"hipcc failed compiling {os.path.basename(src)}")
+    return obj
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(OBJ, exist_ok=True)
+    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    with cf.ThreadPoolExecutor(max_workers=_jobs()) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
+    tmp = LIB + ".tmp"
+    # -z defs: every symbol the units use must be defined by them or a linked library
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,-z,defs", "-o", tmp, *objs]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("hipcc failed linking libparem.so")
     os.replace(tmp, LIB)
     return LIB
 

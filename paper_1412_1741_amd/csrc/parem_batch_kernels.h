@@ -1,0 +1,104 @@
+// Batched walk kernel (persistent, work-item queue) and the structures the
+// batch kernels read. Its instantiations are split by staged tile size over
+// two translation units that compile in parallel.
+#pragma once
+
+#include "parem_device.h"
+
+namespace parem {
+
+// one pair as the batch kernels read it
+struct BatchPair {
+    WalkArgs w;  // w.text is unused: a run's texts come from its pointer array
+    const void *table;
+    uint32_t table_bytes;
+    uint32_t start;
+    KgParams kg;
+    ComposeArgs ca;
+    SegOut seg[2];  // ping-pong segment buffers
+    parem_result *out;
+};
+
+struct WalkItem {
+    uint32_t pair;
+    uint32_t blk;  // chunks blk * 256 ... of the pair
+};
+
+struct ComposeItem {
+    uint32_t pair;
+    uint32_t last;  // 1: the pair's last level (writes its result)
+    uint64_t seg;
+    uint64_t nin;   // maps of the pair at the previous level
+};
+
+// walk kernel variants: the table layout of the pairs they serve
+enum BatchKind : int { BK_BYTE_LDS = 0, BK_BYTE_GLOBAL = 1, BK_KGRAM1 = 2, BK_KGRAM2 = 3, BK_KGRAM3 = 4 };
+
+template <int G, uint32_t TILE, int KIND>
+__global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_batch_walk(
+    const BatchPair *__restrict__ pairs, const uint8_t *const *__restrict__ texts, const WalkItem *__restrict__ items,
+    uint32_t nitems, uint32_t *__restrict__ queue, uint32_t table_cap) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ uint32_t s_next;
+    uint32_t staged = 0xffffffffu;
+    for (;;) {
+        if (threadIdx.x == 0) s_next = atomicAdd(queue, 1u);
+        __syncthreads();
+        const uint32_t it = __builtin_amdgcn_readfirstlane(s_next);
+        // every lane has read s_next, and every wave has left the previous
+        // item (its table and staging area are free)
+        __syncthreads();
+        if (it >= nitems) break;
+        const uint32_t pi = __builtin_amdgcn_readfirstlane(items[it].pair);
+        const uint64_t c0 = (uint64_t)__builtin_amdgcn_readfirstlane(items[it].blk) * kWalkThreads;
+        const BatchPair &bp = pairs[pi];
+        WalkArgs a = bp.w;
+        a.text = texts[pi];
+        if constexpr (KIND != BK_BYTE_GLOBAL) {
+            if (pi != staged) {
+                stage_table(reinterpret_cast<uint4 *>(smem), reinterpret_cast<const uint4 *>(bp.table),
+                            bp.table_bytes / 16u);
+                staged = pi;
+            }
+        }
+        if constexpr (KIND == BK_BYTE_LDS) {
+            ByteStep<uint8_t, kByteLdsRow> st{smem};
+            walk_chunk<G, ByteStep<uint8_t, kByteLdsRow>, true, TILE, WALK_ALL>(st, a, smem + table_cap, c0);
+        } else if constexpr (KIND == BK_BYTE_GLOBAL) {
+            ByteStep<uint16_t, 256> st{reinterpret_cast<const uint16_t *>(bp.table)};
+            walk_chunk<G, ByteStep<uint16_t, 256>, true, TILE, WALK_ALL>(st, a, smem, c0);
+        } else {
+            KgStep<KIND - 1> st{smem, bp.kg};
+            walk_chunk<G, KgStep<KIND - 1>, true, TILE, WALK_ALL>(st, a, smem + table_cap, c0);
+        }
+    }
+}
+
+using WalkKernel = void (*)(const BatchPair *, const uint8_t *const *, const WalkItem *, uint32_t, uint32_t *,
+                            uint32_t);
+
+template <int G, uint32_t TILE>
+WalkKernel walk_kernel_kind(int kind) {
+    switch (kind) {
+        case BK_BYTE_LDS: return k_batch_walk<G, TILE, BK_BYTE_LDS>;
+        case BK_BYTE_GLOBAL: return k_batch_walk<G, TILE, BK_BYTE_GLOBAL>;
+        case BK_KGRAM1: return k_batch_walk<G, TILE, BK_KGRAM1>;
+        case BK_KGRAM2: return k_batch_walk<G, TILE, BK_KGRAM2>;
+        default: return k_batch_walk<G, TILE, BK_KGRAM3>;
+    }
+}
+
+template <uint32_t TILE>
+WalkKernel walk_kernel_tile(uint32_t G, int kind) {
+    switch (G) {
+        case 4: return walk_kernel_kind<4, TILE>(kind);
+        case 8: return walk_kernel_kind<8, TILE>(kind);
+        default: return walk_kernel_kind<16, TILE>(kind);
+    }
+}
+
+// defined in the per-tile translation units
+WalkKernel batch_walk_kernel_64(uint32_t G, int kind);
+WalkKernel batch_walk_kernel_128(uint32_t G, int kind);
+
+}  // namespace parem

@@ -124,6 +124,8 @@ constexpr uint32_t kMaxChunk = 32768;  // chunk maps pack a count < 2^16 beside 
 
 constexpr int kCoverRounds = 3;         // coverage rounds before every incomplete chunk is walked again
 
+// chunking, map width, group, tile and workspace carving of one text under options o
+parem_status plan_chunks(const DeviceDfa &d, uint64_t len, const parem_options &o, bool keep, PlainPlan *p);
 parem_status plan_plain(const DeviceDfa &d, uint64_t len, PlainPlan *p);
 parem_status launch_plain(const DeviceDfa &d, const PlainPlan &p, const uint8_t *d_text,
                           void *d_ws, hipStream_t stream, parem_result *d_out,

@@ -1,0 +1,94 @@
+// Walk kernels of one text and their launchers. The instantiations are
+// spread over several translation units (one per table family and walk
+// mode) so that they compile in parallel; each includes this header and
+// instantiates launch_walk_family for its pair of template arguments.
+#pragma once
+
+#include "parem_device.h"
+
+namespace parem {
+
+// at least 4 waves per SIMD (at most 128 VGPRs) for groups up to 8 walks
+template <typename E, uint32_t ROW, int G, bool LDS_TABLE, bool ALIGNED, uint32_t TILE, int MODE>
+__global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_walk_byte(WalkArgs a, const E *__restrict__ g_table,
+                                                                              uint32_t table_bytes) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    ByteStep<E, ROW> st{g_table};
+    uint32_t tb = 0;
+    if constexpr (LDS_TABLE) {
+        stage_table(reinterpret_cast<uint4 *>(smem), reinterpret_cast<const uint4 *>(g_table), table_bytes / 16u);
+        st.T = reinterpret_cast<const E *>(smem);
+        tb = table_bytes;
+    }
+    walk_chunk<G, ByteStep<E, ROW>, ALIGNED, TILE, MODE>(st, a, smem + tb, (uint64_t)blockIdx.x * kWalkThreads);
+}
+
+template <int G, int B, bool ALIGNED, uint32_t TILE, int MODE>
+__global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_walk_kgram(WalkArgs a,
+                                                                               const uint8_t *__restrict__ g_table,
+                                                                               uint32_t table_bytes, KgParams kp) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    stage_table(reinterpret_cast<uint4 *>(smem), reinterpret_cast<const uint4 *>(g_table), table_bytes / 16u);
+    KgStep<B> st{smem, kp};
+    walk_chunk<G, KgStep<B>, ALIGNED, TILE, MODE>(st, a, smem + table_bytes, (uint64_t)blockIdx.x * kWalkThreads);
+}
+
+template <typename E, uint32_t ROW, bool LDS, bool ALIGNED, uint32_t TILE, int MODE>
+inline void launch_walk_byte(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, hipStream_t stream) {
+    const uint32_t grid = (uint32_t)((p.chunks + kWalkThreads - 1) / kWalkThreads);
+    const size_t lds = (LDS ? d.table_bytes : 0) + ((ALIGNED && MODE != WALK_REDO) ? Stage<TILE>::kBytes : 0);
+    const E *tab = reinterpret_cast<const E *>(d.d_table);
+#define PAREM_WALK(GG)                                                                                            \
+    hipLaunchKernelGGL((k_walk_byte<E, ROW, GG, LDS, ALIGNED, TILE, MODE>), dim3(grid), dim3(kWalkThreads), lds, \
+                       stream, a, tab, d.table_bytes)
+    switch (p.G) {
+        case 2: PAREM_WALK(2); break;
+        case 4: PAREM_WALK(4); break;
+        case 8: PAREM_WALK(8); break;
+        default: PAREM_WALK(16); break;
+    }
+#undef PAREM_WALK
+}
+
+template <int B, bool ALIGNED, uint32_t TILE, int MODE>
+inline void launch_kgram_b(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, hipStream_t stream) {
+    const uint32_t grid = (uint32_t)((p.chunks + kWalkThreads - 1) / kWalkThreads);
+    const size_t lds = d.table_bytes + ((ALIGNED && MODE != WALK_REDO) ? Stage<TILE>::kBytes : 0);
+    const uint8_t *tab = reinterpret_cast<const uint8_t *>(d.d_table);
+#define PAREM_KG(GG)                                                                                              \
+    hipLaunchKernelGGL((k_walk_kgram<GG, B, ALIGNED, TILE, MODE>), dim3(grid), dim3(kWalkThreads), lds, stream, a, \
+                       tab, d.table_bytes, d.kg)
+    switch (p.G) {
+        case 2: PAREM_KG(2); break;
+        case 4: PAREM_KG(4); break;
+        case 8: PAREM_KG(8); break;
+        default: PAREM_KG(16); break;
+    }
+#undef PAREM_KG
+}
+
+template <bool KGRAM, bool ALIGNED, uint32_t TILE, int MODE>
+inline void launch_family_t(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, hipStream_t stream) {
+    if constexpr (KGRAM) {
+        switch (d.kg.bits) {
+            case 1: launch_kgram_b<1, ALIGNED, TILE, MODE>(d, p, a, stream); break;
+            case 2: launch_kgram_b<2, ALIGNED, TILE, MODE>(d, p, a, stream); break;
+            default: launch_kgram_b<3, ALIGNED, TILE, MODE>(d, p, a, stream); break;
+        }
+    } else if (d.layout == PAREM_LAYOUT_BYTE_LDS) {
+        launch_walk_byte<uint8_t, kByteLdsRow, true, ALIGNED, TILE, MODE>(d, p, a, stream);
+    } else {
+        launch_walk_byte<uint16_t, 256, false, ALIGNED, TILE, MODE>(d, p, a, stream);
+    }
+}
+
+// KGRAM: the k-gram layout (B = 1..3), else the byte layouts (LDS / global)
+template <bool KGRAM, int MODE>
+void launch_walk_family(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, hipStream_t stream,
+                        bool aligned) {
+    if (!aligned) launch_family_t<KGRAM, false, 64, MODE>(d, p, a, stream);
+    else if (p.tile == 128 || MODE == WALK_REDO) launch_family_t<KGRAM, true, 128, MODE>(d, p, a, stream);
+    else launch_family_t<KGRAM, true, 64, MODE>(d, p, a, stream);
+}
+
+}  // namespace parem

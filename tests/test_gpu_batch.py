@@ -1,0 +1,216 @@
+"""GPU parity of the batched persistent launch against the CPU oracle.
+
+Every pair of a batch must give the sequential run's (final state, accept
+flag, count) bit-exactly, whatever the per-pair options (chunk length,
+lockstep group, staged tile, merging), with the run captured in a HIP graph
+or enqueued eagerly, and across graph replays with new texts.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from conftest import gpu_available
+
+pytestmark = pytest.mark.gpu
+
+if gpu_available():
+    import torch
+    import paper_1412_1741_amd as P
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def batch_chunk_len(n):
+    """The batch's automatic chunk length (about 256 chunks, 64 B .. 8 KiB)."""
+    L = 64
+    while L < 8192 and L * 256 < n:
+        L *= 2
+    return L
+
+
+def spec_runs(dfa, text, L):
+    n = text.size
+    if n == 0:
+        return 0
+    chunks = (n + L - 1) // L
+    col = np.full(256, -1, dtype=np.int64)
+    col[np.frombuffer(dfa.alphabet, dtype=np.uint8)] = np.arange(dfa.alphabet_size)
+    img = np.asarray([np.unique(dfa.table[:, j]).size for j in range(dfa.alphabet_size)], dtype=np.int64)
+    prev = text[np.arange(1, chunks, dtype=np.int64) * L - 1]
+    cols = col[prev]
+    sizes = np.where(cols >= 0, img[np.maximum(cols, 0)], 1)
+    return 1 + int(sizes.sum())
+
+
+def random_pairs(seed, count, max_states=600, max_len=300_000):
+    rng = np.random.default_rng(seed)
+    lens = [0, 1, 15, 16, 17, 63, 64, 65, 127, 129, 1000, 4097]
+    pairs = []
+    for i in range(count):
+        q = int(np.floor(np.exp(rng.uniform(0, np.log(max_states)))))
+        a = int(rng.choice([1, 2, 3, 4, 5, 8, 20, 256]))
+        alphabet = bytes(rng.choice(256, size=a, replace=False).astype(np.uint8))
+        if rng.random() < 0.5:
+            dfa = W.random_dense_dfa(rng, q, alphabet, num_accepting=int(rng.integers(0, q + 1)))
+        else:
+            acc = rng.choice(q, size=int(rng.integers(0, q + 1)), replace=False)
+            dfa = W.sparse_dfa(rng, q, alphabet, 1, 4, acc)
+        dfa.start = int(rng.integers(0, q))
+        n = lens[i] if i < len(lens) else int(np.exp(rng.uniform(0, np.log(max_len))))
+        pairs.append((dfa, W.uniform_text(rng, alphabet, n)))
+    return pairs
+
+
+def to_device(texts):
+    out = []
+    for t in texts:
+        d = torch.empty(t.size, dtype=torch.uint8, device="cuda")
+        if t.size:
+            d.copy_(torch.from_numpy(t))
+        out.append(d)
+    return out
+
+
+def check(pairs, got, name, opts=None):
+    for i, ((dfa, text), r) in enumerate(zip(pairs, got)):
+        want = oracle.walk_dfa(dfa, text)
+        assert (r.final_state, r.accept, r.count) == (want.final_state, want.accept, want.count), \
+            f"{name}: pair {i} Q={dfa.num_states} A={dfa.alphabet_size} n={text.size}"
+        L = (opts[i].get("chunk_len") if opts else 0) or batch_chunk_len(text.size)
+        assert r.chunks == ((text.size + L - 1) // L if text.size else 0), f"{name}: pair {i}"
+        assert r.spec_runs == spec_runs(dfa, text, L), f"{name}: pair {i}"
+        assert r.rerun_chunks == 0
+
+
+def matchers(pairs):
+    return [P.Matcher(d.table, d.alphabet, d.start, d.accepting) for d, _ in pairs]
+
+
+def test_batch_mixed_graph_and_eager():
+    pairs = random_pairs(101, 96)
+    say(f"[case] batch mixed: {len(pairs)} pairs, {sum(t.size for _, t in pairs)} bytes")
+    ms = matchers(pairs)
+    b = P.Batch(ms, [t.size for _, t in pairs])
+    info = b.describe()
+    say(f"[info] {info}")
+    assert info["pairs"] == len(pairs)
+    dev = to_device([t for _, t in pairs])
+    check(pairs, b.run(dev, use_graph=False), "eager")
+    check(pairs, b.run(dev, use_graph=True), "graph")
+    assert b.describe()["graph_nodes"] >= info["walk_launches"] + info["levels"]
+
+
+def test_batch_graph_replays_new_texts():
+    pairs = random_pairs(202, 40)
+    ms = matchers(pairs)
+    lens = [t.size for _, t in pairs]
+    b = P.Batch(ms, lens)
+    rng = np.random.default_rng(7)
+    for rep in range(3):
+        texts = [W.uniform_text(rng, d.alphabet, n) for (d, _), n in zip(pairs, lens)]
+        cur = [(d, t) for (d, _), t in zip(pairs, texts)]
+        say(f"[case] replay {rep}")
+        dev = to_device(texts)
+        # eager work of the program between replays
+        scratch = torch.arange(1 << 20, device="cuda", dtype=torch.int32).sum()
+        out = b.run_async(dev, use_graph=True)
+        torch.cuda.synchronize()
+        assert int(scratch) == (1 << 20) * ((1 << 20) - 1) // 2
+        check(cur, P.Batch.results(out, len(cur)), f"replay {rep}")
+        check(cur, b.run(dev, use_graph=False), f"eager {rep}")
+
+
+def test_batch_per_pair_options():
+    pairs = random_pairs(303, 32, max_len=100_000)
+    ms = matchers(pairs)
+    rng = np.random.default_rng(3)
+    opts = []
+    for _ in pairs:
+        opts.append({"chunk_len": int(rng.choice([64, 128, 256, 1024, 4096])),
+                     "group": int(rng.choice([4, 8, 16])), "tile": int(rng.choice([64, 128])),
+                     "no_merge": int(rng.random() < 0.2)})
+    say(f"[case] per-pair options")
+    b = P.Batch(ms, [t.size for _, t in pairs], opts)
+    got = b.run(to_device([t for _, t in pairs]))
+    check(pairs, got, "options", opts)
+    kinds = set()
+    for (d, t), m, o in zip(pairs, ms, opts):
+        if t.size:
+            kinds.add((m.describe()["layout"], m.describe()["kgram"], o["group"], o["tile"]))
+    assert b.describe()["walk_launches"] >= len({(k[2], k[3]) for k in kinds})
+
+
+def test_batch_invalid_byte_and_errors():
+    pairs = random_pairs(404, 20, max_len=20_000)
+    bad_i = next(i for i, (d, t) in enumerate(pairs) if t.size > 100 and d.alphabet_size < 256)
+    d, t = pairs[bad_i]
+    t = t.copy()
+    invalid = next(x for x in range(256) if x not in d.alphabet)
+    t[t.size // 2] = invalid
+    pairs[bad_i] = (d, t)
+    ms = matchers(pairs)
+    lens = [x.size for _, x in pairs]
+    say("[case] invalid byte in one pair")
+    dev = to_device([x for _, x in pairs])
+    got = P.Batch(ms, lens).run(dev)
+    for i, ((dd, tt), r) in enumerate(zip(pairs, got)):
+        if i == bad_i:
+            assert r.final_state == P.INVALID_STATE and not r.accept and r.count == 0
+        else:
+            want = oracle.walk_dfa(dd, tt)
+            assert (r.final_state, r.accept, r.count) == (want.final_state, want.accept, want.count)
+    out = torch.empty(len(pairs) * P.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+    with pytest.raises(P.ParemError) as e:
+        P.parem_match_batch([m.handle for m in ms], [x.data_ptr() for x in dev], lens,
+                            torch.cuda.current_stream().cuda_stream, out.data_ptr())
+    assert e.value.status == P.PAREM_ESYMBOL
+    # misaligned text pointer
+    b = P.Batch(ms, lens)
+    buf = torch.empty(lens[bad_i] + 32, dtype=torch.uint8, device="cuda")
+    dev2 = list(dev)
+    dev2[bad_i] = buf[1:1 + lens[bad_i]]
+    with pytest.raises(P.ParemError) as e:
+        b.run(dev2)
+    assert e.value.status == P.PAREM_EINVAL
+    # a lockstep group of 2 is not offered by the batch kernels
+    with pytest.raises(P.ParemError) as e:
+        P.Batch(ms, lens, [{"group": 2}] * len(ms))
+    assert e.value.status == P.PAREM_EUNSUPPORTED
+
+
+def test_match_batch_one_shot():
+    pairs = random_pairs(505, 24, max_len=50_000)
+    ms = matchers(pairs)
+    lens = [t.size for _, t in pairs]
+    dev = to_device([t for _, t in pairs])
+    out = torch.empty(len(pairs) * P.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+    say("[case] parem_match_batch")
+    P.parem_match_batch([m.handle for m in ms], [x.data_ptr() for x in dev], lens,
+                        torch.cuda.current_stream().cuda_stream, out.data_ptr())
+    check(pairs, P.Batch.results(out, len(pairs)), "one-shot")
+
+
+def test_tune_candidates_agree():
+    rng = np.random.default_rng(9)
+    dfa = W.sparse_dfa(rng, 300, bytes(rng.choice(256, size=20, replace=False).astype(np.uint8)), 4, 16,
+                       rng.choice(300, size=5, replace=False))
+    text = W.uniform_text(rng, dfa.alphabet, 1 << 20)
+    m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting)
+    dev = to_device([text])[0]
+    cands = [{"chunk_len": L, "group": g, "tile": t} for L in (1024, 4096) for g in (4, 8, 16) for t in (64, 128)]
+    cands.append({"chunk_len": 1 << 16})  # above the maximum: not runnable
+    say("[case] parem_tune")
+    ms_, best = P.parem_tune(m.handle, dev.data_ptr(), text.size, 16, cands, 2,
+                             torch.cuda.current_stream().cuda_stream)
+    assert ms_[-1] == -1.0 and all(x > 0 for x in ms_[:-1])
+    assert best == int(np.argmin(np.where(np.asarray(ms_) > 0, ms_, np.inf)))
+    want = oracle.walk_dfa(dfa, text)
+    for o in cands[:-1]:
+        r = P.Batch([m], [text.size], [o]).run([dev])[0]
+        assert (r.final_state, r.accept, r.count) == (want.final_state, want.accept, want.count), o

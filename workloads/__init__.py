@@ -100,11 +100,17 @@ def uniform_text(rng: np.random.Generator, alphabet: bytes, n: int) -> np.ndarra
             out[pos:pos + m] = lut[rb]
             pos += m
         return out
+    # other sizes: a random byte b < (256 // a) * a gives symbol b % a
+    # (rejection sampling keeps the draws exactly uniform and independent)
+    lim = (256 // a) * a
+    lut = alpha[np.arange(lim) % a]
     pos = 0
     while pos < n:
         m = min(_BLOCK, n - pos)
-        out[pos:pos + m] = alpha[rng.integers(0, a, size=m, dtype=np.uint8)]
-        pos += m
+        rb = np.frombuffer(rng.bytes(m + m // 8 + 64), dtype=np.uint8)
+        rb = rb[rb < lim][: m]
+        out[pos:pos + rb.size] = lut[rb]
+        pos += rb.size
     return out
 
 
