@@ -21,6 +21,8 @@ import statistics
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -28,12 +30,17 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 WALK_KERNEL = {1: "k_walk_byte", 2: "k_walk_byte", 3: "k_walk_kgram"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_traffic.json")
-WALK_SOURCE = os.path.join(ROOT, "paper_1412_1741_amd", "csrc", "parem_walk.hip")
+WALK_SOURCES = [os.path.join(ROOT, "paper_1412_1741_amd", "csrc", f)
+                for f in ("parem_device.h", "parem_walk_kernels.h", "parem_walk.hip")]
+TUNED_CACHE = os.path.join(ROOT, "paper_1412_1741_amd", "tuned", "batch_mi355x.json")
 
 
 def kernel_source_hash() -> str:
-    with open(WALK_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in WALK_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(n: int):
@@ -66,6 +73,84 @@ def cpu_baseline(dfa, text, budget_s: float = 10.0):
                            f"({dt:.1f} s, single thread)"}
 
 
+def bench_batch(args):
+    """The batched workload: uneven (DFA, text) pairs in one graph-captured
+    run, options from the autotuner; a sample of pairs checked against the
+    oracle."""
+    import concurrent.futures as cf
+
+    import torch
+
+    import oracle
+    import paper_1412_1741_amd as P
+    import workloads as W
+    from paper_1412_1741_amd.autotune import Autotuner
+
+    specs = W.config5_specs()[: args.batch_pairs]
+    print(f"[bench] batch: generating {len(specs)} pairs", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    order = np.argsort([s.text_len for s in specs])
+    sample = set(int(i) for i in order[: len(order) // 2: 16]) | set(int(i) for i in order[-4:])
+    dfas, devs, host = [], [], {}
+    with cf.ThreadPoolExecutor(16) as ex:
+        for i, (dfa, text) in enumerate(ex.map(W.config5_pair, specs)):
+            dfas.append(dfa)
+            devs.append(torch.from_numpy(text).cuda())
+            if i in sample:
+                host[i] = text
+            if (i + 1) % 256 == 0:
+                print(f"[bench] batch: {i + 1} pairs generated ({time.perf_counter() - t0:.1f} s)",
+                      file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    tuner = Autotuner(cache_path=TUNED_CACHE, log=lambda msg: print(f"[bench] tune {msg}", file=sys.stderr,
+                                                                    flush=True))
+    t0 = time.perf_counter()
+    matchers, opts = tuner.plan(dfas, devs)
+    plan_s = time.perf_counter() - t0
+    if args.tune_out:
+        tuner.cache_path = args.tune_out
+        tuner.save()
+    lens = [d.numel() for d in devs]
+    b = P.Batch(matchers, lens, opts)
+    out = torch.empty(len(devs) * P.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    print("[bench] batch: capture + warm-up", file=sys.stderr, flush=True)
+    b.run_async(devs, out, use_graph=True)
+    torch.cuda.synchronize()
+    ev_a = torch.cuda.Event(enable_timing=True)
+    ev_b = torch.cuda.Event(enable_timing=True)
+    steps = max(1, args.batch_steps)
+    ev_a.record(stream)
+    for _ in range(steps):
+        b.run_async(devs, out, use_graph=True)
+    ev_b.record(stream)
+    torch.cuda.synchronize()
+    ms = ev_a.elapsed_time(ev_b) / steps
+    got = P.Batch.results(out, len(devs))
+    total = int(sum(lens))
+    print(f"[bench] batch: oracle check of {len(host)} pairs", file=sys.stderr, flush=True)
+    exact = True
+    for i, text in host.items():
+        want = oracle.walk_dfa(dfas[i], text)
+        r = got[i]
+        exact &= (r.final_state, r.accept, r.count) == (want.final_state, want.accept, want.count)
+    info = b.describe()
+    b.close()
+    for mm in matchers:
+        mm.close()
+    return {"GBps": round(total / (ms * 1e-3) / 1e9, 2), "ms": round(ms, 4), "pairs": len(devs),
+            "text_bytes": total, "steps": steps, "use_graph": True, "graph_nodes": info["graph_nodes"],
+            "walk_launches": info["walk_launches"], "walk_items": info["walk_items"],
+            "compose_levels": info["levels"], "chunks": info["chunks"],
+            "workspace_bytes": info["workspace_bytes"], "spec_runs": int(sum(r.spec_runs for r in got)),
+            "invalid_pairs": int(sum(r.final_state == P.INVALID_STATE for r in got)),
+            "tuned_classes": len(tuner.cache), "tune_seconds": round(tuner.seconds, 2),
+            "tune_candidates_measured": tuner.measured, "plan_seconds": round(plan_s, 2),
+            "generate_seconds": round(gen_s, 2), "oracle_checked_pairs": len(host),
+            "oracle_checked_bytes": int(sum(t.size for t in host.values())), "bit_exact_sample": exact}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +167,9 @@ def main():
                     help="comma list: plain (merged runs), paper (every run walks its chunk), learned")
     ap.add_argument("--learned-m", default="1,4,16")
     ap.add_argument("--train-steps", type=int, default=400)
+    ap.add_argument("--batch-pairs", type=int, default=4096, help="pairs of the batched workload")
+    ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--tune-out", default="", help="write the autotuner cache here (default: not written)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="time a plain device copy of --size bytes instead (counter calibration)")
     args = ap.parse_args()
@@ -224,6 +312,9 @@ def main():
         prop.close()
     agree = all((r.final_state, r.accept, r.count) == (res.final_state, res.accept, res.count)
                 for r in results.values())
+
+    if "batch" in wanted:
+        modes["batch_uneven_4096"] = bench_batch(args)
 
     cpu = None
     exact = None

@@ -52,7 +52,8 @@ enum {
     PAREM_LAYOUT_BYTE_LDS = 1,   /* (Q+1) x 256 byte-indexed table in LDS       */
     PAREM_LAYOUT_BYTE_GLOBAL = 2,/* same table read through L2 (large tables)   */
     PAREM_LAYOUT_KGRAM_LDS = 3,  /* k-symbol stride table in LDS (small alphabets) */
-    PAREM_LAYOUT_SPARSE_LDS = 4  /* per-state default + exception records in LDS */
+    PAREM_LAYOUT_HOT_LDS = 4     /* rows of the most visited states in LDS, the
+                                    others read through L2 (up to 16383 states) */
 };
 
 typedef struct {

@@ -31,7 +31,7 @@ LAYOUT_AUTO = 0
 LAYOUT_BYTE_LDS = 1
 LAYOUT_BYTE_GLOBAL = 2
 LAYOUT_KGRAM_LDS = 3
-LAYOUT_SPARSE_LDS = 4
+LAYOUT_HOT_LDS = 4
 
 RESULT_BYTES = 40
 INVALID_STATE = 0xFFFFFFFF

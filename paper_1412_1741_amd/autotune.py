@@ -1,0 +1,145 @@
+"""Autotuner of the batched launch: table layout, chunk length, lockstep group
+and staged tile per size class, chosen by measurement on the GPU.
+
+A size class groups pairs whose best options should agree: the alphabet
+size, the number of states and the text length, each bucketed by powers of
+four. For a new class the tuner takes the first pair of the batch that falls
+in it and times candidates with ``parem_tune`` (a batch of copies of that
+pair, replayed from a HIP graph), in two rounds:
+
+  1. every table layout the DFA can use x lockstep groups {4, 8, 16}, at the
+     batch's automatic chunk length and 128-byte tiles;
+  2. for the winning layout and group: chunk lengths {1, 4, 16} x the
+     automatic one (clipped to 64 .. 32768 and to the text) x tiles {64, 128}.
+
+Texts shorter than ``min_tune_bytes`` keep the defaults (the layout the
+compile step picks, the automatic chunk length): they carry a negligible share
+of the bytes. Choices persist in a JSON cache keyed by class, so a workload is
+tuned once per machine; ``seconds`` reports the time spent measuring.
+
+Every candidate computes the same result (the sequential run): only speed
+differs, so a choice never affects correctness.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import time
+
+from . import LAYOUT_AUTO, LAYOUT_BYTE_GLOBAL, LAYOUT_BYTE_LDS, LAYOUT_KGRAM_LDS, Matcher, parem_tune
+
+MAX_CHUNK = 32768
+
+
+def batch_chunk_len(n: int) -> int:
+    """The batch's automatic chunk length: about 256 chunks, 64 B .. 8 KiB."""
+    L = 64
+    while L < 8192 and L * 256 < n:
+        L *= 2
+    return L
+
+
+def _bucket4(x: int) -> int:
+    return 0 if x <= 1 else int(math.floor(math.log(x, 4)))
+
+
+def size_class(num_states: int, alphabet_size: int, n: int) -> str:
+    return f"A{alphabet_size}/Q4^{_bucket4(num_states)}/N4^{_bucket4(n)}"
+
+
+class Autotuner:
+    def __init__(self, cache_path: str | None = None, min_tune_bytes: int = 1 << 20, target_bytes: int = 1 << 30,
+                 reps: int = 3, max_copies: int = 256, measure: bool = True, log=None):
+        self.cache_path = cache_path
+        self.log = log
+        self.measure = measure  # False: classes missing from the cache keep the defaults
+        self.min_tune_bytes = min_tune_bytes
+        self.target_bytes = target_bytes
+        self.reps = reps
+        self.max_copies = max_copies
+        self.cache: dict[str, dict] = {}
+        self.seconds = 0.0
+        self.measured = 0
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as f:
+                self.cache = json.load(f)
+
+    def save(self):
+        if self.cache_path:
+            tmp = self.cache_path + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(self.cache, f, indent=1, sort_keys=True)
+            os.replace(tmp, self.cache_path)
+
+    # -- measurement -------------------------------------------------------
+
+    def _time(self, matcher: Matcher, text, cands):
+        import torch
+        n = text.numel()
+        copies = int(max(1, min(self.max_copies, math.ceil(self.target_bytes / max(n, 1)))))
+        t0 = time.perf_counter()
+        ms, best = parem_tune(matcher.handle, text.data_ptr(), n, copies, cands, self.reps,
+                              torch.cuda.current_stream().cuda_stream)
+        self.seconds += time.perf_counter() - t0
+        self.measured += len(cands)
+        return ms, best
+
+    def tune_pair(self, dfa, text) -> dict:
+        """Measure the candidates for one (DFA, device text) pair."""
+        n = text.numel()
+        layouts = [LAYOUT_BYTE_GLOBAL]
+        if dfa.num_states + 1 <= 128:
+            layouts.append(LAYOUT_BYTE_LDS)
+        matchers = {}
+        for lay in layouts + [LAYOUT_KGRAM_LDS]:
+            m = Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, layout=lay)
+            if m.describe()["layout"] == lay:
+                matchers[lay] = m
+            else:
+                m.close()
+        L0 = batch_chunk_len(n)
+        best = None
+        for lay, m in matchers.items():
+            cands = [{"chunk_len": L0, "group": g, "tile": 128} for g in (4, 8, 16)]
+            ms, b = self._time(m, text, cands)
+            if ms[b] > 0 and (best is None or ms[b] < best[0]):
+                best = (ms[b], lay, cands[b]["group"])
+        _, lay, g = best
+        Ls = sorted({min(MAX_CHUNK, max(64, L0 * f)) for f in (1, 4, 16)})
+        Ls = [L for L in Ls if L == L0 or L <= max(64, n)]
+        cands = [{"chunk_len": L, "group": g, "tile": t} for L in Ls for t in (64, 128)]
+        ms, b = self._time(matchers[lay], text, cands)
+        for m in matchers.values():
+            m.close()
+        choice = {"layout": lay, **cands[b], "ms_per_copy": ms[b],
+                  "bytes": int(n), "GBps": round(n / (ms[b] * 1e-3) / 1e9, 2) if ms[b] > 0 else None}
+        return choice
+
+    # -- planning ------------------------------------------------------------
+
+    def choose(self, dfa, text) -> tuple[int, dict]:
+        """(layout, options) for one pair; tunes its class on first sight."""
+        n = text.numel()
+        if n < self.min_tune_bytes:
+            return LAYOUT_AUTO, {}
+        key = size_class(dfa.num_states, dfa.alphabet_size, n)
+        if key not in self.cache:
+            if not self.measure:
+                return LAYOUT_AUTO, {}
+            self.cache[key] = self.tune_pair(dfa, text)
+            if self.log:
+                self.log(f"{key}: {self.cache[key]} ({self.seconds:.1f} s so far)")
+        c = self.cache[key]
+        return int(c["layout"]), {"chunk_len": int(c["chunk_len"]), "group": int(c["group"]),
+                                  "tile": int(c["tile"])}
+
+    def plan(self, dfas, texts):
+        """Matchers compiled with the chosen layouts and per-pair options."""
+        matchers, opts = [], []
+        for dfa, text in zip(dfas, texts):
+            lay, o = self.choose(dfa, text)
+            m = Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, layout=lay)
+            matchers.append(m)
+            opts.append(o if o else {"chunk_len": 0})
+        return matchers, opts

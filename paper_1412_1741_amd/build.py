@@ -21,9 +21,15 @@ SOURCES = [
     "parem_walk_kgram_all.hip",
     "parem_walk_kgram_sel.hip",
     "parem_walk_kgram_redo.hip",
-    "parem_walk_byte_all.hip",
-    "parem_walk_byte_sel.hip",
-    "parem_walk_byte_redo.hip",
+    "parem_walk_bytelds_all.hip",
+    "parem_walk_bytelds_sel.hip",
+    "parem_walk_bytelds_redo.hip",
+    "parem_walk_byteglobal_all.hip",
+    "parem_walk_byteglobal_sel.hip",
+    "parem_walk_byteglobal_redo.hip",
+    "parem_walk_hot_all.hip",
+    "parem_walk_hot_sel.hip",
+    "parem_walk_hot_redo.hip",
     "parem_mlp.hip",
     "parem_batch.hip",
     "parem_batch_t64.hip",

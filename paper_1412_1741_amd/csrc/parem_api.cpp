@@ -32,7 +32,11 @@ void release(DeviceDfa &d) {
     hipFree(d.d_final);
     hipFree(d.d_verify);
     hipFree(d.d_inv);
+    hipFree(d.d_full);
+    hipFree(d.d_enc);
     d.d_inv = nullptr;
+    d.d_full = nullptr;
+    d.d_enc = nullptr;
     d.d_table = nullptr;
     d.d_cls = nullptr;
     d.d_loff = nullptr;
@@ -63,6 +67,54 @@ std::vector<E> byte_table(const DeviceDfa &d, const std::vector<uint32_t> &t, ui
         }
     }
     return out;
+}
+
+// Hot-row layout. The hot states are the kHotMax states of largest weight
+// under the stationary behaviour of the walk on uniformly random symbols
+// (power iteration, averaged over the later iterates so that periodic chains
+// settle); their rows go to LDS, followed by one row of kHotLost entries and
+// the hot states' ids. Every destination is stored encoded (its slot for a
+// hot state, kHotFlag | id for a cold one) with its final flag in bit 15.
+void hot_tables(DeviceDfa &d, const std::vector<uint32_t> &t, std::vector<uint8_t> &image,
+                std::vector<uint16_t> &full, std::vector<uint16_t> &enc) {
+    const uint32_t Q = d.Q, A = d.A;
+    std::vector<double> pi(Q, 1.0 / Q), nx(Q), acc(Q, 0.0);
+    for (int it = 0; it < 48; ++it) {
+        std::fill(nx.begin(), nx.end(), 0.0);
+        for (uint32_t q = 0; q < Q; ++q) {
+            const double w = pi[q] / A;
+            for (uint32_t a = 0; a < A; ++a) nx[t[(size_t)q * A + a]] += w;
+        }
+        pi.swap(nx);
+        if (it >= 16)
+            for (uint32_t q = 0; q < Q; ++q) acc[q] += pi[q];
+    }
+    std::vector<uint32_t> order(Q);
+    for (uint32_t q = 0; q < Q; ++q) order[q] = q;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return acc[a] > acc[b]; });
+    const uint32_t H = std::min<uint32_t>(parem::kHotMax, Q);
+    enc.assign(Q + 1, 0);
+    for (uint32_t q = 0; q <= Q; ++q) enc[q] = (uint16_t)(parem::kHotFlag | q);
+    for (uint32_t s = 0; s < H; ++s) enc[order[s]] = (uint16_t)s;
+    full.assign((size_t)(Q + 1) * 256, 0);
+    for (uint32_t q = 0; q <= Q; ++q) {
+        for (uint32_t x = 0; x < 256; ++x) {
+            uint32_t nxs = d.sent;
+            if (q < Q && d.cls[x] < A) nxs = t[(size_t)q * A + d.cls[x]];
+            full[(size_t)q * 256 + x] = (uint16_t)(enc[nxs] | ((uint32_t)d.final_flag[nxs] << 15));
+        }
+    }
+    const size_t rows_bytes = (size_t)(H + 1) * parem::kHotRow * 2;
+    image.assign((rows_bytes + (size_t)H * 2 + 15) / 16 * 16, 0);
+    uint16_t *rows = reinterpret_cast<uint16_t *>(image.data());
+    for (uint32_t s = 0; s < H; ++s) {
+        std::copy(full.begin() + (size_t)order[s] * 256, full.begin() + (size_t)order[s] * 256 + 256,
+                  rows + (size_t)s * parem::kHotRow);
+        rows[(size_t)(H + 1) * parem::kHotRow + s] = (uint16_t)order[s];
+    }
+    std::fill(rows + (size_t)H * parem::kHotRow, rows + (size_t)(H + 1) * parem::kHotRow,
+              (uint16_t)parem::kHotLost);
+    d.hot_rows = H;
 }
 
 // k-gram layout. Finds B bits and a shift such that (x >> shift) & (2^B - 1)
@@ -174,7 +226,7 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
             if (r) return PAREM_EINVAL;
         if (o.chunk_len % 64 || o.chunk_len > parem::kMaxChunk) return PAREM_EINVAL;
         if (o.group && o.group != 2 && o.group != 4 && o.group != 8 && o.group != 16) return PAREM_EINVAL;
-        if (o.layout > PAREM_LAYOUT_SPARSE_LDS) return PAREM_EINVAL;
+        if (o.layout > PAREM_LAYOUT_HOT_LDS) return PAREM_EINVAL;
         if (o.tile && o.tile != 64 && o.tile != 128) return PAREM_EINVAL;
         if (o.kgram) return PAREM_EINVAL;
         if (o.no_merge > 1) return PAREM_EINVAL;
@@ -248,10 +300,12 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
     std::vector<uint8_t> kgbytes;
     const bool kg_ok = (layout == PAREM_LAYOUT_AUTO || layout == PAREM_LAYOUT_KGRAM_LDS) && build_kgram(d, t, kgbytes);
     const bool lds_ok = d.Q + 1 <= 128;
+    const bool hot_ok = d.Q + 1 <= 0x3fffu;  // kHotFlag | id stays below kHotLost
     if (layout == PAREM_LAYOUT_AUTO || (layout == PAREM_LAYOUT_KGRAM_LDS && !kg_ok))
-        layout = kg_ok ? PAREM_LAYOUT_KGRAM_LDS : (lds_ok ? PAREM_LAYOUT_BYTE_LDS : PAREM_LAYOUT_BYTE_GLOBAL);
-    if (layout == PAREM_LAYOUT_BYTE_LDS && !lds_ok) layout = PAREM_LAYOUT_BYTE_GLOBAL;
-    if (layout == PAREM_LAYOUT_SPARSE_LDS) layout = PAREM_LAYOUT_BYTE_GLOBAL;
+        layout = kg_ok ? PAREM_LAYOUT_KGRAM_LDS
+                       : (lds_ok ? PAREM_LAYOUT_BYTE_LDS : (hot_ok ? PAREM_LAYOUT_HOT_LDS : PAREM_LAYOUT_BYTE_GLOBAL));
+    if (layout == PAREM_LAYOUT_BYTE_LDS && !lds_ok) layout = hot_ok ? PAREM_LAYOUT_HOT_LDS : PAREM_LAYOUT_BYTE_GLOBAL;
+    if (layout == PAREM_LAYOUT_HOT_LDS && !hot_ok) layout = PAREM_LAYOUT_BYTE_GLOBAL;
     d.layout = layout;
     if (layout != PAREM_LAYOUT_KGRAM_LDS) {
         d.kgram = 0;
@@ -277,6 +331,19 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
             uint8_t *p = nullptr;
             st = upload(bt, &p);
             d.d_table = p;
+        } else if (layout == PAREM_LAYOUT_HOT_LDS) {
+            std::vector<uint8_t> image;
+            std::vector<uint16_t> full, enc;
+            hot_tables(d, t, image, full, enc);
+            d.entry_bytes = 2;
+            d.row_stride = parem::kHotRow;
+            d.table_bytes = (uint32_t)image.size();
+            d.lds_bytes = d.table_bytes;
+            uint8_t *p = nullptr;
+            st = upload(image, &p);
+            d.d_table = p;
+            if (st == PAREM_OK) st = upload(full, &d.d_full);
+            if (st == PAREM_OK) st = upload(enc, &d.d_enc);
         } else {
             auto bt = byte_table<uint16_t>(d, t, 256);
             d.entry_bytes = 2;

@@ -73,6 +73,7 @@ uint32_t batch_chunk_len(uint64_t len) {
 static int batch_kind(const DeviceDfa &d) {
     if (d.layout == PAREM_LAYOUT_KGRAM_LDS) return BK_KGRAM1 + (int)d.kg.bits - 1;
     if (d.layout == PAREM_LAYOUT_BYTE_LDS) return BK_BYTE_LDS;
+    if (d.layout == PAREM_LAYOUT_HOT_LDS) return BK_HOT;
     return BK_BYTE_GLOBAL;
 }
 
@@ -274,6 +275,9 @@ static parem_status batch_plan(const parem_handle *dfas, const uint64_t *lens, u
         q.w = walk_args(d, p, nullptr, pws);
         q.table = d.d_table;
         q.table_bytes = d.table_bytes;
+        q.full = d.d_full;
+        q.enc = d.d_enc;
+        q.hot_rows = d.hot_rows;
         q.kg = d.kg;
         for (size_t k = 0; k < p.seg.size() && k < 2; ++k) q.seg[k] = seg_out(p, pws, k);
     }

@@ -13,6 +13,9 @@ struct BatchPair {
     const void *table;
     uint32_t table_bytes;
     uint32_t start;
+    const uint16_t *full;  // hot-row layout: the whole table and the state encoding
+    const uint16_t *enc;
+    uint32_t hot_rows;
     KgParams kg;
     ComposeArgs ca;
     SegOut seg[2];  // ping-pong segment buffers
@@ -32,7 +35,7 @@ struct ComposeItem {
 };
 
 // walk kernel variants: the table layout of the pairs they serve
-enum BatchKind : int { BK_BYTE_LDS = 0, BK_BYTE_GLOBAL = 1, BK_KGRAM1 = 2, BK_KGRAM2 = 3, BK_KGRAM3 = 4 };
+enum BatchKind : int { BK_BYTE_LDS = 0, BK_BYTE_GLOBAL = 1, BK_KGRAM1 = 2, BK_KGRAM2 = 3, BK_KGRAM3 = 4, BK_HOT = 5 };
 
 template <int G, uint32_t TILE, int KIND>
 __global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_batch_walk(
@@ -67,6 +70,10 @@ __global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_batch_walk(
         } else if constexpr (KIND == BK_BYTE_GLOBAL) {
             ByteStep<uint16_t, 256> st{reinterpret_cast<const uint16_t *>(bp.table)};
             walk_chunk<G, ByteStep<uint16_t, 256>, true, TILE, WALK_ALL>(st, a, smem, c0);
+        } else if constexpr (KIND == BK_HOT) {
+            const uint16_t *hot = reinterpret_cast<const uint16_t *>(smem);
+            HotStep st{hot, hot + (bp.hot_rows + 1) * kHotRow, bp.full, bp.enc, bp.hot_rows};
+            walk_chunk<G, HotStep, true, TILE, WALK_ALL>(st, a, smem + table_cap, c0);
         } else {
             KgStep<KIND - 1> st{smem, bp.kg};
             walk_chunk<G, KgStep<KIND - 1>, true, TILE, WALK_ALL>(st, a, smem + table_cap, c0);
@@ -84,7 +91,8 @@ WalkKernel walk_kernel_kind(int kind) {
         case BK_BYTE_GLOBAL: return k_batch_walk<G, TILE, BK_BYTE_GLOBAL>;
         case BK_KGRAM1: return k_batch_walk<G, TILE, BK_KGRAM1>;
         case BK_KGRAM2: return k_batch_walk<G, TILE, BK_KGRAM2>;
-        default: return k_batch_walk<G, TILE, BK_KGRAM3>;
+        case BK_KGRAM3: return k_batch_walk<G, TILE, BK_KGRAM3>;
+        default: return k_batch_walk<G, TILE, BK_HOT>;
     }
 }
 

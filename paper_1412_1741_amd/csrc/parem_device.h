@@ -39,6 +39,7 @@ __device__ __forceinline__ uint32_t lds_u16(const uint8_t *base, uint32_t byte_o
 // different banks (rows of 256 one-byte entries would all start on bank 0).
 template <typename E, uint32_t ROW>
 struct ByteStep {
+    static constexpr bool kRedo = false;  // pieces never need a second pass
     static constexpr uint32_t kAcc = sizeof(E) * 8 - 1;
     static constexpr uint32_t kMask = (1u << kAcc) - 1u;
     const E *__restrict__ T;
@@ -69,10 +70,81 @@ struct ByteStep {
     }
 };
 
+// Hot-row layout: the byte-table rows of the H most visited states sit in
+// LDS, the other rows are read through L2. A walk carries its state encoded:
+// the slot (0..H-1) of a hot state, kHotFlag | id for a cold one; every
+// entry holds the encoded destination plus the final flag in bit 15.
+// Sixteen bytes are first stepped through LDS alone (row min(state, H); row
+// H is all kHotLost, so a walk that leaves the hot rows stays marked); a
+// lane whose walks did not all stay hot steps the same sixteen bytes again
+// from the saved states with the global rows for cold states.
+struct HotStep {
+    static constexpr bool kRedo = true;
+    const uint16_t *__restrict__ hot;   // LDS: H + 1 rows of kHotRow entries
+    const uint16_t *__restrict__ ids;   // LDS: state id of each hot slot
+    const uint16_t *__restrict__ full;  // global: (Q+1) x 256 entries
+    const uint16_t *__restrict__ enc;   // global: encoded id of each state
+    uint32_t H;
+
+    __device__ __forceinline__ uint32_t init(uint32_t s) const { return enc[s]; }
+    __device__ __forceinline__ uint32_t id(uint32_t r) const { return r < H ? ids[r] : (r & 0x3fffu); }
+    __device__ __forceinline__ bool same(uint32_t a, uint32_t b) const { return a == b; }
+    __device__ __forceinline__ void fast(uint32_t &s, uint32_t &c, uint32_t byte) const {
+        const uint32_t v = hot[min(s, H) * kHotRow + byte];
+        c += v >> 15;
+        s = v & 0x7fffu;
+    }
+    __device__ __forceinline__ void one(uint32_t &s, uint32_t &c, uint32_t byte) const {
+        uint32_t v;
+        if (s < H) v = hot[s * kHotRow + byte];
+        else v = full[(s & 0x3fffu) * 256u + byte];
+        c += v >> 15;
+        s = v & 0x7fffu;
+    }
+    template <int G>
+    __device__ __forceinline__ void step16(const uint4 q, uint32_t (&R)[G], uint32_t (&c)[G], int nw) const {
+        uint32_t R0[G], c0[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            R0[j] = R[j];
+            c0[j] = c[j];
+        }
+        const uint32_t d[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+#pragma unroll
+            for (int j = 0; j < G; ++j)
+                if (j < nw) fast(R[j], c[j], (d[k >> 2] >> (8 * (k & 3))) & 0xffu);
+        }
+        bool cold = false;
+#pragma unroll
+        for (int j = 0; j < G; ++j) cold |= j < nw && R[j] >= H;
+        if (cold) {
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                R[j] = R0[j];
+                c[j] = c0[j];
+            }
+#pragma unroll 1
+            for (int k = 0; k < 16; ++k) {
+                const uint32_t word = k < 8 ? (k < 4 ? q.x : q.y) : (k < 12 ? q.z : q.w);
+                const uint32_t byte = (word >> (8 * (k & 3))) & 0xffu;
+#pragma unroll
+                for (int j = 0; j < G; ++j)
+                    if (j < nw) one(R[j], c[j], byte);
+            }
+        }
+    }
+    __device__ __forceinline__ void byte(uint32_t x, uint32_t &R, uint32_t &c, uint32_t &bad) const {
+        one(R, c, x);
+    }
+};
+
 // k-gram table: a state is carried as its row base (state << RS) plus the
 // count bits of the last entry read.
 template <int B>
 struct KgStep {
+    static constexpr bool kRedo = false;
     static constexpr uint32_t K = (B == 3) ? 2 : 4;   // symbols per lookup
     static constexpr uint32_t RS = K * B + 1;         // row bytes = 1 << RS
     static constexpr uint32_t LOW = (1u << RS) - 1u;  // count field
@@ -163,7 +235,15 @@ __device__ __forceinline__ void merge_check(const ST &st, Walks<G> &w) {
 // followers) or for the leader alone
 template <int G, typename ST>
 __device__ __forceinline__ void piece(const ST &st, Walks<G> &w, const uint4 q, uint32_t &bad) {
-    if (w.wave_pending) {
+    if constexpr (ST::kRedo) {
+        if (w.wave_pending) {
+            st.template step16<G>(q, w.R, w.c, G);
+            merge_check<G>(st, w);
+            w.wave_pending = __any(w.pending != 0);
+        } else {
+            st.template step16<G>(q, w.R, w.c, 1);
+        }
+    } else if (w.wave_pending) {
         st.template dword<G>(q.x, w.R, w.S, w.c, G, bad);
         st.template dword<G>(q.y, w.R, w.S, w.c, G, bad);
         st.template dword<G>(q.z, w.R, w.S, w.c, G, bad);
@@ -882,22 +962,34 @@ __device__ __forceinline__ void compose_segs_seg(uint8_t *smem, const SegOut &in
 }
 
 
-// walk launch of one text for a table family (k-gram or byte tables) and
-// walk mode; instantiated in its own translation unit per (family, mode)
-template <bool KGRAM, int MODE>
+// walk launch of one text for a table layout and walk mode; instantiated in
+// its own translation unit per (layout, mode)
+template <int LAYOUT, int MODE>
 void launch_walk_family(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, hipStream_t stream, bool aligned);
-extern template void launch_walk_family<true, WALK_ALL>(const DeviceDfa &, const PlainPlan &, const WalkArgs &,
-                                                        hipStream_t, bool);
-extern template void launch_walk_family<true, WALK_SELECTED>(const DeviceDfa &, const PlainPlan &, const WalkArgs &,
-                                                             hipStream_t, bool);
-extern template void launch_walk_family<true, WALK_REDO>(const DeviceDfa &, const PlainPlan &, const WalkArgs &,
-                                                         hipStream_t, bool);
-extern template void launch_walk_family<false, WALK_ALL>(const DeviceDfa &, const PlainPlan &, const WalkArgs &,
-                                                         hipStream_t, bool);
-extern template void launch_walk_family<false, WALK_SELECTED>(const DeviceDfa &, const PlainPlan &,
-                                                              const WalkArgs &, hipStream_t, bool);
-extern template void launch_walk_family<false, WALK_REDO>(const DeviceDfa &, const PlainPlan &, const WalkArgs &,
-                                                          hipStream_t, bool);
+extern template void launch_walk_family<PAREM_LAYOUT_KGRAM_LDS, WALK_ALL>(const DeviceDfa &, const PlainPlan &,
+                                                     const WalkArgs &, hipStream_t, bool);
+extern template void launch_walk_family<PAREM_LAYOUT_KGRAM_LDS, WALK_SELECTED>(const DeviceDfa &, const PlainPlan &,
+                                                     const WalkArgs &, hipStream_t, bool);
+extern template void launch_walk_family<PAREM_LAYOUT_KGRAM_LDS, WALK_REDO>(const DeviceDfa &, const PlainPlan &,
+                                                     const WalkArgs &, hipStream_t, bool);
+extern template void launch_walk_family<PAREM_LAYOUT_BYTE_LDS, WALK_ALL>(const DeviceDfa &, const PlainPlan &,
+                                                     const WalkArgs &, hipStream_t, bool);
+extern template void launch_walk_family<PAREM_LAYOUT_BYTE_LDS, WALK_SELECTED>(const DeviceDfa &, const PlainPlan &,
+                                                     const WalkArgs &, hipStream_t, bool);
+extern template void launch_walk_family<PAREM_LAYOUT_BYTE_LDS, WALK_REDO>(const DeviceDfa &, const PlainPlan &,
+                                                     const WalkArgs &, hipStream_t, bool);
+extern template void launch_walk_family<PAREM_LAYOUT_BYTE_GLOBAL, WALK_ALL>(const DeviceDfa &, const PlainPlan &,
+                                                     const WalkArgs &, hipStream_t, bool);
+extern template void launch_walk_family<PAREM_LAYOUT_BYTE_GLOBAL, WALK_SELECTED>(const DeviceDfa &, const PlainPlan &,
+                                                     const WalkArgs &, hipStream_t, bool);
+extern template void launch_walk_family<PAREM_LAYOUT_BYTE_GLOBAL, WALK_REDO>(const DeviceDfa &, const PlainPlan &,
+                                                     const WalkArgs &, hipStream_t, bool);
+extern template void launch_walk_family<PAREM_LAYOUT_HOT_LDS, WALK_ALL>(const DeviceDfa &, const PlainPlan &,
+                                                     const WalkArgs &, hipStream_t, bool);
+extern template void launch_walk_family<PAREM_LAYOUT_HOT_LDS, WALK_SELECTED>(const DeviceDfa &, const PlainPlan &,
+                                                     const WalkArgs &, hipStream_t, bool);
+extern template void launch_walk_family<PAREM_LAYOUT_HOT_LDS, WALK_REDO>(const DeviceDfa &, const PlainPlan &,
+                                                     const WalkArgs &, hipStream_t, bool);
 
 // ---------------------------------------------------------------------------
 // host-side argument builders

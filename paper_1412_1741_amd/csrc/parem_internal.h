@@ -62,7 +62,18 @@ struct DeviceDfa {
     uint8_t *d_verify = nullptr;     // unused (kept null)
     uint16_t *d_inv = nullptr;       // [(A+2) * (Q+1)] position of a state in each class list, 0xffff if absent
     uint32_t inv_lds = 0;            // bytes of d_inv staged in LDS by the compose kernels (0: read from L2)
+    // hot-row layout: d_table is the LDS image (hot rows, then their state ids)
+    uint16_t *d_full = nullptr;      // (Q+1) x 256 byte table with encoded destinations
+    uint16_t *d_enc = nullptr;       // [Q+1] encoded id of each state (slot when hot, 0x4000 | id else)
+    uint32_t hot_rows = 0;
 };
+
+// hot-row layout: at most kHotMax rows of kHotRow u16 entries (256 bytes plus
+// padding that shifts successive rows by one LDS bank)
+constexpr uint32_t kHotMax = 32;
+constexpr uint32_t kHotRow = 258;
+constexpr uint32_t kHotFlag = 0x4000u;  // cold state: kHotFlag | id; hot state: its slot
+constexpr uint32_t kHotLost = 0x7fffu;  // entries of the extra LDS row H
 
 // learned proposal network dimensions (32-byte window, 16-d embeddings)
 constexpr uint32_t kMlpWindow = 32;

@@ -317,8 +317,12 @@ parem_status plan_plain(const DeviceDfa &d, uint64_t len, PlainPlan *p) {
 template <int MODE>
 static void launch_walk(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, hipStream_t stream,
                         bool aligned) {
-    if (d.layout == PAREM_LAYOUT_KGRAM_LDS) launch_walk_family<true, MODE>(d, p, a, stream, aligned);
-    else launch_walk_family<false, MODE>(d, p, a, stream, aligned);
+    switch (d.layout) {
+        case PAREM_LAYOUT_KGRAM_LDS: launch_walk_family<PAREM_LAYOUT_KGRAM_LDS, MODE>(d, p, a, stream, aligned); break;
+        case PAREM_LAYOUT_BYTE_LDS: launch_walk_family<PAREM_LAYOUT_BYTE_LDS, MODE>(d, p, a, stream, aligned); break;
+        case PAREM_LAYOUT_HOT_LDS: launch_walk_family<PAREM_LAYOUT_HOT_LDS, MODE>(d, p, a, stream, aligned); break;
+        default: launch_walk_family<PAREM_LAYOUT_BYTE_GLOBAL, MODE>(d, p, a, stream, aligned); break;
+    }
 }
 
 static parem_status launch_compose(const DeviceDfa &d, const PlainPlan &p, uint8_t *ws, hipStream_t stream,

@@ -8,6 +8,21 @@
 
 namespace parem {
 
+// Walk modes other than WALK_ALL (learned selection, re-walk) lock-step 8 or
+// 16 walks; WALK_ALL offers every group size.
+#define PAREM_GROUP_SWITCH(X)                                 \
+    if constexpr (MODE == WALK_ALL) {                         \
+        switch (p.G) {                                        \
+            case 2: X(2); break;                              \
+            case 4: X(4); break;                              \
+            case 8: X(8); break;                              \
+            default: X(16); break;                            \
+        }                                                     \
+    } else {                                                  \
+        if (p.G <= 8) X(8);                                   \
+        else X(16);                                           \
+    }
+
 // at least 4 waves per SIMD (at most 128 VGPRs) for groups up to 8 walks
 template <typename E, uint32_t ROW, int G, bool LDS_TABLE, bool ALIGNED, uint32_t TILE, int MODE>
 __global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_walk_byte(WalkArgs a, const E *__restrict__ g_table,
@@ -21,6 +36,18 @@ __global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_walk_byte(Wa
         tb = table_bytes;
     }
     walk_chunk<G, ByteStep<E, ROW>, ALIGNED, TILE, MODE>(st, a, smem + tb, (uint64_t)blockIdx.x * kWalkThreads);
+}
+
+template <int G, bool ALIGNED, uint32_t TILE, int MODE>
+__global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_walk_hot(WalkArgs a, const uint8_t *__restrict__ g_table,
+                                                                             uint32_t table_bytes, uint32_t hot_rows,
+                                                                             const uint16_t *__restrict__ full,
+                                                                             const uint16_t *__restrict__ enc) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    stage_table(reinterpret_cast<uint4 *>(smem), reinterpret_cast<const uint4 *>(g_table), table_bytes / 16u);
+    const uint16_t *hot = reinterpret_cast<const uint16_t *>(smem);
+    HotStep st{hot, hot + (hot_rows + 1) * kHotRow, full, enc, hot_rows};
+    walk_chunk<G, HotStep, ALIGNED, TILE, MODE>(st, a, smem + table_bytes, (uint64_t)blockIdx.x * kWalkThreads);
 }
 
 template <int G, int B, bool ALIGNED, uint32_t TILE, int MODE>
@@ -41,12 +68,7 @@ inline void launch_walk_byte(const DeviceDfa &d, const PlainPlan &p, const WalkA
 #define PAREM_WALK(GG)                                                                                            \
     hipLaunchKernelGGL((k_walk_byte<E, ROW, GG, LDS, ALIGNED, TILE, MODE>), dim3(grid), dim3(kWalkThreads), lds, \
                        stream, a, tab, d.table_bytes)
-    switch (p.G) {
-        case 2: PAREM_WALK(2); break;
-        case 4: PAREM_WALK(4); break;
-        case 8: PAREM_WALK(8); break;
-        default: PAREM_WALK(16); break;
-    }
+    PAREM_GROUP_SWITCH(PAREM_WALK)
 #undef PAREM_WALK
 }
 
@@ -58,37 +80,48 @@ inline void launch_kgram_b(const DeviceDfa &d, const PlainPlan &p, const WalkArg
 #define PAREM_KG(GG)                                                                                              \
     hipLaunchKernelGGL((k_walk_kgram<GG, B, ALIGNED, TILE, MODE>), dim3(grid), dim3(kWalkThreads), lds, stream, a, \
                        tab, d.table_bytes, d.kg)
-    switch (p.G) {
-        case 2: PAREM_KG(2); break;
-        case 4: PAREM_KG(4); break;
-        case 8: PAREM_KG(8); break;
-        default: PAREM_KG(16); break;
-    }
+    PAREM_GROUP_SWITCH(PAREM_KG)
 #undef PAREM_KG
 }
 
-template <bool KGRAM, bool ALIGNED, uint32_t TILE, int MODE>
+template <bool ALIGNED, uint32_t TILE, int MODE>
+inline void launch_walk_hot(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, hipStream_t stream) {
+    const uint32_t grid = (uint32_t)((p.chunks + kWalkThreads - 1) / kWalkThreads);
+    const size_t lds = d.table_bytes + ((ALIGNED && MODE != WALK_REDO) ? Stage<TILE>::kBytes : 0);
+    const uint8_t *tab = reinterpret_cast<const uint8_t *>(d.d_table);
+#define PAREM_HOT(GG)                                                                                           \
+    hipLaunchKernelGGL((k_walk_hot<GG, ALIGNED, TILE, MODE>), dim3(grid), dim3(kWalkThreads), lds, stream, a, tab, \
+                       d.table_bytes, d.hot_rows, d.d_full, d.d_enc)
+    PAREM_GROUP_SWITCH(PAREM_HOT)
+#undef PAREM_HOT
+}
+
+template <int LAYOUT, bool ALIGNED, uint32_t TILE, int MODE>
 inline void launch_family_t(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, hipStream_t stream) {
-    if constexpr (KGRAM) {
+    if constexpr (LAYOUT == PAREM_LAYOUT_KGRAM_LDS) {
         switch (d.kg.bits) {
             case 1: launch_kgram_b<1, ALIGNED, TILE, MODE>(d, p, a, stream); break;
             case 2: launch_kgram_b<2, ALIGNED, TILE, MODE>(d, p, a, stream); break;
             default: launch_kgram_b<3, ALIGNED, TILE, MODE>(d, p, a, stream); break;
         }
-    } else if (d.layout == PAREM_LAYOUT_BYTE_LDS) {
+    } else if constexpr (LAYOUT == PAREM_LAYOUT_BYTE_LDS) {
         launch_walk_byte<uint8_t, kByteLdsRow, true, ALIGNED, TILE, MODE>(d, p, a, stream);
+    } else if constexpr (LAYOUT == PAREM_LAYOUT_HOT_LDS) {
+        launch_walk_hot<ALIGNED, TILE, MODE>(d, p, a, stream);
     } else {
         launch_walk_byte<uint16_t, 256, false, ALIGNED, TILE, MODE>(d, p, a, stream);
     }
 }
 
-// KGRAM: the k-gram layout (B = 1..3), else the byte layouts (LDS / global)
-template <bool KGRAM, int MODE>
+// one table layout and walk mode
+template <int LAYOUT, int MODE>
 void launch_walk_family(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, hipStream_t stream,
                         bool aligned) {
-    if (!aligned) launch_family_t<KGRAM, false, 64, MODE>(d, p, a, stream);
-    else if (p.tile == 128 || MODE == WALK_REDO) launch_family_t<KGRAM, true, 128, MODE>(d, p, a, stream);
-    else launch_family_t<KGRAM, true, 64, MODE>(d, p, a, stream);
+    if (!aligned) launch_family_t<LAYOUT, false, 64, MODE>(d, p, a, stream);
+    else if (p.tile == 128 || MODE == WALK_REDO) launch_family_t<LAYOUT, true, 128, MODE>(d, p, a, stream);
+    else launch_family_t<LAYOUT, true, 64, MODE>(d, p, a, stream);
 }
+
+#undef PAREM_GROUP_SWITCH
 
 }  // namespace parem

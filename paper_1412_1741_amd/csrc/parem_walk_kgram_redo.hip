@@ -2,6 +2,6 @@
 #include "parem_walk_kernels.h"
 
 namespace parem {
-template void launch_walk_family<true, WALK_REDO>(const DeviceDfa &, const PlainPlan &,
-                                                         const WalkArgs &, hipStream_t, bool);
+template void launch_walk_family<PAREM_LAYOUT_KGRAM_LDS, WALK_REDO>(const DeviceDfa &, const PlainPlan &, const WalkArgs &, hipStream_t,
+                                              bool);
 }  // namespace parem

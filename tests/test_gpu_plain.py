@@ -86,7 +86,7 @@ def test_config2_small_groups(group):
 
 
 def all_layouts():
-    return [P.LAYOUT_AUTO, P.LAYOUT_KGRAM_LDS, P.LAYOUT_BYTE_LDS, P.LAYOUT_BYTE_GLOBAL]
+    return [P.LAYOUT_AUTO, P.LAYOUT_KGRAM_LDS, P.LAYOUT_BYTE_LDS, P.LAYOUT_BYTE_GLOBAL, P.LAYOUT_HOT_LDS]
 
 
 def test_config2_layouts():
@@ -181,7 +181,33 @@ def test_large_state_counts():
     for q in (128, 300, 1000, 4096):
         dfa = W.random_dense_dfa(rng, q, bytes(range(0, 256, 16)), num_accepting=q // 8)
         text = W.uniform_text(rng, dfa.alphabet, 1 << 18)
-        run_case(f"dense Q={q}", dfa, text, chunk_len=4096)
+        for lay in (P.LAYOUT_BYTE_GLOBAL, P.LAYOUT_HOT_LDS):
+            run_case(f"dense Q={q} layout={lay}", dfa, text, chunk_len=4096, layout=lay)
+
+
+@pytest.mark.parametrize("group", [2, 4, 8, 16])
+def test_hot_rows_sparse_and_dense(group):
+    """Hot-row layout: a sparse byte DFA whose walk stays in a few hot rows,
+    a dense one whose walk mostly leaves them (every piece stepped twice),
+    and one with fewer states than hot rows."""
+    rng = np.random.default_rng(500 + group)
+    sym = rng.choice(256, size=64, replace=False).astype(np.uint8)
+    acc = rng.choice(np.arange(1, 3000), size=16, replace=False)
+    sparse = W.sparse_dfa(rng, 3000, bytes(range(256)), 4, 4, acc, explicit_cols=sym)
+    text = W.zipf_text(rng, sym, (1 << 20) + 77)
+    m = P.Matcher(sparse.table, sparse.alphabet, sparse.start, sparse.accepting)
+    assert m.describe()["layout"] == P.LAYOUT_HOT_LDS
+    m.close()
+    run_case(f"hot sparse G={group}", sparse, text, chunk_len=1024, group=group)
+    run_case(f"hot sparse tiny G={group}", sparse, text[:1000], chunk_len=64, group=group, offset=3)
+    dense = W.random_dense_dfa(rng, 700, bytes(rng.choice(256, size=4, replace=False).astype(np.uint8)),
+                               num_accepting=70)
+    run_case(f"hot dense G={group}", dense, W.uniform_text(rng, dense.alphabet, 1 << 18), chunk_len=2048,
+             group=group, layout=P.LAYOUT_HOT_LDS)
+    small = W.random_dense_dfa(rng, 20, bytes(rng.choice(256, size=30, replace=False).astype(np.uint8)),
+                               num_accepting=3)
+    run_case(f"hot small G={group}", small, W.uniform_text(rng, small.alphabet, 100_000), chunk_len=512,
+             group=group, layout=P.LAYOUT_HOT_LDS)
 
 
 def test_invalid_bytes():

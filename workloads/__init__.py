@@ -66,6 +66,13 @@ class Dfa:
 _BLOCK = 1 << 26  # generate large texts in 64 MiB blocks to bound host memory
 
 
+def _random_bytes(rng: np.random.Generator, m: int) -> np.ndarray:
+    """``m`` i.i.d. uniform bytes (64-bit draws: several times faster than
+    Generator.bytes)."""
+    k = (m + 7) // 8
+    return rng.integers(0, 2 ** 64 - 1, size=k, dtype=np.uint64, endpoint=True).view(np.uint8)[:m]
+
+
 def uniform_text(rng: np.random.Generator, alphabet: bytes, n: int) -> np.ndarray:
     """``n`` bytes drawn i.i.d. uniformly from ``alphabet``."""
     alpha = np.frombuffer(alphabet, dtype=np.uint8)
@@ -84,7 +91,7 @@ def uniform_text(rng: np.random.Generator, alphabet: bytes, n: int) -> np.ndarra
         pos = 0
         while pos < q:
             m = min(_BLOCK, q - pos)
-            rb = np.frombuffer(rng.bytes(m), dtype=np.uint8)
+            rb = _random_bytes(rng, m)
             out[4 * pos:4 * (pos + m)].view(np.uint32)[:] = lut32[rb]
             pos += m
         tail = n - 4 * q
@@ -92,12 +99,11 @@ def uniform_text(rng: np.random.Generator, alphabet: bytes, n: int) -> np.ndarra
             out[4 * q:] = alpha[rng.integers(0, 4, size=tail)]
         return out
     if a == 256:
-        lut = alpha
+        # every byte value is in the alphabet: uniform bytes are uniform symbols
         pos = 0
         while pos < n:
             m = min(_BLOCK, n - pos)
-            rb = np.frombuffer(rng.bytes(m), dtype=np.uint8)
-            out[pos:pos + m] = lut[rb]
+            out[pos:pos + m] = _random_bytes(rng, m)
             pos += m
         return out
     # other sizes: a random byte b < (256 // a) * a gives symbol b % a
@@ -107,12 +113,11 @@ def uniform_text(rng: np.random.Generator, alphabet: bytes, n: int) -> np.ndarra
     pos = 0
     while pos < n:
         m = min(_BLOCK, n - pos)
-        rb = np.frombuffer(rng.bytes(m + m // 8 + 64), dtype=np.uint8)
+        rb = _random_bytes(rng, m + m // 8 + 64)
         rb = rb[rb < lim][: m]
         out[pos:pos + rb.size] = lut[rb]
         pos += rb.size
     return out
-
 
 def zipf_lut(symbols: np.ndarray, s: float = 1.1) -> np.ndarray:
     """65536-entry inverse-CDF table: a uniform 16-bit draw ``u`` maps to
