@@ -65,7 +65,15 @@ typedef struct {
     uint32_t no_merge;    /* 1: every speculated run walks its whole chunk, as the
                              paper's Algorithm 1 does; 0 (default): runs that
                              reach the same state are merged (identical results) */
-    uint32_t reserved[2]; /* must be zero                                        */
+    uint32_t lookback;    /* 0 (default): chunk c is walked from R_c, the image of
+                             the column of the byte before it (Algorithm 1).
+                             K > 0: from the image of every state under the K
+                             bytes before the chunk (K capped at the chunk
+                             length and at the chunk's offset), a subset of R_c
+                             that still holds the true entry state, so results
+                             are identical; chunks whose image has more than 64
+                             states use R_c. At most 4096; needs Q < 16384.   */
+    uint32_t reserved;    /* must be zero                                        */
 } parem_options;
 
 typedef struct {

@@ -46,7 +46,7 @@ class ParemError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("chunk_len", ctypes.c_uint32), ("layout", ctypes.c_uint32), ("group", ctypes.c_uint32),
                 ("kgram", ctypes.c_uint32), ("tile", ctypes.c_uint32), ("no_merge", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 2)]
+                ("lookback", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class Result(ctypes.Structure):
@@ -157,7 +157,7 @@ def _check(status: int, where: str):
 
 
 def parem_compile(table, alphabet, start: int, accepting, *, chunk_len: int = 0, layout: int = 0,
-                  group: int = 0, tile: int = 0, no_merge: bool = False) -> int:
+                  group: int = 0, tile: int = 0, no_merge: bool = False, lookback: int = 0) -> int:
     """Compile a total DFA; returns the handle (an integer address)."""
     t = np.ascontiguousarray(table)
     if t.ndim != 2:
@@ -166,7 +166,7 @@ def parem_compile(table, alphabet, start: int, accepting, *, chunk_len: int = 0,
         t = np.ascontiguousarray(t, dtype=np.uint32)
     alpha = np.frombuffer(bytes(alphabet), dtype=np.uint8).copy()
     acc = np.ascontiguousarray(np.asarray(accepting, dtype=np.uint32).reshape(-1))
-    opt = Options(chunk_len, layout, group, 0, tile, 1 if no_merge else 0)
+    opt = Options(chunk_len, layout, group, 0, tile, 1 if no_merge else 0, lookback)
     h = ctypes.c_void_p()
     st = lib().parem_compile(t.ctypes.data, t.dtype.itemsize, t.shape[0], alpha.ctypes.data, alpha.size,
                             int(start), acc.ctypes.data if acc.size else None, acc.size, ctypes.byref(opt),

@@ -7,10 +7,12 @@ four. For a new class the tuner takes the first pair of the batch that falls
 in it and times candidates with ``parem_tune`` (a batch of copies of that
 pair, replayed from a HIP graph), in two rounds:
 
-  1. every table layout the DFA can use x lockstep groups {4, 8, 16}, at the
-     batch's automatic chunk length and 128-byte tiles;
-  2. for the winning layout and group: chunk lengths {1, 4, 16} x the
-     automatic one (clipped to 64 .. 32768 and to the text) x tiles {64, 128}.
+  1. every table layout the DFA can use x speculated sets (Algorithm 1's,
+     or lookback sets over 32 or 512 bytes), at the batch's automatic chunk
+     length, 8 walks in lockstep and 128-byte tiles;
+  2. for the winning layout and sets: chunk lengths {1, 4, 16} x the
+     automatic one (clipped to 64 .. 32768 and to the text) x lockstep
+     groups {4, 8, 16} x tiles {64, 128}.
 
 Texts shorter than ``min_tune_bytes`` keep the defaults (the layout the
 compile step picks, the automatic chunk length): they carry a negligible share
@@ -49,8 +51,8 @@ def size_class(num_states: int, alphabet_size: int, n: int) -> str:
 
 
 class Autotuner:
-    def __init__(self, cache_path: str | None = None, min_tune_bytes: int = 1 << 20, target_bytes: int = 1 << 30,
-                 reps: int = 3, max_copies: int = 256, measure: bool = True, log=None):
+    def __init__(self, cache_path: str | None = None, min_tune_bytes: int = 1 << 20, target_bytes: int = 256 << 20,
+                 reps: int = 2, max_copies: int = 256, measure: bool = True, log=None):
         self.cache_path = cache_path
         self.log = log
         self.measure = measure  # False: classes missing from the cache keep the defaults
@@ -101,14 +103,15 @@ class Autotuner:
         L0 = batch_chunk_len(n)
         best = None
         for lay, m in matchers.items():
-            cands = [{"chunk_len": L0, "group": g, "tile": 128} for g in (4, 8, 16)]
+            cands = [{"chunk_len": L0, "group": 8, "tile": 128, "lookback": k} for k in (0, 32, 512)]
             ms, b = self._time(m, text, cands)
             if ms[b] > 0 and (best is None or ms[b] < best[0]):
-                best = (ms[b], lay, cands[b]["group"])
-        _, lay, g = best
+                best = (ms[b], lay, cands[b]["lookback"])
+        _, lay, k = best
         Ls = sorted({min(MAX_CHUNK, max(64, L0 * f)) for f in (1, 4, 16)})
         Ls = [L for L in Ls if L == L0 or L <= max(64, n)]
-        cands = [{"chunk_len": L, "group": g, "tile": t} for L in Ls for t in (64, 128)]
+        cands = [{"chunk_len": L, "group": g, "tile": t, "lookback": k} for L in Ls for g in (4, 8, 16)
+                 for t in (64, 128)]
         ms, b = self._time(matchers[lay], text, cands)
         for m in matchers.values():
             m.close()
@@ -132,7 +135,7 @@ class Autotuner:
                 self.log(f"{key}: {self.cache[key]} ({self.seconds:.1f} s so far)")
         c = self.cache[key]
         return int(c["layout"]), {"chunk_len": int(c["chunk_len"]), "group": int(c["group"]),
-                                  "tile": int(c["tile"])}
+                                  "tile": int(c["tile"]), "lookback": int(c.get("lookback", 0))}
 
     def plan(self, dfas, texts):
         """Matchers compiled with the chosen layouts and per-pair options."""

@@ -34,6 +34,8 @@ SOURCES = [
     "parem_batch.hip",
     "parem_batch_t64.hip",
     "parem_batch_t128.hip",
+    "parem_batch_t64_sel.hip",
+    "parem_batch_t128_sel.hip",
 ]
 
 HIP_FLAGS = [

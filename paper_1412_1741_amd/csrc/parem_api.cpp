@@ -34,6 +34,8 @@ void release(DeviceDfa &d) {
     hipFree(d.d_inv);
     hipFree(d.d_full);
     hipFree(d.d_enc);
+    hipFree(d.d_next);
+    d.d_next = nullptr;
     d.d_inv = nullptr;
     d.d_full = nullptr;
     d.d_enc = nullptr;
@@ -222,8 +224,8 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
     parem_options o{};
     if (opt) {
         o = *opt;
-        for (uint32_t r : o.reserved)
-            if (r) return PAREM_EINVAL;
+        if (o.reserved) return PAREM_EINVAL;
+        if (o.lookback > parem::kLookMax) return PAREM_EINVAL;
         if (o.chunk_len % 64 || o.chunk_len > parem::kMaxChunk) return PAREM_EINVAL;
         if (o.group && o.group != 2 && o.group != 4 && o.group != 8 && o.group != 16) return PAREM_EINVAL;
         if (o.layout > PAREM_LAYOUT_HOT_LDS) return PAREM_EINVAL;
@@ -359,6 +361,14 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
     if (st == PAREM_OK) st = upload(d.loff, &d.d_loff);
     if (st == PAREM_OK) st = upload(d.llist, &d.d_llist);
     if (st == PAREM_OK) st = upload(d.final_flag, &d.d_final);
+    if (st == PAREM_OK && d.Q + 1 <= parem::kLookStates) {
+        // next state by class for lookback sets; the sentinel row stays in the sentinel
+        std::vector<uint16_t> nx((size_t)(d.Q + 1) * d.A);
+        for (uint32_t q = 0; q <= d.Q; ++q)
+            for (uint32_t a = 0; a < d.A; ++a)
+                nx[(size_t)q * d.A + a] = (uint16_t)(q < d.Q ? t[(size_t)q * d.A + a] : d.sent);
+        st = upload(nx, &d.d_next);
+    }
     // inverse index of the class lists (composition looks up the position of
     // an end state in the next chunk's list); skipped when it would be huge
     const uint64_t inv_entries = (uint64_t)d.num_classes * (d.Q + 1);

@@ -57,8 +57,45 @@ __global__ void k_batch_empty(const BatchPair *__restrict__ pairs, const uint32_
     *bp.out = r;
 }
 
-static WalkKernel walk_kernel(uint32_t G, uint32_t tile, int kind) {
+static WalkKernel walk_kernel(uint32_t G, uint32_t tile, int kind, bool sel) {
+    if (sel) return tile == 64 ? batch_walk_kernel_64_sel(G, kind) : batch_walk_kernel_128_sel(G, kind);
     return tile == 64 ? batch_walk_kernel_64(G, kind) : batch_walk_kernel_128(G, kind);
+}
+
+// lookback sets of four chunks of one pair per workgroup (one wave each)
+__global__ __launch_bounds__(256) void k_batch_lookback(const BatchPair *__restrict__ pairs,
+                                                        const uint8_t *const *__restrict__ texts,
+                                                        const LookItem *__restrict__ items, uint32_t wave_bytes) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const LookItem &it = items[blockIdx.x];
+    const BatchPair &bp = pairs[it.pair];
+    const uint64_t c = (uint64_t)it.quad * 4u + (threadIdx.x >> 6);
+    if (c >= bp.la.nchunks) return;
+    LookArgs a = bp.la;
+    a.text = texts[it.pair];
+    lookback_chunk(a, c, smem + (threadIdx.x >> 6) * wave_bytes);
+}
+
+// walks started by a lookback pair (nsel 0: the chunk's whole set); runs
+// after the pair's result is written
+__global__ __launch_bounds__(256) void k_batch_look_stats(const BatchPair *__restrict__ pairs,
+                                                          const uint32_t *__restrict__ idx) {
+    const BatchPair &bp = pairs[idx[blockIdx.x]];
+    unsigned long long runs = 0;
+    for (uint64_t c = threadIdx.x; c < bp.w.nchunks; c += 256) {
+        uint32_t r = bp.w.nsel[c];
+        if (!r) {
+            const uint32_t cl = bp.w.map_cls[c] & 0x7fffu;
+            r = bp.ca.loff[cl + 1] - bp.ca.loff[cl];
+        }
+        runs += r;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) runs += (unsigned long long)__shfl_xor((long long)runs, o, 64);
+    __shared__ unsigned long long part[4];
+    if ((threadIdx.x & 63u) == 0) part[threadIdx.x >> 6] = runs;
+    __syncthreads();
+    if (threadIdx.x == 0) bp.out->spec_runs = part[0] + part[1] + part[2] + part[3];
 }
 
 // Automatic chunk length inside a batch: the other pairs supply the
@@ -80,6 +117,7 @@ static int batch_kind(const DeviceDfa &d) {
 struct BatchVariant {
     int kind = 0;
     uint32_t G = 0, tile = 0;
+    bool sel = false;        // lookback selections (WALK_SELECTED)
     uint32_t table_cap = 0;  // largest LDS table of its pairs (16-byte multiple)
     std::vector<WalkItem> items;
     uint64_t off_items = 0;
@@ -105,6 +143,10 @@ struct parem_batch_s {
     std::vector<parem::BatchVariant> variants;
     std::vector<parem::BatchLevel> levels;
     std::vector<uint32_t> empties;
+    std::vector<uint32_t> look_pairs;
+    std::vector<parem::LookItem> look_items;
+    uint32_t look_wave = 0;
+    uint64_t off_look_pairs = 0, off_look_items = 0;
     uint64_t off_empties = 0, off_pairs = 0, off_queue = 0, off_texts = 0, off_results = 0;
     uint64_t chunks = 0, text_bytes = 0, ws_bytes = 0, items = 0;
     uint8_t *d_meta = nullptr;
@@ -151,7 +193,7 @@ static parem_status batch_plan(const parem_handle *dfas, const uint64_t *lens, u
         if (d.device != b->device) return PAREM_EINVAL;
         b->dfas[i] = &d;
         parem_options o = opts ? opts[i] : d.opt;
-        if (o.kgram != 0 || o.reserved[0] || o.reserved[1]) return PAREM_EINVAL;
+        if (o.kgram != 0 || o.reserved || o.lookback > kLookMax) return PAREM_EINVAL;
         if (o.chunk_len == 0) o.chunk_len = batch_chunk_len(lens[i]);
         PlainPlan &p = b->plans[i];
         parem_status st = plan_chunks(d, lens[i], o, false, &p);
@@ -166,17 +208,24 @@ static parem_status batch_plan(const parem_handle *dfas, const uint64_t *lens, u
         ws_off[i] = ws;
         ws = align256(ws + p.bytes);
         const int kind = batch_kind(d);
+        const bool sel = p.look > 0;
+        if (sel) {
+            b->look_pairs.push_back(i);
+            for (uint64_t q4 = 0; q4 < (p.chunks + 3) / 4; ++q4) b->look_items.push_back(LookItem{i, (uint32_t)q4});
+            b->look_wave = std::max(b->look_wave, look_wave_bytes((d.Q + 1 + 31) / 32, p.look));
+        }
         int v = -1;
         for (size_t k = 0; k < b->variants.size(); ++k) {
             const BatchVariant &x = b->variants[k];
-            if (x.kind == kind && x.G == p.G && x.tile == p.tile) v = (int)k;
+            if (x.kind == kind && x.G == p.G && x.tile == p.tile && x.sel == sel) v = (int)k;
         }
         if (v < 0) {
             BatchVariant x;
             x.kind = kind;
             x.G = p.G;
             x.tile = p.tile;
-            x.fn = walk_kernel(p.G, p.tile, kind);
+            x.sel = sel;
+            x.fn = walk_kernel(p.G, p.tile, kind, sel);
             b->variants.push_back(x);
             v = (int)b->variants.size() - 1;
         }
@@ -251,6 +300,8 @@ static parem_status batch_plan(const parem_handle *dfas, const uint64_t *lens, u
     for (BatchVariant &x : b->variants) x.off_items = take(x.items.size() * sizeof(WalkItem));
     for (BatchLevel &lv : b->levels) lv.off_items = take(lv.items.size() * sizeof(ComposeItem));
     b->off_empties = take(b->empties.size() * 4);
+    b->off_look_pairs = take(b->look_pairs.size() * 4);
+    b->off_look_items = take(b->look_items.size() * sizeof(LookItem));
     b->off_queue = take(std::max<size_t>(b->variants.size(), 1) * 4);
     b->off_texts = take((uint64_t)n * 8);
     b->off_results = take((uint64_t)n * sizeof(parem_result));
@@ -280,6 +331,12 @@ static parem_status batch_plan(const parem_handle *dfas, const uint64_t *lens, u
         q.hot_rows = d.hot_rows;
         q.kg = d.kg;
         for (size_t k = 0; k < p.seg.size() && k < 2; ++k) q.seg[k] = seg_out(p, pws, k);
+        if (p.look) {
+            q.la = look_args(d, p, nullptr, pws);
+            q.w.sel = q.la.sel;
+            q.w.nsel = q.la.nsel;
+            q.w.sel_stride = kLookCap;
+        }
     }
     auto put = [&](uint64_t o, const void *src, size_t bytes) {
         return bytes == 0 || hipMemcpy(b->d_meta + o, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
@@ -289,6 +346,12 @@ static parem_status batch_plan(const parem_handle *dfas, const uint64_t *lens, u
     for (BatchLevel &lv : b->levels)
         ok = ok && put(lv.off_items, lv.items.data(), lv.items.size() * sizeof(ComposeItem));
     ok = ok && put(b->off_empties, b->empties.data(), b->empties.size() * 4);
+    ok = ok && put(b->off_look_pairs, b->look_pairs.data(), b->look_pairs.size() * 4);
+    ok = ok && put(b->off_look_items, b->look_items.data(), b->look_items.size() * sizeof(LookItem));
+    if (ok && b->look_wave * 4 > 64 * 1024 &&
+        hipFuncSetAttribute(reinterpret_cast<const void *>(k_batch_lookback), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(b->look_wave * 4)) != hipSuccess)
+        return PAREM_EUNSUPPORTED;
     return ok ? PAREM_OK : PAREM_EDEVICE;
 }
 
@@ -297,6 +360,10 @@ static parem_status batch_enqueue(const parem_batch_s *b, hipStream_t s) {
     const BatchPair *pairs = reinterpret_cast<const BatchPair *>(b->d_meta + b->off_pairs);
     const uint8_t *const *texts = reinterpret_cast<const uint8_t *const *>(b->d_meta + b->off_texts);
     uint32_t *queue = reinterpret_cast<uint32_t *>(b->d_meta + b->off_queue);
+    if (!b->look_items.empty())
+        hipLaunchKernelGGL(k_batch_lookback, dim3((uint32_t)b->look_items.size()), dim3(256), 4 * b->look_wave, s,
+                           pairs, texts, reinterpret_cast<const LookItem *>(b->d_meta + b->off_look_items),
+                           b->look_wave);
     if (!b->variants.empty()) {
         hipLaunchKernelGGL(k_batch_clear, dim3(1), dim3(64), 0, s, queue, (uint32_t)b->variants.size());
         for (size_t v = 0; v < b->variants.size(); ++v) {
@@ -317,6 +384,9 @@ static parem_status batch_enqueue(const parem_batch_s *b, hipStream_t s) {
         hipLaunchKernelGGL(k_batch_compose, dim3((uint32_t)lv.items.size()), dim3(kComposeThreads), lv.lds, s, pairs,
                            reinterpret_cast<const ComposeItem *>(b->d_meta + lv.off_items), (uint32_t)l);
     }
+    if (!b->look_pairs.empty())
+        hipLaunchKernelGGL(k_batch_look_stats, dim3((uint32_t)b->look_pairs.size()), dim3(256), 0, s, pairs,
+                           reinterpret_cast<const uint32_t *>(b->d_meta + b->off_look_pairs));
     return hipGetLastError() == hipSuccess ? PAREM_OK : PAREM_EDEVICE;
 }
 

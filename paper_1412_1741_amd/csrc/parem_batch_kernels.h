@@ -20,6 +20,12 @@ struct BatchPair {
     ComposeArgs ca;
     SegOut seg[2];  // ping-pong segment buffers
     parem_result *out;
+    LookArgs la;    // lookback sets (la.K == 0: Algorithm 1's sets); la.text unused
+};
+
+struct LookItem {
+    uint32_t pair;
+    uint32_t quad;  // chunks 4 * quad ... 4 * quad + 3 of the pair
 };
 
 struct WalkItem {
@@ -37,7 +43,7 @@ struct ComposeItem {
 // walk kernel variants: the table layout of the pairs they serve
 enum BatchKind : int { BK_BYTE_LDS = 0, BK_BYTE_GLOBAL = 1, BK_KGRAM1 = 2, BK_KGRAM2 = 3, BK_KGRAM3 = 4, BK_HOT = 5 };
 
-template <int G, uint32_t TILE, int KIND>
+template <int G, uint32_t TILE, int KIND, int MODE>
 __global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_batch_walk(
     const BatchPair *__restrict__ pairs, const uint8_t *const *__restrict__ texts, const WalkItem *__restrict__ items,
     uint32_t nitems, uint32_t *__restrict__ queue, uint32_t table_cap) {
@@ -56,7 +62,7 @@ __global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_batch_walk(
         const uint64_t c0 = (uint64_t)__builtin_amdgcn_readfirstlane(items[it].blk) * kWalkThreads;
         const BatchPair &bp = pairs[pi];
         WalkArgs a = bp.w;
-        a.text = texts[pi];
+        a.text = texts[pi];  // with MODE == WALK_SELECTED, a.sel / a.nsel hold the lookback sets
         if constexpr (KIND != BK_BYTE_GLOBAL) {
             if (pi != staged) {
                 stage_table(reinterpret_cast<uint4 *>(smem), reinterpret_cast<const uint4 *>(bp.table),
@@ -66,17 +72,17 @@ __global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_batch_walk(
         }
         if constexpr (KIND == BK_BYTE_LDS) {
             ByteStep<uint8_t, kByteLdsRow> st{smem};
-            walk_chunk<G, ByteStep<uint8_t, kByteLdsRow>, true, TILE, WALK_ALL>(st, a, smem + table_cap, c0);
+            walk_chunk<G, ByteStep<uint8_t, kByteLdsRow>, true, TILE, MODE>(st, a, smem + table_cap, c0);
         } else if constexpr (KIND == BK_BYTE_GLOBAL) {
             ByteStep<uint16_t, 256> st{reinterpret_cast<const uint16_t *>(bp.table)};
-            walk_chunk<G, ByteStep<uint16_t, 256>, true, TILE, WALK_ALL>(st, a, smem, c0);
+            walk_chunk<G, ByteStep<uint16_t, 256>, true, TILE, MODE>(st, a, smem, c0);
         } else if constexpr (KIND == BK_HOT) {
             const uint16_t *hot = reinterpret_cast<const uint16_t *>(smem);
             HotStep st{hot, hot + (bp.hot_rows + 1) * kHotRow, bp.full, bp.enc, bp.hot_rows};
-            walk_chunk<G, HotStep, true, TILE, WALK_ALL>(st, a, smem + table_cap, c0);
+            walk_chunk<G, HotStep, true, TILE, MODE>(st, a, smem + table_cap, c0);
         } else {
             KgStep<KIND - 1> st{smem, bp.kg};
-            walk_chunk<G, KgStep<KIND - 1>, true, TILE, WALK_ALL>(st, a, smem + table_cap, c0);
+            walk_chunk<G, KgStep<KIND - 1>, true, TILE, MODE>(st, a, smem + table_cap, c0);
         }
     }
 }
@@ -84,29 +90,31 @@ __global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_batch_walk(
 using WalkKernel = void (*)(const BatchPair *, const uint8_t *const *, const WalkItem *, uint32_t, uint32_t *,
                             uint32_t);
 
-template <int G, uint32_t TILE>
+template <int G, uint32_t TILE, int MODE>
 WalkKernel walk_kernel_kind(int kind) {
     switch (kind) {
-        case BK_BYTE_LDS: return k_batch_walk<G, TILE, BK_BYTE_LDS>;
-        case BK_BYTE_GLOBAL: return k_batch_walk<G, TILE, BK_BYTE_GLOBAL>;
-        case BK_KGRAM1: return k_batch_walk<G, TILE, BK_KGRAM1>;
-        case BK_KGRAM2: return k_batch_walk<G, TILE, BK_KGRAM2>;
-        case BK_KGRAM3: return k_batch_walk<G, TILE, BK_KGRAM3>;
-        default: return k_batch_walk<G, TILE, BK_HOT>;
+        case BK_BYTE_LDS: return k_batch_walk<G, TILE, BK_BYTE_LDS, MODE>;
+        case BK_BYTE_GLOBAL: return k_batch_walk<G, TILE, BK_BYTE_GLOBAL, MODE>;
+        case BK_KGRAM1: return k_batch_walk<G, TILE, BK_KGRAM1, MODE>;
+        case BK_KGRAM2: return k_batch_walk<G, TILE, BK_KGRAM2, MODE>;
+        case BK_KGRAM3: return k_batch_walk<G, TILE, BK_KGRAM3, MODE>;
+        default: return k_batch_walk<G, TILE, BK_HOT, MODE>;
     }
 }
 
-template <uint32_t TILE>
+template <uint32_t TILE, int MODE>
 WalkKernel walk_kernel_tile(uint32_t G, int kind) {
     switch (G) {
-        case 4: return walk_kernel_kind<4, TILE>(kind);
-        case 8: return walk_kernel_kind<8, TILE>(kind);
-        default: return walk_kernel_kind<16, TILE>(kind);
+        case 4: return walk_kernel_kind<4, TILE, MODE>(kind);
+        case 8: return walk_kernel_kind<8, TILE, MODE>(kind);
+        default: return walk_kernel_kind<16, TILE, MODE>(kind);
     }
 }
 
-// defined in the per-tile translation units
+// defined in the per-(tile, mode) translation units
 WalkKernel batch_walk_kernel_64(uint32_t G, int kind);
 WalkKernel batch_walk_kernel_128(uint32_t G, int kind);
+WalkKernel batch_walk_kernel_64_sel(uint32_t G, int kind);
+WalkKernel batch_walk_kernel_128_sel(uint32_t G, int kind);
 
 }  // namespace parem

@@ -1,0 +1,6 @@
+// Instantiation unit: batched walk kernels with 64-byte staged tiles, lookback selections.
+#include "parem_batch_kernels.h"
+
+namespace parem {
+WalkKernel batch_walk_kernel_64_sel(uint32_t G, int kind) { return walk_kernel_tile<64, WALK_SELECTED>(G, kind); }
+}  // namespace parem

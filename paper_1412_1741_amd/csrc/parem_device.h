@@ -476,8 +476,8 @@ struct WalkArgs {
     uint32_t *map;        // [RM][nchunks] packed end | count << 16 (end 0xffff: not walked)
     uint16_t *map_cls;    // [nchunks] class, bit 15 = ends differ
     uint16_t *map_lead;   // [nchunks] end state of the leader walk
-    const uint16_t *sel;  // learned selection: positions [nchunks][sel_stride] (null: whole set)
-    const uint8_t *nsel;  // [nchunks] number of selected positions
+    const uint16_t *sel;  // selection: positions [nchunks][sel_stride] in the chunk's set
+    const uint8_t *nsel;  // [nchunks] number of selected positions (0: the whole set)
     uint32_t sel_stride;
     const uint8_t *redo;  // re-walk mode: only chunks with redo[c] != 0, from the whole set
 };
@@ -502,9 +502,13 @@ __device__ __forceinline__ void walk_chunk(const ST &st, const WalkArgs &a, uint
     Positions pos{nullptr};
     uint32_t nwalk = nlist;
     if constexpr (MODE == WALK_SELECTED) {
+        // nsel 0: this chunk walks its whole set
         if (active) {
-            pos.sel = a.sel + c * a.sel_stride;
-            nwalk = a.nsel[c];
+            const uint32_t ns = a.nsel[c];
+            if (ns) {
+                pos.sel = a.sel + c * a.sel_stride;
+                nwalk = ns;
+            }
         } else {
             nwalk = 1;
         }
@@ -533,7 +537,8 @@ __device__ __forceinline__ void walk_chunk(const ST &st, const WalkArgs &a, uint
     uint32_t *out = a.map + c;
     if constexpr (MODE == WALK_SELECTED) {
         // entries not walked are marked absent
-        for (uint32_t j = 0; j < nlist; ++j) out[(uint64_t)j * a.nchunks] = kAbsent16;
+        if (pos.sel)
+            for (uint32_t j = 0; j < nlist; ++j) out[(uint64_t)j * a.nchunks] = kAbsent16;
     }
     walk_direct<G, ST, ALIGNED>(st, w, p, ntiles * TILE, len, true, bad);
     bool nonuni = store_pass<G>(st, w, pos, 1, nwalk, true, lead_end, lead_cnt, out, a.nchunks);
@@ -552,6 +557,138 @@ __device__ __forceinline__ void walk_chunk(const ST &st, const WalkArgs &a, uint
     // bit 15: the walks end in more than one state
     a.map_cls[c] = (uint16_t)(cls | (nonuni ? 0x8000u : 0u));
     a.map_lead[c] = (uint16_t)lead_end;
+}
+
+// ---------------------------------------------------------------------------
+// lookback sets: chunk c >= 1 starts in some state of
+// B_c = delta*(Q, t[b-K .. b-1]) (b = c*L), the image of every state under the
+// K bytes before it; B_c is a subset of R_c (its last step is the column of
+// t[b-1]) and holds the true entry state. One wave per chunk: the set is a
+// bitmap in LDS mapped byte by byte; the result is the ascending positions of
+// B_c in R_c's sorted list, or nsel 0 (walk all of R_c) when |B_c| > cap.
+// ---------------------------------------------------------------------------
+
+struct LookArgs {
+    const uint8_t *text;
+    uint32_t L;
+    uint64_t nchunks;
+    uint32_t K;             // lookback bytes, 1 <= K <= L
+    uint32_t Q, A;
+    uint32_t words;         // bitmap words: ceil((Q + 1) / 32)
+    const uint8_t *cls;     // byte -> class (A or more: invalid)
+    const uint16_t *next;   // (Q+1) x A next state by class
+    const uint16_t *inv;    // (A+2) x (Q+1) position of a state in a class list
+    uint16_t *sel;          // [nchunks][kLookCap]
+    uint8_t *nsel;          // [nchunks]
+};
+
+// LDS bytes one wave of the lookback needs
+__host__ __device__ inline uint32_t look_wave_bytes(uint32_t words, uint32_t K) {
+    return (2u * words * 4u + 256u + K + 15u) & ~15u;
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o, 64);
+    return v;
+}
+
+// the wave's lanes compute chunk c's lookback set; `ws` is the wave's LDS
+__device__ __forceinline__ void lookback_chunk(const LookArgs &a, uint64_t c, uint8_t *ws) {
+    const uint32_t lane = threadIdx.x & 63u;
+    if (c == 0) {
+        if (lane == 0) {
+            a.nsel[0] = 1;  // chunk 0: {q0}, position 0 of the start class
+            a.sel[0] = 0;
+        }
+        return;
+    }
+    const uint32_t W = a.words;
+    uint32_t *cur = reinterpret_cast<uint32_t *>(ws);
+    uint32_t *nxt = cur + W;
+    uint8_t *cl = reinterpret_cast<uint8_t *>(nxt + W);
+    uint8_t *win = cl + 256;
+    const uint64_t b = c * (uint64_t)a.L;
+    const uint32_t K = (uint32_t)min((uint64_t)a.K, b);
+    const uint8_t *src = a.text + (b - K);
+    for (uint32_t k = lane; k < K; k += 64) win[k] = src[k];
+    for (uint32_t x = lane; x < 256; x += 64) cl[x] = a.cls[x];
+    for (uint32_t w = lane; w < W; w += 64) {
+        const uint32_t lo = w * 32u;  // states 0 .. Q-1 (not the sentinel)
+        cur[w] = lo + 32u <= a.Q ? 0xffffffffu : (a.Q > lo ? (1u << (a.Q - lo)) - 1u : 0u);
+        nxt[w] = 0;
+    }
+    wave_sync();
+    bool invalid = false;
+    for (uint32_t k = 0; k < K; ++k) {
+        const uint32_t col = cl[win[k]];
+        if (col >= a.A) {  // a byte outside the alphabet: the match fails anyway
+            invalid = true;
+            break;
+        }
+        for (uint32_t w = lane; w < W; w += 64) {
+            uint32_t bits = cur[w];
+            if (bits) {
+                cur[w] = 0;
+                do {
+                    const uint32_t q = w * 32u + (uint32_t)__builtin_ctz(bits);
+                    bits &= bits - 1u;
+                    const uint32_t nq = a.next[q * a.A + col];
+                    atomicOr(&nxt[nq >> 5], 1u << (nq & 31u));
+                } while (bits);
+            }
+        }
+        wave_sync();
+        uint32_t *t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    uint16_t *out = a.sel + c * kLookCap;
+    if (invalid) {
+        if (lane == 0) {
+            a.nsel[c] = 1;  // any state: the walk through the invalid byte ends in the sentinel
+            out[0] = 0;
+        }
+        return;
+    }
+    const uint32_t per = (W + 63u) / 64u;
+    const uint32_t w0 = min(lane * per, W), w1 = min(w0 + per, W);
+    uint32_t mine = 0;
+    for (uint32_t w = w0; w < w1; ++w) mine += (uint32_t)__builtin_popcount(cur[w]);
+    const uint32_t total = wave_sum(mine);
+    if (total > kLookCap) {
+        if (lane == 0) a.nsel[c] = 0;
+        return;
+    }
+    // exclusive prefix over lanes: ascending state order across lanes
+    uint32_t off = mine;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t v = (uint32_t)__shfl_up((int)off, o, 64);
+        if ((int)lane >= o) off += v;
+    }
+    off -= mine;
+    const uint32_t cls_prev = cl[win[K - 1]];
+    const uint16_t *pos = a.inv + (size_t)cls_prev * (a.Q + 1);
+    uint32_t missing = 0;
+    for (uint32_t w = w0; w < w1; ++w) {
+        uint32_t bits = cur[w];
+        while (bits) {
+            const uint32_t q = w * 32u + (uint32_t)__builtin_ctz(bits);
+            bits &= bits - 1u;
+            const uint32_t p = pos[q];
+            missing |= p == 0xffffu;
+            out[off++] = (uint16_t)p;
+        }
+    }
+    missing = wave_sum(missing);
+    if (lane == 0) a.nsel[c] = missing ? 0 : (uint8_t)total;  // a state outside R_c cannot occur
 }
 
 // copy the table into LDS with four 16-byte loads in flight per thread
@@ -1021,6 +1158,23 @@ inline WalkArgs walk_args(const DeviceDfa &d, const PlainPlan &p, const uint8_t 
     a.map = reinterpret_cast<uint32_t *>(ws + p.off_map);
     a.map_cls = reinterpret_cast<uint16_t *>(ws + p.off_mcls);
     a.map_lead = reinterpret_cast<uint16_t *>(ws + p.off_mlead);
+    return a;
+}
+
+inline LookArgs look_args(const DeviceDfa &d, const PlainPlan &p, const uint8_t *text, uint8_t *ws) {
+    LookArgs a{};
+    a.text = text;
+    a.L = p.L;
+    a.nchunks = p.chunks;
+    a.K = p.look;
+    a.Q = d.Q;
+    a.A = d.A;
+    a.words = (d.Q + 1 + 31) / 32;
+    a.cls = d.d_cls;
+    a.next = d.d_next;
+    a.inv = d.d_inv;
+    a.sel = reinterpret_cast<uint16_t *>(ws + p.off_sel);
+    a.nsel = ws + p.off_nsel;
     return a;
 }
 

@@ -64,6 +64,7 @@ struct DeviceDfa {
     uint32_t inv_lds = 0;            // bytes of d_inv staged in LDS by the compose kernels (0: read from L2)
     // hot-row layout: d_table is the LDS image (hot rows, then their state ids)
     uint16_t *d_full = nullptr;      // (Q+1) x 256 byte table with encoded destinations
+    uint16_t *d_next = nullptr;      // [(Q+1) x A] next state by class (lookback sets); row Q: the sentinel
     uint16_t *d_enc = nullptr;       // [Q+1] encoded id of each state (slot when hot, 0x4000 | id else)
     uint32_t hot_rows = 0;
 };
@@ -118,6 +119,7 @@ struct PlainPlan {
     uint32_t tile = 0;       // staged tile bytes per chunk (64 or 128)
     uint32_t merge = 1;      // 0: speculated runs are never merged
     uint32_t m = 0;          // learned: states walked per chunk
+    uint32_t look = 0;       // lookback bytes (0: the speculated sets of Algorithm 1)
     bool keep = false;       // keep every composition level (down-sweep)
     std::vector<uint64_t> levels;  // maps after each composition level
     struct Seg {
@@ -134,6 +136,10 @@ constexpr uint32_t kByteLdsRow = 260;  // row stride of the LDS byte table
 constexpr uint32_t kMaxChunk = 32768;  // chunk maps pack a count < 2^16 beside the end state
 
 constexpr int kCoverRounds = 3;         // coverage rounds before every incomplete chunk is walked again
+
+constexpr uint32_t kLookMax = 4096;     // longest lookback window
+constexpr uint32_t kLookCap = 64;       // largest lookback set walked as a selection
+constexpr uint32_t kLookStates = 16384; // lookback sets need Q + 1 <= this
 
 // chunking, map width, group, tile and workspace carving of one text under options o
 parem_status plan_chunks(const DeviceDfa &d, uint64_t len, const parem_options &o, bool keep, PlainPlan *p);

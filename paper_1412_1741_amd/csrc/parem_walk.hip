@@ -164,6 +164,33 @@ __global__ void k_learned_stats(const uint8_t *__restrict__ nsel, const uint8_t 
     }
 }
 
+// walks started under lookback selection (nsel 0: the chunk's whole set)
+__global__ void k_look_stats(const uint8_t *__restrict__ nsel, const uint16_t *__restrict__ map_cls,
+                             const uint32_t *__restrict__ loff, uint64_t C, unsigned long long *__restrict__ acc) {
+    const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long runs = 0;
+    if (c < C) {
+        runs = nsel[c];
+        if (!runs) {
+            const uint32_t cl = map_cls[c] & 0x7fffu;
+            runs = loff[cl + 1] - loff[cl];
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) runs += (unsigned long long)__shfl_xor((long long)runs, o, 64);
+    __shared__ unsigned long long part[4];
+    if ((threadIdx.x & 63u) == 0) part[threadIdx.x >> 6] = runs;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(&acc[0], part[0] + part[1] + part[2] + part[3]);
+}
+
+__global__ __launch_bounds__(256) void k_lookback(LookArgs a, uint32_t wave_bytes) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const uint64_t c = (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (c >= a.nchunks) return;  // whole waves leave; no workgroup barrier follows
+    lookback_chunk(a, c, smem + (threadIdx.x >> 6) * wave_bytes);
+}
+
 __global__ void k_learned_total(const unsigned long long *__restrict__ acc, parem_result *__restrict__ result) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         result->spec_runs = acc[0];
@@ -266,6 +293,7 @@ parem_status plan_chunks(const DeviceDfa &d, uint64_t len, const parem_options &
     if (L % 64 != 0 || L == 0 || L > kMaxChunk) return PAREM_EINVAL;
     q.L = L;
     q.chunks = (len + L - 1) / L;
+    q.look = (o.lookback && d.d_next && d.d_inv) ? std::min<uint32_t>(o.lookback, L) : 0u;
     q.tile = o.tile ? o.tile : 128;
     q.merge = o.no_merge ? 0u : 1u;
     if (q.tile != 64 && q.tile != 128) return PAREM_EINVAL;
@@ -286,6 +314,11 @@ parem_status plan_chunks(const DeviceDfa &d, uint64_t len, const parem_options &
     q.off_map = take(ch * q.RM * 4);  // packed chunk maps
     q.off_mcls = take(ch * 2);
     q.off_mlead = take(ch * 2);
+    if (q.look) {
+        q.off_sel = take(ch * kLookCap * 2);  // lookback selection (positions in R_c)
+        q.off_nsel = take(ch);
+        q.off_flags = take(64);               // speculated-walk tally
+    }
     // segment levels: kept separately (down-sweep) or two ping-pong buffers
     uint64_t m = q.chunks;
     q.levels.clear();
@@ -364,17 +397,36 @@ parem_status launch_plain(const DeviceDfa &d, const PlainPlan &p, const uint8_t 
     uint8_t *ws = reinterpret_cast<uint8_t *>(d_ws);
     const bool aligned = (reinterpret_cast<uintptr_t>(d_text) & 15u) == 0;
     if (ev_begin && hipEventRecord(ev_begin, stream) != hipSuccess) return PAREM_EDEVICE;
-    const WalkArgs a = walk_args(d, p, d_text, ws);
-    launch_walk<WALK_ALL>(d, p, a, stream, aligned);
+    WalkArgs a = walk_args(d, p, d_text, ws);
+    if (p.look) {
+        const LookArgs la = look_args(d, p, d_text, ws);
+        const uint32_t wb = look_wave_bytes(la.words, la.K);
+        hipLaunchKernelGGL(k_lookback, dim3((uint32_t)((p.chunks + 3) / 4)), dim3(256), 4 * wb, stream, la, wb);
+        a.sel = la.sel;
+        a.nsel = la.nsel;
+        a.sel_stride = kLookCap;
+        launch_walk<WALK_SELECTED>(d, p, a, stream, aligned);
+    } else {
+        launch_walk<WALK_ALL>(d, p, a, stream, aligned);
+    }
     if (hipGetLastError() != hipSuccess) return PAREM_EDEVICE;
     if (ev_end && hipEventRecord(ev_end, stream) != hipSuccess) return PAREM_EDEVICE;
-    return launch_compose(d, p, ws, stream, d_out);
+    parem_status st = launch_compose(d, p, ws, stream, d_out);
+    if (st != PAREM_OK || !p.look) return st;
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(ws + p.off_flags);
+    hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(64), 0, stream, reinterpret_cast<uint32_t *>(acc), 4u);
+    hipLaunchKernelGGL(k_look_stats, dim3((uint32_t)((p.chunks + 255) / 256)), dim3(256), 0, stream, a.nsel,
+                       a.map_cls, d.d_loff, p.chunks, acc);
+    hipLaunchKernelGGL(k_learned_total, dim3(1), dim3(64), 0, stream, acc, d_out);
+    return hipGetLastError() == hipSuccess ? PAREM_OK : PAREM_EDEVICE;
 }
 
 // ---- boundary states ----
 
 parem_status plan_boundary(const DeviceDfa &d, uint64_t len, uint32_t L, PlainPlan *p) {
-    parem_status st = plan_chunks(d, len, with_chunk_len(d.opt, L), true, p);
+    parem_options o = with_chunk_len(d.opt, L);
+    o.lookback = 0;  // the down-sweep reads the walked maps of Algorithm 1's sets
+    parem_status st = plan_chunks(d, len, o, true, p);
     if (st != PAREM_OK) return st;
     // entry arrays per level (level 0 is the caller's output)
     uint64_t off = p->bytes;
@@ -425,7 +477,9 @@ parem_status launch_boundary(const DeviceDfa &d, const PlainPlan &p, const uint8
 // ---- learned speculation ----
 
 parem_status plan_learned(const DeviceDfa &d, const Proposal &pr, uint64_t len, uint32_t m, PlainPlan *p) {
-    parem_status st = plan_chunks(d, len, d.opt, false, p);
+    parem_options o = d.opt;
+    o.lookback = 0;  // the proposal selects within Algorithm 1's sets
+    parem_status st = plan_chunks(d, len, o, false, p);
     if (st != PAREM_OK) return st;
     uint64_t off = p->bytes;
     const uint64_t ch = std::max<uint64_t>(p->chunks, 1);

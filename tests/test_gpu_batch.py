@@ -84,7 +84,11 @@ def check(pairs, got, name, opts=None):
             f"{name}: pair {i} Q={dfa.num_states} A={dfa.alphabet_size} n={text.size}"
         L = (opts[i].get("chunk_len") if opts else 0) or batch_chunk_len(text.size)
         assert r.chunks == ((text.size + L - 1) // L if text.size else 0), f"{name}: pair {i}"
-        assert r.spec_runs == spec_runs(dfa, text, L), f"{name}: pair {i}"
+        if opts and opts[i].get("lookback"):
+            assert r.spec_runs <= spec_runs(dfa, text, L), f"{name}: pair {i}"
+            assert r.spec_runs >= r.chunks
+        else:
+            assert r.spec_runs == spec_runs(dfa, text, L), f"{name}: pair {i}"
         assert r.rerun_chunks == 0
 
 
@@ -134,7 +138,8 @@ def test_batch_per_pair_options():
     for _ in pairs:
         opts.append({"chunk_len": int(rng.choice([64, 128, 256, 1024, 4096])),
                      "group": int(rng.choice([4, 8, 16])), "tile": int(rng.choice([64, 128])),
-                     "no_merge": int(rng.random() < 0.2)})
+                     "no_merge": int(rng.random() < 0.2),
+                     "lookback": int(rng.choice([0, 0, 1, 16, 256, 4096]))})
     say(f"[case] per-pair options")
     b = P.Batch(ms, [t.size for _, t in pairs], opts)
     got = b.run(to_device([t for _, t in pairs]))
@@ -142,8 +147,8 @@ def test_batch_per_pair_options():
     kinds = set()
     for (d, t), m, o in zip(pairs, ms, opts):
         if t.size:
-            kinds.add((m.describe()["layout"], m.describe()["kgram"], o["group"], o["tile"]))
-    assert b.describe()["walk_launches"] >= len({(k[2], k[3]) for k in kinds})
+            kinds.add((m.describe()["layout"], m.describe()["kgram"], o["group"], o["tile"], o["lookback"] > 0))
+    assert b.describe()["walk_launches"] >= len({(k[2], k[3], k[4]) for k in kinds})
 
 
 def test_batch_invalid_byte_and_errors():
@@ -203,7 +208,8 @@ def test_tune_candidates_agree():
     text = W.uniform_text(rng, dfa.alphabet, 1 << 20)
     m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting)
     dev = to_device([text])[0]
-    cands = [{"chunk_len": L, "group": g, "tile": t} for L in (1024, 4096) for g in (4, 8, 16) for t in (64, 128)]
+    cands = [{"chunk_len": L, "group": g, "tile": t, "lookback": k} for L in (1024, 4096) for g in (4, 8, 16)
+             for t in (64, 128) for k in (0, 64)]
     cands.append({"chunk_len": 1 << 16})  # above the maximum: not runnable
     say("[case] parem_tune")
     ms_, best = P.parem_tune(m.handle, dev.data_ptr(), text.size, 16, cands, 2,

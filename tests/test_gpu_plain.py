@@ -40,7 +40,7 @@ def expected_spec_runs(dfa, text, L):
     return 1 + int(sizes.sum())
 
 
-def run_case(name, dfa, text, offset=0, **opts):
+def run_case(name, dfa, text, offset=0, check_spec=True, **opts):
     say(f"[case] {name}: Q={dfa.num_states} A={dfa.alphabet_size} n={text.size} opts={opts} off={offset}")
     m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, **opts)
     try:
@@ -52,7 +52,7 @@ def run_case(name, dfa, text, offset=0, **opts):
         got = m.match(dev)
         assert (got.final_state, got.accept, got.count) == (want.final_state, want.accept, want.count), name
         L = opts.get("chunk_len") or None
-        if L is not None:
+        if L is not None and check_spec:
             assert got.chunks == (text.size + L - 1) // L
             assert got.spec_runs == expected_spec_runs(dfa, text, L)
         assert got.rerun_chunks == 0
@@ -304,3 +304,61 @@ def test_nonsynchronizing_dfa():
     text = np.frombuffer(b"abcr", dtype=np.uint8)[rng.choice(4, size=300000, p=probs)]
     for lay in all_layouts():
         run_case(f"mixed layout={lay}", dfa2, text, chunk_len=128, layout=lay, group=8)
+
+
+def lookback_runs(dfa, text, L, K, cap=64):
+    """Walks started with lookback sets: |B_c| when at most cap, else |R_c|
+    (B_c: image of every state under the K bytes before chunk c)."""
+    col = np.full(256, -1, dtype=np.int64)
+    col[np.frombuffer(dfa.alphabet, dtype=np.uint8)] = np.arange(dfa.alphabet_size)
+    T = dfa.table.astype(np.int64)
+    chunks = (text.size + L - 1) // L
+    runs = 1
+    for c in range(1, chunks):
+        b = c * L
+        k = min(K, b, L)
+        s = np.arange(dfa.num_states)
+        for x in text[b - k:b]:
+            s = np.unique(T[s, col[x]])
+        r = np.unique(T[:, col[text[b - 1]]]).size
+        runs += s.size if s.size <= cap else r
+    return runs
+
+
+@pytest.mark.parametrize("K", [1, 7, 64, 700, 4096])
+def test_lookback_sets(K):
+    rng = np.random.default_rng(900 + K)
+    dense = W.random_dense_dfa(rng, 700, bytes(rng.choice(256, size=4, replace=False).astype(np.uint8)),
+                               num_accepting=50)
+    sym = rng.choice(256, size=20, replace=False).astype(np.uint8)
+    sparse = W.sparse_dfa(rng, 1500, bytes(sym), 4, 16, rng.choice(1500, size=24, replace=False))
+    dna, _ = W.config2(n=1024)
+    cases = [("dense", dense), ("sparse", sparse), ("dna", dna)]
+    for name, dfa in cases:
+        text = W.uniform_text(rng, dfa.alphabet, (1 << 19) + 33)
+        for L, G in ((1024, 8), (8192, 16), (64, 4)):
+            got = run_case(f"lookback K={K} {name} L={L}", dfa, text, chunk_len=L, lookback=K, group=G,
+                           check_spec=False)
+            if L >= 1024 and K <= 64:
+                assert got.spec_runs == lookback_runs(dfa, text, L, K), (name, L, K)
+    # small texts: every chunk's set checked
+    small = W.uniform_text(rng, dense.alphabet, 3000)
+    got = run_case(f"lookback K={K} small", dense, small, chunk_len=128, lookback=K, check_spec=False)
+    assert got.spec_runs == lookback_runs(dense, small, 128, K)
+
+
+def test_lookback_invalid_bytes():
+    rng = np.random.default_rng(31)
+    dfa = W.random_dense_dfa(rng, 300, b"ACGT", num_accepting=20)
+    base = W.uniform_text(rng, dfa.alphabet, 50_000)
+    for pos in (0, 1, 1023, 1024, 1025, 2047, 30_000, 49_999):
+        text = base.copy()
+        text[pos] = ord("x")
+        for K in (1, 16, 512):
+            say(f"[case] lookback invalid pos={pos} K={K}")
+            m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, chunk_len=1024, lookback=K)
+            dev = torch.from_numpy(text).cuda()
+            with pytest.raises(P.ParemError) as e:
+                m.match(dev)
+            assert e.value.status == P.PAREM_ESYMBOL
+            m.close()
