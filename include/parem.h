@@ -52,8 +52,10 @@ enum {
     PAREM_LAYOUT_BYTE_LDS = 1,   /* (Q+1) x 256 byte-indexed table in LDS       */
     PAREM_LAYOUT_BYTE_GLOBAL = 2,/* same table read through L2 (large tables)   */
     PAREM_LAYOUT_KGRAM_LDS = 3,  /* k-symbol stride table in LDS (small alphabets) */
-    PAREM_LAYOUT_HOT_LDS = 4     /* rows of the most visited states in LDS, the
+    PAREM_LAYOUT_HOT_LDS = 4,    /* rows of the most visited states in LDS, the
                                     others read through L2 (up to 16383 states) */
+    PAREM_LAYOUT_CLASS_LDS = 5   /* (Q+1) x (A+1) table indexed by column, plus the
+                                    byte-to-column map, in LDS (up to 48 KiB) */
 };
 
 typedef struct {
@@ -68,11 +70,11 @@ typedef struct {
     uint32_t lookback;    /* 0 (default): chunk c is walked from R_c, the image of
                              the column of the byte before it (Algorithm 1).
                              K > 0: from the image of every state under the K
-                             bytes before the chunk (K capped at the chunk
-                             length and at the chunk's offset), a subset of R_c
-                             that still holds the true entry state, so results
-                             are identical; chunks whose image has more than 64
-                             states use R_c. At most 4096; needs Q < 16384.   */
+                             bytes before the chunk (K capped at the chunk's
+                             offset), a subset of R_c that still holds the true
+                             entry state, so results are identical; chunks
+                             whose image has more than 64 states use R_c. At
+                             most 4096; ignored when Q >= 16384.              */
     uint32_t reserved;    /* must be zero                                        */
 } parem_options;
 

@@ -8,15 +8,15 @@ in it and times candidates with ``parem_tune`` (a batch of copies of that
 pair, replayed from a HIP graph), in two rounds:
 
   1. every table layout the DFA can use x speculated sets (Algorithm 1's,
-     or lookback sets over 32 or 512 bytes), at the batch's automatic chunk
+     or lookback sets over 32, 256 or 2048 bytes), at the batch's automatic chunk
      length, 8 walks in lockstep and 128-byte tiles;
-  2. for the winning layout and sets: chunk lengths {1, 4, 16} x the
-     automatic one (clipped to 64 .. 32768 and to the text) x lockstep
+  2. for the winning layout and sets: chunk lengths {1/4, 1, 4} x the
+     automatic one (clipped to 64 .. 8192 and to the text) x lockstep
      groups {4, 8, 16} x tiles {64, 128}.
 
 Texts shorter than ``min_tune_bytes`` keep the defaults (the layout the
-compile step picks, the automatic chunk length): they carry a negligible share
-of the bytes. Choices persist in a JSON cache keyed by class, so a workload is
+compile step picks, the automatic chunk length, lookback sets when a column
+image is wide): they carry a negligible share of the bytes. Choices persist in a JSON cache keyed by class, so a workload is
 tuned once per machine; ``seconds`` reports the time spent measuring.
 
 Every candidate computes the same result (the sequential run): only speed
@@ -29,9 +29,15 @@ import math
 import os
 import time
 
-from . import LAYOUT_AUTO, LAYOUT_BYTE_GLOBAL, LAYOUT_BYTE_LDS, LAYOUT_KGRAM_LDS, Matcher, parem_tune
+import numpy as np
 
-MAX_CHUNK = 32768
+from . import (LAYOUT_AUTO, LAYOUT_BYTE_GLOBAL, LAYOUT_BYTE_LDS, LAYOUT_CLASS_LDS, LAYOUT_HOT_LDS, LAYOUT_KGRAM_LDS,
+               Matcher, parem_tune)
+
+# Inside a batch a work item (256 chunks, one lane each) takes about as long
+# as one lane needs for one chunk; longer chunks would raise throughput in
+# isolation but leave a few long items at the end of the run.
+MAX_CHUNK = 8192
 
 
 def batch_chunk_len(n: int) -> int:
@@ -51,7 +57,7 @@ def size_class(num_states: int, alphabet_size: int, n: int) -> str:
 
 
 class Autotuner:
-    def __init__(self, cache_path: str | None = None, min_tune_bytes: int = 1 << 20, target_bytes: int = 256 << 20,
+    def __init__(self, cache_path: str | None = None, min_tune_bytes: int = 16 << 10, target_bytes: int = 1 << 30,
                  reps: int = 2, max_copies: int = 256, measure: bool = True, log=None):
         self.cache_path = cache_path
         self.log = log
@@ -90,11 +96,8 @@ class Autotuner:
     def tune_pair(self, dfa, text) -> dict:
         """Measure the candidates for one (DFA, device text) pair."""
         n = text.numel()
-        layouts = [LAYOUT_BYTE_GLOBAL]
-        if dfa.num_states + 1 <= 128:
-            layouts.append(LAYOUT_BYTE_LDS)
         matchers = {}
-        for lay in layouts + [LAYOUT_KGRAM_LDS]:
+        for lay in (LAYOUT_BYTE_GLOBAL, LAYOUT_BYTE_LDS, LAYOUT_KGRAM_LDS, LAYOUT_CLASS_LDS, LAYOUT_HOT_LDS):
             m = Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, layout=lay)
             if m.describe()["layout"] == lay:
                 matchers[lay] = m
@@ -103,12 +106,12 @@ class Autotuner:
         L0 = batch_chunk_len(n)
         best = None
         for lay, m in matchers.items():
-            cands = [{"chunk_len": L0, "group": 8, "tile": 128, "lookback": k} for k in (0, 32, 512)]
+            cands = [{"chunk_len": L0, "group": 8, "tile": 128, "lookback": k} for k in (0, 32, 256, 2048)]
             ms, b = self._time(m, text, cands)
             if ms[b] > 0 and (best is None or ms[b] < best[0]):
                 best = (ms[b], lay, cands[b]["lookback"])
         _, lay, k = best
-        Ls = sorted({min(MAX_CHUNK, max(64, L0 * f)) for f in (1, 4, 16)})
+        Ls = sorted({min(MAX_CHUNK, max(64, int(L0 * f))) for f in (0.25, 1, 4)})
         Ls = [L for L in Ls if L == L0 or L <= max(64, n)]
         cands = [{"chunk_len": L, "group": g, "tile": t, "lookback": k} for L in Ls for g in (4, 8, 16)
                  for t in (64, 128)]
@@ -121,15 +124,23 @@ class Autotuner:
 
     # -- planning ------------------------------------------------------------
 
+    @staticmethod
+    def default(dfa) -> tuple[int, dict]:
+        """Untuned pairs: the compile step's layout; lookback sets over 256
+        bytes when a column image is large (speculation would be costly)."""
+        t = np.asarray(dfa.table)
+        widest = max(np.unique(t[:, j]).size for j in range(t.shape[1]))
+        return LAYOUT_AUTO, ({"chunk_len": 0, "lookback": 256} if widest > 64 else {})
+
     def choose(self, dfa, text) -> tuple[int, dict]:
         """(layout, options) for one pair; tunes its class on first sight."""
         n = text.numel()
         if n < self.min_tune_bytes:
-            return LAYOUT_AUTO, {}
+            return self.default(dfa)
         key = size_class(dfa.num_states, dfa.alphabet_size, n)
         if key not in self.cache:
             if not self.measure:
-                return LAYOUT_AUTO, {}
+                return self.default(dfa)
             self.cache[key] = self.tune_pair(dfa, text)
             if self.log:
                 self.log(f"{key}: {self.cache[key]} ({self.seconds:.1f} s so far)")

@@ -30,6 +30,9 @@ SOURCES = [
     "parem_walk_hot_all.hip",
     "parem_walk_hot_sel.hip",
     "parem_walk_hot_redo.hip",
+    "parem_walk_class_all.hip",
+    "parem_walk_class_sel.hip",
+    "parem_walk_class_redo.hip",
     "parem_mlp.hip",
     "parem_batch.hip",
     "parem_batch_t64.hip",

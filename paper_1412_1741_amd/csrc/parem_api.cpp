@@ -77,8 +77,9 @@ std::vector<E> byte_table(const DeviceDfa &d, const std::vector<uint32_t> &t, ui
 // settle); their rows go to LDS, followed by one row of kHotLost entries and
 // the hot states' ids. Every destination is stored encoded (its slot for a
 // hot state, kHotFlag | id for a cold one) with its final flag in bit 15.
-void hot_tables(DeviceDfa &d, const std::vector<uint32_t> &t, std::vector<uint8_t> &image,
-                std::vector<uint16_t> &full, std::vector<uint16_t> &enc) {
+// Weight share of the hot states (a cheap stand-in for how often a walk stays
+// in LDS rows); fills `order` with the states by decreasing weight.
+double hot_share(const DeviceDfa &d, const std::vector<uint32_t> &t, std::vector<uint32_t> &order) {
     const uint32_t Q = d.Q, A = d.A;
     std::vector<double> pi(Q, 1.0 / Q), nx(Q), acc(Q, 0.0);
     for (int it = 0; it < 48; ++it) {
@@ -91,9 +92,18 @@ void hot_tables(DeviceDfa &d, const std::vector<uint32_t> &t, std::vector<uint8_
         if (it >= 16)
             for (uint32_t q = 0; q < Q; ++q) acc[q] += pi[q];
     }
-    std::vector<uint32_t> order(Q);
+    order.resize(Q);
     for (uint32_t q = 0; q < Q; ++q) order[q] = q;
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return acc[a] > acc[b]; });
+    double all = 0.0, top = 0.0;
+    for (uint32_t q = 0; q < Q; ++q) all += acc[q];
+    for (uint32_t s = 0; s < std::min<uint32_t>(parem::kHotMax, Q); ++s) top += acc[order[s]];
+    return all > 0.0 ? top / all : 1.0;
+}
+
+void hot_tables(DeviceDfa &d, const std::vector<uint32_t> &t, const std::vector<uint32_t> &order,
+                std::vector<uint8_t> &image, std::vector<uint16_t> &full, std::vector<uint16_t> &enc) {
+    const uint32_t Q = d.Q, A = d.A;
     const uint32_t H = std::min<uint32_t>(parem::kHotMax, Q);
     enc.assign(Q + 1, 0);
     for (uint32_t q = 0; q <= Q; ++q) enc[q] = (uint16_t)(parem::kHotFlag | q);
@@ -228,7 +238,7 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
         if (o.lookback > parem::kLookMax) return PAREM_EINVAL;
         if (o.chunk_len % 64 || o.chunk_len > parem::kMaxChunk) return PAREM_EINVAL;
         if (o.group && o.group != 2 && o.group != 4 && o.group != 8 && o.group != 16) return PAREM_EINVAL;
-        if (o.layout > PAREM_LAYOUT_HOT_LDS) return PAREM_EINVAL;
+        if (o.layout > PAREM_LAYOUT_CLASS_LDS) return PAREM_EINVAL;
         if (o.tile && o.tile != 64 && o.tile != 128) return PAREM_EINVAL;
         if (o.kgram) return PAREM_EINVAL;
         if (o.no_merge > 1) return PAREM_EINVAL;
@@ -303,10 +313,17 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
     const bool kg_ok = (layout == PAREM_LAYOUT_AUTO || layout == PAREM_LAYOUT_KGRAM_LDS) && build_kgram(d, t, kgbytes);
     const bool lds_ok = d.Q + 1 <= 128;
     const bool hot_ok = d.Q + 1 <= 0x3fffu;  // kHotFlag | id stays below kHotLost
+    const bool class_ok = 256 + (uint64_t)(d.Q + 1) * (d.A + 1) * 2 <= parem::kClassLdsMax;
+    std::vector<uint32_t> hot_order;
+    // automatic choice: k-gram, LDS byte table, column-indexed LDS table, hot
+    // rows only when they hold most of the walk's weight, else through L2
+    const bool hot_auto = hot_ok && !kg_ok && !lds_ok && !class_ok && hot_share(d, t, hot_order) >= 0.9;
+    const uint32_t big = hot_auto ? PAREM_LAYOUT_HOT_LDS : PAREM_LAYOUT_BYTE_GLOBAL;
     if (layout == PAREM_LAYOUT_AUTO || (layout == PAREM_LAYOUT_KGRAM_LDS && !kg_ok))
         layout = kg_ok ? PAREM_LAYOUT_KGRAM_LDS
-                       : (lds_ok ? PAREM_LAYOUT_BYTE_LDS : (hot_ok ? PAREM_LAYOUT_HOT_LDS : PAREM_LAYOUT_BYTE_GLOBAL));
-    if (layout == PAREM_LAYOUT_BYTE_LDS && !lds_ok) layout = hot_ok ? PAREM_LAYOUT_HOT_LDS : PAREM_LAYOUT_BYTE_GLOBAL;
+                       : (lds_ok ? PAREM_LAYOUT_BYTE_LDS : (class_ok ? PAREM_LAYOUT_CLASS_LDS : big));
+    if (layout == PAREM_LAYOUT_BYTE_LDS && !lds_ok) layout = class_ok ? PAREM_LAYOUT_CLASS_LDS : big;
+    if (layout == PAREM_LAYOUT_CLASS_LDS && !class_ok) layout = big;
     if (layout == PAREM_LAYOUT_HOT_LDS && !hot_ok) layout = PAREM_LAYOUT_BYTE_GLOBAL;
     d.layout = layout;
     if (layout != PAREM_LAYOUT_KGRAM_LDS) {
@@ -333,10 +350,30 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
             uint8_t *p = nullptr;
             st = upload(bt, &p);
             d.d_table = p;
+        } else if (layout == PAREM_LAYOUT_CLASS_LDS) {
+            // [256 B byte -> column][(Q+1) x (A+1) u16 entries]
+            const uint32_t A1 = d.A + 1;
+            std::vector<uint8_t> image((256 + (size_t)(d.Q + 1) * A1 * 2 + 15) / 16 * 16, 0);
+            for (uint32_t x = 0; x < 256; ++x) image[x] = d.cls[x];
+            uint16_t *T = reinterpret_cast<uint16_t *>(image.data() + 256);
+            for (uint32_t q = 0; q <= d.Q; ++q) {
+                for (uint32_t a = 0; a < A1; ++a) {
+                    const uint32_t nx = (q < d.Q && a < d.A) ? t[(size_t)q * d.A + a] : d.sent;
+                    T[(size_t)q * A1 + a] = (uint16_t)(nx | ((uint32_t)d.final_flag[nx] << 15));
+                }
+            }
+            d.entry_bytes = 2;
+            d.row_stride = A1;
+            d.table_bytes = (uint32_t)image.size();
+            d.lds_bytes = d.table_bytes;
+            uint8_t *p = nullptr;
+            st = upload(image, &p);
+            d.d_table = p;
         } else if (layout == PAREM_LAYOUT_HOT_LDS) {
             std::vector<uint8_t> image;
             std::vector<uint16_t> full, enc;
-            hot_tables(d, t, image, full, enc);
+            if (hot_order.empty()) hot_share(d, t, hot_order);
+            hot_tables(d, t, hot_order, image, full, enc);
             d.entry_bytes = 2;
             d.row_stride = parem::kHotRow;
             d.table_bytes = (uint32_t)image.size();

@@ -73,7 +73,7 @@ __global__ __launch_bounds__(256) void k_batch_lookback(const BatchPair *__restr
     if (c >= bp.la.nchunks) return;
     LookArgs a = bp.la;
     a.text = texts[it.pair];
-    lookback_chunk(a, c, smem + (threadIdx.x >> 6) * wave_bytes);
+    lookback_chunk(a, bp.start, c, smem + (threadIdx.x >> 6) * wave_bytes);
 }
 
 // walks started by a lookback pair (nsel 0: the chunk's whole set); runs
@@ -111,6 +111,7 @@ static int batch_kind(const DeviceDfa &d) {
     if (d.layout == PAREM_LAYOUT_KGRAM_LDS) return BK_KGRAM1 + (int)d.kg.bits - 1;
     if (d.layout == PAREM_LAYOUT_BYTE_LDS) return BK_BYTE_LDS;
     if (d.layout == PAREM_LAYOUT_HOT_LDS) return BK_HOT;
+    if (d.layout == PAREM_LAYOUT_CLASS_LDS) return BK_CLASS;
     return BK_BYTE_GLOBAL;
 }
 
@@ -155,6 +156,13 @@ struct parem_batch_s {
     hipEvent_t staged = nullptr;        // the last pointer upload has been read
     bool staged_pending = false;
     hipStream_t cap_stream = nullptr;
+    // walk launches run on up to kBranches concurrent streams (branches of
+    // the graph): a launch whose items are few and long overlaps the others
+    static constexpr int kBranches = 4;
+    hipStream_t aux[kBranches - 1] = {};
+    hipEvent_t fork = nullptr, join[kBranches - 1] = {};
+    std::vector<int> branch;  // per variant
+    int nbranch = 1;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     size_t graph_nodes = 0;
@@ -167,6 +175,11 @@ static void batch_release(parem_batch_s *b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    for (int i = 0; i < parem_batch_s::kBranches - 1; ++i) {
+        if (b->aux[i]) (void)hipStreamDestroy(b->aux[i]);
+        if (b->join[i]) (void)hipEventDestroy(b->join[i]);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->staged) (void)hipEventDestroy(b->staged);
     if (b->h_texts) (void)hipHostFree(b->h_texts);
     (void)hipFree(b->d_meta);
@@ -212,7 +225,7 @@ static parem_status batch_plan(const parem_handle *dfas, const uint64_t *lens, u
         if (sel) {
             b->look_pairs.push_back(i);
             for (uint64_t q4 = 0; q4 < (p.chunks + 3) / 4; ++q4) b->look_items.push_back(LookItem{i, (uint32_t)q4});
-            b->look_wave = std::max(b->look_wave, look_wave_bytes((d.Q + 1 + 31) / 32, p.look));
+            b->look_wave = std::max(b->look_wave, look_wave_bytes((d.Q + 1 + 31) / 32));
         }
         int v = -1;
         for (size_t k = 0; k < b->variants.size(); ++k) {
@@ -262,6 +275,26 @@ static parem_status batch_plan(const parem_handle *dfas, const uint64_t *lens, u
             return PAREM_EDEVICE;
         if (per_cu < 1) return PAREM_EUNSUPPORTED;
         x.grid = (uint32_t)std::min<uint64_t>(x.items.size(), (uint64_t)per_cu * (uint64_t)cus);
+    }
+
+    // branches: variants by decreasing (longest chunk x items), dealt round robin
+    b->branch.assign(b->variants.size(), 0);
+    b->nbranch = (int)std::min<size_t>(parem_batch_s::kBranches, b->variants.size());
+    if (b->nbranch > 1) {
+        std::vector<size_t> ord(b->variants.size());
+        std::vector<uint64_t> cost(b->variants.size(), 0);
+        for (size_t v = 0; v < b->variants.size(); ++v) {
+            ord[v] = v;
+            for (const WalkItem &it : b->variants[v].items) cost[v] += b->plans[it.pair].L;
+        }
+        std::stable_sort(ord.begin(), ord.end(), [&](size_t l, size_t r) { return cost[l] > cost[r]; });
+        for (size_t k = 0; k < ord.size(); ++k) b->branch[ord[k]] = (int)(k % (size_t)b->nbranch);
+        if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) return PAREM_EDEVICE;
+        for (int i = 0; i < b->nbranch - 1; ++i) {
+            if (hipStreamCreateWithFlags(&b->aux[i], hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming) != hipSuccess)
+                return PAREM_EDEVICE;
+        }
     }
 
     // composition levels
@@ -366,11 +399,22 @@ static parem_status batch_enqueue(const parem_batch_s *b, hipStream_t s) {
                            b->look_wave);
     if (!b->variants.empty()) {
         hipLaunchKernelGGL(k_batch_clear, dim3(1), dim3(64), 0, s, queue, (uint32_t)b->variants.size());
+        const int nb = b->nbranch;
+        if (nb > 1) {
+            if (hipEventRecord(b->fork, s) != hipSuccess) return PAREM_EDEVICE;
+            for (int i = 0; i < nb - 1; ++i)
+                if (hipStreamWaitEvent(b->aux[i], b->fork, 0) != hipSuccess) return PAREM_EDEVICE;
+        }
         for (size_t v = 0; v < b->variants.size(); ++v) {
             const BatchVariant &x = b->variants[v];
             const WalkItem *items = reinterpret_cast<const WalkItem *>(b->d_meta + x.off_items);
-            hipLaunchKernelGGL(x.fn, dim3(x.grid), dim3(kWalkThreads), x.lds, s, pairs, texts, items,
+            hipStream_t bs = b->branch[v] == 0 ? s : b->aux[b->branch[v] - 1];
+            hipLaunchKernelGGL(x.fn, dim3(x.grid), dim3(kWalkThreads), x.lds, bs, pairs, texts, items,
                                (uint32_t)x.items.size(), queue + v, x.table_cap);
+        }
+        for (int i = 0; i < nb - 1; ++i) {
+            if (hipEventRecord(b->join[i], b->aux[i]) != hipSuccess || hipStreamWaitEvent(s, b->join[i], 0) != hipSuccess)
+                return PAREM_EDEVICE;
         }
     }
     if (!b->empties.empty()) {

@@ -41,7 +41,15 @@ struct ComposeItem {
 };
 
 // walk kernel variants: the table layout of the pairs they serve
-enum BatchKind : int { BK_BYTE_LDS = 0, BK_BYTE_GLOBAL = 1, BK_KGRAM1 = 2, BK_KGRAM2 = 3, BK_KGRAM3 = 4, BK_HOT = 5 };
+enum BatchKind : int {
+    BK_BYTE_LDS = 0,
+    BK_BYTE_GLOBAL = 1,
+    BK_KGRAM1 = 2,
+    BK_KGRAM2 = 3,
+    BK_KGRAM3 = 4,
+    BK_HOT = 5,
+    BK_CLASS = 6
+};
 
 template <int G, uint32_t TILE, int KIND, int MODE>
 __global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_batch_walk(
@@ -76,6 +84,9 @@ __global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_batch_walk(
         } else if constexpr (KIND == BK_BYTE_GLOBAL) {
             ByteStep<uint16_t, 256> st{reinterpret_cast<const uint16_t *>(bp.table)};
             walk_chunk<G, ByteStep<uint16_t, 256>, true, TILE, MODE>(st, a, smem, c0);
+        } else if constexpr (KIND == BK_CLASS) {
+            ClassStep st{smem, reinterpret_cast<const uint16_t *>(smem + 256), bp.w.start_class};  // A + 1
+            walk_chunk<G, ClassStep, true, TILE, MODE>(st, a, smem + table_cap, c0);
         } else if constexpr (KIND == BK_HOT) {
             const uint16_t *hot = reinterpret_cast<const uint16_t *>(smem);
             HotStep st{hot, hot + (bp.hot_rows + 1) * kHotRow, bp.full, bp.enc, bp.hot_rows};
@@ -98,6 +109,7 @@ WalkKernel walk_kernel_kind(int kind) {
         case BK_KGRAM1: return k_batch_walk<G, TILE, BK_KGRAM1, MODE>;
         case BK_KGRAM2: return k_batch_walk<G, TILE, BK_KGRAM2, MODE>;
         case BK_KGRAM3: return k_batch_walk<G, TILE, BK_KGRAM3, MODE>;
+        case BK_CLASS: return k_batch_walk<G, TILE, BK_CLASS, MODE>;
         default: return k_batch_walk<G, TILE, BK_HOT, MODE>;
     }
 }

@@ -70,6 +70,42 @@ struct ByteStep {
     }
 };
 
+// Column-indexed table in LDS: byte -> column through a 256-entry map (one
+// read per byte, shared by the lane's walks), then entry (state, column) =
+// next | final << 15. Column A sends every state to the sentinel (invalid
+// bytes); the sentinel row stays in the sentinel.
+struct ClassStep {
+    static constexpr bool kRedo = false;
+    const uint8_t *__restrict__ col;   // LDS: [256]
+    const uint16_t *__restrict__ T;    // LDS: (Q+1) x (A+1)
+    uint32_t A1;                       // A + 1
+
+    __device__ __forceinline__ uint32_t init(uint32_t s) const { return s; }
+    __device__ __forceinline__ uint32_t id(uint32_t r) const { return r; }
+    __device__ __forceinline__ bool same(uint32_t a, uint32_t b) const { return a == b; }
+    __device__ __forceinline__ void one(uint32_t &s, uint32_t &c, uint32_t cl) const {
+        const uint32_t v = T[s * A1 + cl];
+        c += v >> 15;
+        s = v & 0x7fffu;
+    }
+    template <int G>
+    __device__ __forceinline__ void dword(uint32_t d, uint32_t (&R)[G], uint32_t (&S)[G], uint32_t (&c)[G], int nw,
+                                          uint32_t &bad) const {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t cl = col[(d >> (8 * k)) & 0xffu];
+#pragma unroll
+            for (int j = 0; j < G; ++j)
+                if (j < nw) one(R[j], c[j], cl);
+        }
+    }
+    template <int G>
+    __device__ __forceinline__ void flush(uint32_t (&S)[G], uint32_t (&c)[G], int nw) const {}
+    __device__ __forceinline__ void byte(uint32_t x, uint32_t &R, uint32_t &c, uint32_t &bad) const {
+        one(R, c, col[x]);
+    }
+};
+
 // Hot-row layout: the byte-table rows of the H most visited states sit in
 // LDS, the other rows are read through L2. A walk carries its state encoded:
 // the slot (0..H-1) of a hot state, kHotFlag | id for a cold one; every
@@ -561,18 +597,21 @@ __device__ __forceinline__ void walk_chunk(const ST &st, const WalkArgs &a, uint
 
 // ---------------------------------------------------------------------------
 // lookback sets: chunk c >= 1 starts in some state of
-// B_c = delta*(Q, t[b-K .. b-1]) (b = c*L), the image of every state under the
-// K bytes before it; B_c is a subset of R_c (its last step is the column of
-// t[b-1]) and holds the true entry state. One wave per chunk: the set is a
-// bitmap in LDS mapped byte by byte; the result is the ascending positions of
-// B_c in R_c's sorted list, or nsel 0 (walk all of R_c) when |B_c| > cap.
+// B_c = delta*(Q, t[b-K .. b-1]) (b = c*L, K <= b), the image of every state
+// under the K bytes before it; B_c is a subset of R_c (its last step is the
+// column of t[b-1]) and holds the true entry state, so the true run is always
+// walked. Entries of other walks that end outside B_c become absent in the
+// composition, which only ever follows the true run to the result. One wave
+// per chunk: the set is a bitmap in LDS mapped byte by byte; the result is
+// the ascending positions of B_c in R_c's sorted list, or nsel 0 (walk all of
+// R_c) when |B_c| > cap.
 // ---------------------------------------------------------------------------
 
 struct LookArgs {
     const uint8_t *text;
     uint32_t L;
     uint64_t nchunks;
-    uint32_t K;             // lookback bytes, 1 <= K <= L
+    uint32_t K;             // first lookback window in bytes
     uint32_t Q, A;
     uint32_t words;         // bitmap words: ceil((Q + 1) / 32)
     const uint8_t *cls;     // byte -> class (A or more: invalid)
@@ -582,9 +621,9 @@ struct LookArgs {
     uint8_t *nsel;          // [nchunks]
 };
 
-// LDS bytes one wave of the lookback needs
-__host__ __device__ inline uint32_t look_wave_bytes(uint32_t words, uint32_t K) {
-    return (2u * words * 4u + 256u + K + 15u) & ~15u;
+// LDS bytes one wave of the lookback needs (window of up to kLookMax bytes)
+__host__ __device__ inline uint32_t look_wave_bytes(uint32_t words) {
+    return (2u * words * 4u + 256u + kLookMax + 15u) & ~15u;
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -599,39 +638,25 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
     return v;
 }
 
-// the wave's lanes compute chunk c's lookback set; `ws` is the wave's LDS
-__device__ __forceinline__ void lookback_chunk(const LookArgs &a, uint64_t c, uint8_t *ws) {
+// Image under win[0 .. K) of every state (from_start false) or of {q0}
+// (the window starts at the text start). Leaves the set in *cur; returns
+// false when a byte outside the alphabet was met.
+__device__ __forceinline__ bool look_image(const LookArgs &a, uint32_t start, bool from_start, const uint8_t *win,
+                                           uint32_t K, const uint8_t *cl, uint32_t *&cur, uint32_t *&nxt) {
     const uint32_t lane = threadIdx.x & 63u;
-    if (c == 0) {
-        if (lane == 0) {
-            a.nsel[0] = 1;  // chunk 0: {q0}, position 0 of the start class
-            a.sel[0] = 0;
-        }
-        return;
-    }
     const uint32_t W = a.words;
-    uint32_t *cur = reinterpret_cast<uint32_t *>(ws);
-    uint32_t *nxt = cur + W;
-    uint8_t *cl = reinterpret_cast<uint8_t *>(nxt + W);
-    uint8_t *win = cl + 256;
-    const uint64_t b = c * (uint64_t)a.L;
-    const uint32_t K = (uint32_t)min((uint64_t)a.K, b);
-    const uint8_t *src = a.text + (b - K);
-    for (uint32_t k = lane; k < K; k += 64) win[k] = src[k];
-    for (uint32_t x = lane; x < 256; x += 64) cl[x] = a.cls[x];
     for (uint32_t w = lane; w < W; w += 64) {
         const uint32_t lo = w * 32u;  // states 0 .. Q-1 (not the sentinel)
-        cur[w] = lo + 32u <= a.Q ? 0xffffffffu : (a.Q > lo ? (1u << (a.Q - lo)) - 1u : 0u);
+        uint32_t v;
+        if (from_start) v = (start >> 5) == w ? 1u << (start & 31u) : 0u;
+        else v = lo + 32u <= a.Q ? 0xffffffffu : (a.Q > lo ? (1u << (a.Q - lo)) - 1u : 0u);
+        cur[w] = v;
         nxt[w] = 0;
     }
     wave_sync();
-    bool invalid = false;
     for (uint32_t k = 0; k < K; ++k) {
         const uint32_t col = cl[win[k]];
-        if (col >= a.A) {  // a byte outside the alphabet: the match fails anyway
-            invalid = true;
-            break;
-        }
+        if (col >= a.A) return false;  // uniform: every lane reads the same byte
         for (uint32_t w = lane; w < W; w += 64) {
             uint32_t bits = cur[w];
             if (bits) {
@@ -649,23 +674,59 @@ __device__ __forceinline__ void lookback_chunk(const LookArgs &a, uint64_t c, ui
         cur = nxt;
         nxt = t;
     }
-    uint16_t *out = a.sel + c * kLookCap;
-    if (invalid) {
+    return true;
+}
+
+// The wave's lanes compute chunk c's lookback set; `ws` is the wave's LDS.
+// The window starts at K bytes and grows fourfold (up to kLookMax) while the
+// image has more than kLookCap states; a window that reaches the text start
+// maps {q0} instead of every state, which gives the true entry state alone.
+__device__ __forceinline__ void lookback_chunk(const LookArgs &a, uint32_t start, uint64_t c, uint8_t *ws) {
+    const uint32_t lane = threadIdx.x & 63u;
+    if (c == 0) {
         if (lane == 0) {
-            a.nsel[c] = 1;  // any state: the walk through the invalid byte ends in the sentinel
-            out[0] = 0;
+            a.nsel[0] = 1;  // chunk 0: {q0}, position 0 of the start class
+            a.sel[0] = 0;
         }
+        return;
+    }
+    const uint32_t W = a.words;
+    uint32_t *cur = reinterpret_cast<uint32_t *>(ws);
+    uint32_t *nxt = cur + W;
+    uint8_t *cl = reinterpret_cast<uint8_t *>(nxt + W);
+    uint8_t *win = cl + 256;
+    const uint64_t b = c * (uint64_t)a.L;
+    for (uint32_t x = lane; x < 256; x += 64) cl[x] = a.cls[x];
+    uint16_t *out = a.sel + c * kLookCap;
+    uint32_t K = a.K, total = 0;
+    for (;;) {
+        const bool from_start = (uint64_t)K >= b;
+        const uint32_t Kc = from_start ? (uint32_t)b : K;
+        const uint8_t *src = a.text + (b - Kc);
+        for (uint32_t k = lane; k < Kc; k += 64) win[k] = src[k];
+        wave_sync();
+        if (!look_image(a, start, from_start, win, Kc, cl, cur, nxt)) {
+            if (lane == 0) {
+                a.nsel[c] = 1;  // any state: the walk through the invalid byte ends in the sentinel
+                out[0] = 0;
+            }
+            return;
+        }
+        uint32_t cnt = 0;
+        for (uint32_t w = lane; w < W; w += 64) cnt += (uint32_t)__builtin_popcount(cur[w]);
+        total = wave_sum(cnt);
+        if (total <= kLookCap || from_start || K >= kLookMax) break;
+        K = min(K * 4u, kLookMax);
+        wave_sync();  // every lane is done with the window before it is rewritten
+    }
+    if (total > kLookCap) {
+        if (lane == 0) a.nsel[c] = 0;
         return;
     }
     const uint32_t per = (W + 63u) / 64u;
     const uint32_t w0 = min(lane * per, W), w1 = min(w0 + per, W);
     uint32_t mine = 0;
     for (uint32_t w = w0; w < w1; ++w) mine += (uint32_t)__builtin_popcount(cur[w]);
-    const uint32_t total = wave_sum(mine);
-    if (total > kLookCap) {
-        if (lane == 0) a.nsel[c] = 0;
-        return;
-    }
     // exclusive prefix over lanes: ascending state order across lanes
     uint32_t off = mine;
 #pragma unroll
@@ -674,7 +735,7 @@ __device__ __forceinline__ void lookback_chunk(const LookArgs &a, uint64_t c, ui
         if ((int)lane >= o) off += v;
     }
     off -= mine;
-    const uint32_t cls_prev = cl[win[K - 1]];
+    const uint32_t cls_prev = cl[a.text[b - 1]];
     const uint16_t *pos = a.inv + (size_t)cls_prev * (a.Q + 1);
     uint32_t missing = 0;
     for (uint32_t w = w0; w < w1; ++w) {
@@ -1103,6 +1164,12 @@ __device__ __forceinline__ void compose_segs_seg(uint8_t *smem, const SegOut &in
 // its own translation unit per (layout, mode)
 template <int LAYOUT, int MODE>
 void launch_walk_family(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, hipStream_t stream, bool aligned);
+extern template void launch_walk_family<PAREM_LAYOUT_CLASS_LDS, WALK_ALL>(const DeviceDfa &, const PlainPlan &,
+                                                     const WalkArgs &, hipStream_t, bool);
+extern template void launch_walk_family<PAREM_LAYOUT_CLASS_LDS, WALK_SELECTED>(const DeviceDfa &, const PlainPlan &,
+                                                     const WalkArgs &, hipStream_t, bool);
+extern template void launch_walk_family<PAREM_LAYOUT_CLASS_LDS, WALK_REDO>(const DeviceDfa &, const PlainPlan &,
+                                                     const WalkArgs &, hipStream_t, bool);
 extern template void launch_walk_family<PAREM_LAYOUT_KGRAM_LDS, WALK_ALL>(const DeviceDfa &, const PlainPlan &,
                                                      const WalkArgs &, hipStream_t, bool);
 extern template void launch_walk_family<PAREM_LAYOUT_KGRAM_LDS, WALK_SELECTED>(const DeviceDfa &, const PlainPlan &,

@@ -72,6 +72,7 @@ struct DeviceDfa {
 // hot-row layout: at most kHotMax rows of kHotRow u16 entries (256 bytes plus
 // padding that shifts successive rows by one LDS bank)
 constexpr uint32_t kHotMax = 32;
+constexpr uint32_t kClassLdsMax = 48 * 1024;  // largest column-indexed LDS table
 constexpr uint32_t kHotRow = 258;
 constexpr uint32_t kHotFlag = 0x4000u;  // cold state: kHotFlag | id; hot state: its slot
 constexpr uint32_t kHotLost = 0x7fffu;  // entries of the extra LDS row H

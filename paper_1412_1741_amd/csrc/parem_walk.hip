@@ -184,11 +184,11 @@ __global__ void k_look_stats(const uint8_t *__restrict__ nsel, const uint16_t *_
     if (threadIdx.x == 0) atomicAdd(&acc[0], part[0] + part[1] + part[2] + part[3]);
 }
 
-__global__ __launch_bounds__(256) void k_lookback(LookArgs a, uint32_t wave_bytes) {
+__global__ __launch_bounds__(256) void k_lookback(LookArgs a, uint32_t start, uint32_t wave_bytes) {
     extern __shared__ __align__(16) uint8_t smem[];
     const uint64_t c = (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6);
     if (c >= a.nchunks) return;  // whole waves leave; no workgroup barrier follows
-    lookback_chunk(a, c, smem + (threadIdx.x >> 6) * wave_bytes);
+    lookback_chunk(a, start, c, smem + (threadIdx.x >> 6) * wave_bytes);
 }
 
 __global__ void k_learned_total(const unsigned long long *__restrict__ acc, parem_result *__restrict__ result) {
@@ -293,7 +293,7 @@ parem_status plan_chunks(const DeviceDfa &d, uint64_t len, const parem_options &
     if (L % 64 != 0 || L == 0 || L > kMaxChunk) return PAREM_EINVAL;
     q.L = L;
     q.chunks = (len + L - 1) / L;
-    q.look = (o.lookback && d.d_next && d.d_inv) ? std::min<uint32_t>(o.lookback, L) : 0u;
+    q.look = (o.lookback && d.d_next && d.d_inv) ? o.lookback : 0u;
     q.tile = o.tile ? o.tile : 128;
     q.merge = o.no_merge ? 0u : 1u;
     if (q.tile != 64 && q.tile != 128) return PAREM_EINVAL;
@@ -354,6 +354,7 @@ static void launch_walk(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &
         case PAREM_LAYOUT_KGRAM_LDS: launch_walk_family<PAREM_LAYOUT_KGRAM_LDS, MODE>(d, p, a, stream, aligned); break;
         case PAREM_LAYOUT_BYTE_LDS: launch_walk_family<PAREM_LAYOUT_BYTE_LDS, MODE>(d, p, a, stream, aligned); break;
         case PAREM_LAYOUT_HOT_LDS: launch_walk_family<PAREM_LAYOUT_HOT_LDS, MODE>(d, p, a, stream, aligned); break;
+        case PAREM_LAYOUT_CLASS_LDS: launch_walk_family<PAREM_LAYOUT_CLASS_LDS, MODE>(d, p, a, stream, aligned); break;
         default: launch_walk_family<PAREM_LAYOUT_BYTE_GLOBAL, MODE>(d, p, a, stream, aligned); break;
     }
 }
@@ -400,8 +401,8 @@ parem_status launch_plain(const DeviceDfa &d, const PlainPlan &p, const uint8_t 
     WalkArgs a = walk_args(d, p, d_text, ws);
     if (p.look) {
         const LookArgs la = look_args(d, p, d_text, ws);
-        const uint32_t wb = look_wave_bytes(la.words, la.K);
-        hipLaunchKernelGGL(k_lookback, dim3((uint32_t)((p.chunks + 3) / 4)), dim3(256), 4 * wb, stream, la, wb);
+        const uint32_t wb = look_wave_bytes(la.words);
+        hipLaunchKernelGGL(k_lookback, dim3((uint32_t)((p.chunks + 3) / 4)), dim3(256), 4 * wb, stream, la, d.start, wb);
         a.sel = la.sel;
         a.nsel = la.nsel;
         a.sel_stride = kLookCap;

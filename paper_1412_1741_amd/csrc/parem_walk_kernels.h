@@ -50,6 +50,16 @@ __global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_walk_hot(Wal
     walk_chunk<G, HotStep, ALIGNED, TILE, MODE>(st, a, smem + table_bytes, (uint64_t)blockIdx.x * kWalkThreads);
 }
 
+template <int G, bool ALIGNED, uint32_t TILE, int MODE>
+__global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_walk_class(WalkArgs a,
+                                                                               const uint8_t *__restrict__ g_table,
+                                                                               uint32_t table_bytes, uint32_t A1) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    stage_table(reinterpret_cast<uint4 *>(smem), reinterpret_cast<const uint4 *>(g_table), table_bytes / 16u);
+    ClassStep st{smem, reinterpret_cast<const uint16_t *>(smem + 256), A1};
+    walk_chunk<G, ClassStep, ALIGNED, TILE, MODE>(st, a, smem + table_bytes, (uint64_t)blockIdx.x * kWalkThreads);
+}
+
 template <int G, int B, bool ALIGNED, uint32_t TILE, int MODE>
 __global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_walk_kgram(WalkArgs a,
                                                                                const uint8_t *__restrict__ g_table,
@@ -96,6 +106,18 @@ inline void launch_walk_hot(const DeviceDfa &d, const PlainPlan &p, const WalkAr
 #undef PAREM_HOT
 }
 
+template <bool ALIGNED, uint32_t TILE, int MODE>
+inline void launch_walk_class(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, hipStream_t stream) {
+    const uint32_t grid = (uint32_t)((p.chunks + kWalkThreads - 1) / kWalkThreads);
+    const size_t lds = d.table_bytes + ((ALIGNED && MODE != WALK_REDO) ? Stage<TILE>::kBytes : 0);
+    const uint8_t *tab = reinterpret_cast<const uint8_t *>(d.d_table);
+#define PAREM_CLS(GG)                                                                                             \
+    hipLaunchKernelGGL((k_walk_class<GG, ALIGNED, TILE, MODE>), dim3(grid), dim3(kWalkThreads), lds, stream, a, tab, \
+                       d.table_bytes, d.A + 1)
+    PAREM_GROUP_SWITCH(PAREM_CLS)
+#undef PAREM_CLS
+}
+
 template <int LAYOUT, bool ALIGNED, uint32_t TILE, int MODE>
 inline void launch_family_t(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, hipStream_t stream) {
     if constexpr (LAYOUT == PAREM_LAYOUT_KGRAM_LDS) {
@@ -108,6 +130,8 @@ inline void launch_family_t(const DeviceDfa &d, const PlainPlan &p, const WalkAr
         launch_walk_byte<uint8_t, kByteLdsRow, true, ALIGNED, TILE, MODE>(d, p, a, stream);
     } else if constexpr (LAYOUT == PAREM_LAYOUT_HOT_LDS) {
         launch_walk_hot<ALIGNED, TILE, MODE>(d, p, a, stream);
+    } else if constexpr (LAYOUT == PAREM_LAYOUT_CLASS_LDS) {
+        launch_walk_class<ALIGNED, TILE, MODE>(d, p, a, stream);
     } else {
         launch_walk_byte<uint16_t, 256, false, ALIGNED, TILE, MODE>(d, p, a, stream);
     }

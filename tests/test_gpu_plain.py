@@ -86,7 +86,8 @@ def test_config2_small_groups(group):
 
 
 def all_layouts():
-    return [P.LAYOUT_AUTO, P.LAYOUT_KGRAM_LDS, P.LAYOUT_BYTE_LDS, P.LAYOUT_BYTE_GLOBAL, P.LAYOUT_HOT_LDS]
+    return [P.LAYOUT_AUTO, P.LAYOUT_KGRAM_LDS, P.LAYOUT_BYTE_LDS, P.LAYOUT_BYTE_GLOBAL, P.LAYOUT_HOT_LDS,
+            P.LAYOUT_CLASS_LDS]
 
 
 def test_config2_layouts():
@@ -181,8 +182,34 @@ def test_large_state_counts():
     for q in (128, 300, 1000, 4096):
         dfa = W.random_dense_dfa(rng, q, bytes(range(0, 256, 16)), num_accepting=q // 8)
         text = W.uniform_text(rng, dfa.alphabet, 1 << 18)
-        for lay in (P.LAYOUT_BYTE_GLOBAL, P.LAYOUT_HOT_LDS):
+        for lay in (P.LAYOUT_BYTE_GLOBAL, P.LAYOUT_HOT_LDS, P.LAYOUT_CLASS_LDS):
             run_case(f"dense Q={q} layout={lay}", dfa, text, chunk_len=4096, layout=lay)
+
+
+@pytest.mark.parametrize("q,a", [(3000, 4), (1000, 20), (90, 255), (5000, 4)])
+def test_class_table(q, a):
+    """Column-indexed LDS table: chosen automatically when it fits in 48 KiB
+    (and no k-gram code or LDS byte table applies); invalid bytes included."""
+    rng = np.random.default_rng(q + a)
+    alphabet = bytes(rng.choice(256, size=a, replace=False).astype(np.uint8))
+    dfa = W.random_dense_dfa(rng, q, alphabet, num_accepting=max(1, q // 10))
+    m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, layout=P.LAYOUT_CLASS_LDS)
+    fits = 256 + (q + 1) * (a + 1) * 2 <= 48 * 1024
+    assert (m.describe()["layout"] == P.LAYOUT_CLASS_LDS) == fits
+    m.close()
+    text = W.uniform_text(rng, alphabet, (1 << 18) + 5)
+    for G in (4, 16):
+        run_case(f"class Q={q} A={a} G={G}", dfa, text, chunk_len=1024, group=G, layout=P.LAYOUT_CLASS_LDS)
+        run_case(f"class lookback Q={q} A={a} G={G}", dfa, text, chunk_len=1024, group=G,
+                 layout=P.LAYOUT_CLASS_LDS, lookback=128, check_spec=False)
+    bad = text.copy()
+    bad[5000] = next(x for x in range(256) if x not in alphabet)
+    say(f"[case] class invalid byte Q={q} A={a}")
+    m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, layout=P.LAYOUT_CLASS_LDS, chunk_len=1024)
+    with pytest.raises(P.ParemError) as e:
+        m.match(torch.from_numpy(bad).cuda())
+    assert e.value.status == P.PAREM_ESYMBOL
+    m.close()
 
 
 @pytest.mark.parametrize("group", [2, 4, 8, 16])
@@ -306,9 +333,11 @@ def test_nonsynchronizing_dfa():
         run_case(f"mixed layout={lay}", dfa2, text, chunk_len=128, layout=lay, group=8)
 
 
-def lookback_runs(dfa, text, L, K, cap=64):
-    """Walks started with lookback sets: |B_c| when at most cap, else |R_c|
-    (B_c: image of every state under the K bytes before chunk c)."""
+def lookback_runs(dfa, text, L, K, cap=64, kmax=4096):
+    """Walks started with lookback sets: |B_c| when at most cap, else |R_c|.
+    B_c is the image of every state under the K bytes before chunk c; the
+    window grows fourfold (up to kmax) while |B_c| > cap, and a window that
+    reaches the text start maps {q0} instead."""
     col = np.full(256, -1, dtype=np.int64)
     col[np.frombuffer(dfa.alphabet, dtype=np.uint8)] = np.arange(dfa.alphabet_size)
     T = dfa.table.astype(np.int64)
@@ -316,10 +345,15 @@ def lookback_runs(dfa, text, L, K, cap=64):
     runs = 1
     for c in range(1, chunks):
         b = c * L
-        k = min(K, b, L)
-        s = np.arange(dfa.num_states)
-        for x in text[b - k:b]:
-            s = np.unique(T[s, col[x]])
+        k = K
+        while True:
+            from_start = k >= b
+            s = np.asarray([dfa.start]) if from_start else np.arange(dfa.num_states)
+            for x in text[b - (b if from_start else k):b]:
+                s = np.unique(T[s, col[x]])
+            if s.size <= cap or from_start or k >= kmax:
+                break
+            k = min(4 * k, kmax)
         r = np.unique(T[:, col[text[b - 1]]]).size
         runs += s.size if s.size <= cap else r
     return runs
@@ -341,6 +375,7 @@ def test_lookback_sets(K):
                            check_spec=False)
             if L >= 1024 and K <= 64:
                 assert got.spec_runs == lookback_runs(dfa, text, L, K), (name, L, K)
+            assert got.spec_runs <= expected_spec_runs(dfa, text, L)
     # small texts: every chunk's set checked
     small = W.uniform_text(rng, dense.alphabet, 3000)
     got = run_case(f"lookback K={K} small", dense, small, chunk_len=128, lookback=K, check_spec=False)
