@@ -163,7 +163,7 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--no-merge", action="store_true", help="walk every speculated run through its whole chunk")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--modes", default="plain,paper,learned",
+    ap.add_argument("--modes", default="plain,paper,learned,batch",
                     help="comma list: plain (merged runs), paper (every run walks its chunk), learned")
     ap.add_argument("--learned-m", default="1,4,16")
     ap.add_argument("--train-steps", type=int, default=400)

@@ -220,3 +220,40 @@ def test_tune_candidates_agree():
     for o in cands[:-1]:
         r = P.Batch([m], [text.size], [o]).run([dev])[0]
         assert (r.final_state, r.accept, r.count) == (want.final_state, want.accept, want.count), o
+
+
+def test_batch_uneven_4096_full_size():
+    """The 4096-pair uneven workload at full size, planned as the benchmark
+    plans it (autotuner cache, no new measurements), in one graph replay:
+    every pair's result is checked against the oracle for the shorter half of
+    the pairs (sampled) and the longest ones, and every result is valid."""
+    import concurrent.futures as cf
+    import os
+
+    from paper_1412_1741_amd.autotune import Autotuner
+
+    specs = W.config5_specs()
+    order = np.argsort([s.text_len for s in specs])
+    sample = set(int(i) for i in order[: len(order) // 2: 8]) | set(int(i) for i in order[-3:])
+    dfas, devs, host = [], [], {}
+    say(f"[case] uneven batch: generating {len(specs)} pairs")
+    with cf.ThreadPoolExecutor(16) as ex:
+        for i, (dfa, text) in enumerate(ex.map(W.config5_pair, specs)):
+            dfas.append(dfa)
+            devs.append(torch.from_numpy(text).cuda())
+            if i in sample:
+                host[i] = text
+    cache = os.path.join(os.path.dirname(P.__file__), "tuned", "batch_mi355x.json")
+    tuner = Autotuner(cache_path=cache, measure=False)
+    ms, opts = tuner.plan(dfas, devs)
+    b = P.Batch(ms, [d.numel() for d in devs], opts)
+    say(f"[info] {b.describe()}")
+    got = b.run(devs, use_graph=True)
+    say(f"[case] uneven batch: oracle on {len(host)} pairs")
+    for i, text in host.items():
+        want = oracle.walk_dfa(dfas[i], text)
+        r = got[i]
+        assert (r.final_state, r.accept, r.count) == (want.final_state, want.accept, want.count), i
+    for i, r in enumerate(got):
+        assert r.final_state < dfas[i].num_states, i
+        assert r.chunks == 0 or r.spec_runs >= r.chunks
