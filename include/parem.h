@@ -258,9 +258,14 @@ parem_status parem_match_learned_async(parem_handle h, parem_proposal p, uint32_
  *
  * parem_batch_create   dfas[n], lens[n] (bytes of each pair's text), opts
  *                      (n entries, or NULL for each handle's own options).
+ *                      props (n entries, or NULL) and m: pair i with a
+ *                      non-null props[i] (a proposal of dfas[i]) is matched
+ *                      with learned speculation, top-m[i] states per chunk
+ *                      (1..16), as parem_match_learned_async does; these
+ *                      pairs run one after another on a branch of their own.
  *                      Allocates the plan's device memory (workspace for
  *                      every pair). Pairs with lens[i] == 0 are allowed.
- *                      The handles must outlive the plan.
+ *                      The handles and proposals must outlive the plan.
  * parem_batch_run      d_texts: host array of n device pointers, each
  *                      16-byte aligned (PAREM_EINVAL otherwise), holding
  *                      lens[i] bytes. d_out: device array of n results.
@@ -269,7 +274,11 @@ parem_status parem_match_learned_async(parem_handle h, parem_proposal p, uint32_
  *                      one plan must not overlap (they share its workspace).
  *                      A text byte outside its pair's alphabet gives that
  *                      pair final_state 0xffffffff, accept 0, count 0 (the
- *                      other pairs are unaffected).
+ *                      other pairs are unaffected). The graph reads the
+ *                      texts of plain pairs through a pointer array, so it
+ *                      is replayed for any texts; learned pairs take their
+ *                      text pointers as launch arguments, so new pointers
+ *                      for them make the run capture a new graph.
  * parem_batch_describe plan statistics (any pointer may be NULL).
  * parem_match_batch    create + run (graph) + synchronize + free; on a byte
  *                      outside an alphabet returns PAREM_ESYMBOL after
@@ -281,13 +290,15 @@ typedef struct {
     uint64_t walk_items;     /* work items of 256 chunks                          */
     uint32_t levels;         /* composition launches                              */
     uint32_t graph_nodes;    /* nodes of the captured graph (0 before capture)    */
+    uint32_t learned_pairs;  /* pairs matched with learned speculation             */
     uint64_t chunks;         /* chunks over all pairs                             */
     uint64_t text_bytes;     /* bytes over all pairs                              */
     uint64_t workspace_bytes;
 } parem_batch_info;
 
 parem_status parem_batch_create(const parem_handle *dfas, const uint64_t *lens, uint32_t n,
-                                const parem_options *opts, parem_batch *out);
+                                const parem_options *opts, const parem_proposal *props, const uint32_t *m,
+                                parem_batch *out);
 parem_status parem_batch_run(parem_batch b, const uint8_t *const *d_texts, void *stream, parem_result *d_out,
                              int use_graph);
 parem_status parem_batch_describe(parem_batch b, parem_batch_info *info);

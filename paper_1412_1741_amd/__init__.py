@@ -60,8 +60,8 @@ assert ctypes.sizeof(Result) == RESULT_BYTES
 
 class BatchInfo(ctypes.Structure):
     _fields_ = [("pairs", ctypes.c_uint32), ("walk_launches", ctypes.c_uint32), ("walk_items", ctypes.c_uint64),
-                ("levels", ctypes.c_uint32), ("graph_nodes", ctypes.c_uint32), ("chunks", ctypes.c_uint64),
-                ("text_bytes", ctypes.c_uint64), ("workspace_bytes", ctypes.c_uint64)]
+                ("levels", ctypes.c_uint32), ("graph_nodes", ctypes.c_uint32), ("learned_pairs", ctypes.c_uint32),
+                ("chunks", ctypes.c_uint64), ("text_bytes", ctypes.c_uint64), ("workspace_bytes", ctypes.c_uint64)]
 
 
 def _load() -> ctypes.CDLL:
@@ -110,7 +110,7 @@ def _load() -> ctypes.CDLL:
     lib.parem_match_learned_async.restype = i32
     lib.parem_match_learned_async.argtypes = [vp, vp, u32, vp, u64, vp, u64, vp, vp, vp, vp]
     lib.parem_batch_create.restype = i32
-    lib.parem_batch_create.argtypes = [vp, vp, u32, vp, ctypes.POINTER(vp)]
+    lib.parem_batch_create.argtypes = [vp, vp, u32, vp, vp, vp, ctypes.POINTER(vp)]
     lib.parem_batch_run.restype = i32
     lib.parem_batch_run.argtypes = [vp, vp, vp, vp, i32]
     lib.parem_batch_describe.restype = i32
@@ -298,16 +298,24 @@ def _u64_array(values):
     return np.ascontiguousarray(np.asarray(values, dtype=np.uint64).reshape(-1))
 
 
-def parem_batch_create(handles, lens, opts=None) -> int:
-    """Plan a batch; ``opts`` is None or one Options (or dict of its fields) per pair."""
+def parem_batch_create(handles, lens, opts=None, proposals=None, m=None) -> int:
+    """Plan a batch; ``opts`` is None or one Options (or dict of its fields) per
+    pair; ``proposals`` is None or one proposal handle (or 0: plain) per pair,
+    with ``m`` the top-m of each learned pair."""
     n = len(handles)
     hs = (ctypes.c_void_p * max(n, 1))(*handles)
     ln = _u64_array(lens)
     if ln.size != n:
         raise ValueError("one length per pair")
     oa = _options_array(opts)
+    pa = None
+    ma = None
+    if proposals is not None:
+        pa = (ctypes.c_void_p * max(n, 1))(*[p or None for p in proposals])
+        ma = np.ascontiguousarray(np.asarray(m if m is not None else [0] * n, dtype=np.uint32).reshape(-1))
     b = ctypes.c_void_p()
-    _check(lib().parem_batch_create(hs, ln.ctypes.data, n, oa, ctypes.byref(b)), "parem_batch_create")
+    _check(lib().parem_batch_create(hs, ln.ctypes.data, n, oa, pa, ma.ctypes.data if ma is not None else None,
+                                    ctypes.byref(b)), "parem_batch_create")
     return b.value
 
 
@@ -472,11 +480,13 @@ class Batch:
     """A planned batch of (Matcher, text length) pairs; ``run`` matches one
     set of uint8 device tensors of those lengths (16-byte aligned)."""
 
-    def __init__(self, matchers, lens, opts=None):
-        self.handles = [m.handle for m in matchers]
-        self._matchers = list(matchers)  # the handles must outlive the plan
+    def __init__(self, matchers, lens, opts=None, proposals=None, m=None):
+        self.handles = [m_.handle for m_ in matchers]
+        self._matchers = list(matchers)  # the handles and proposals must outlive the plan
+        self._proposals = list(proposals) if proposals is not None else None
         self.lens = [int(x) for x in lens]
-        self.handle = parem_batch_create(self.handles, self.lens, opts)
+        props = None if proposals is None else [p.handle if p is not None else 0 for p in proposals]
+        self.handle = parem_batch_create(self.handles, self.lens, opts, props, m)
 
     def close(self):
         if self.handle:

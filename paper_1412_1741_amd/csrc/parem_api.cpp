@@ -496,7 +496,7 @@ parem_status parem_boundary_states(parem_handle h, const uint8_t *d_text, uint64
 parem_status parem_learned_workspace_size(parem_handle h, parem_proposal pr, uint64_t len, uint64_t *bytes) {
     if (!h || !pr || !bytes) return PAREM_EINVAL;
     parem::PlainPlan p;
-    parem_status st = parem::plan_learned(h->dev, *pr, len, 16, &p);
+    parem_status st = parem::plan_learned(h->dev, *pr, len, 16, h->dev.opt, &p);
     if (st != PAREM_OK) return st;
     *bytes = p.bytes;
     return PAREM_OK;
@@ -508,7 +508,7 @@ parem_status parem_match_learned_async(parem_handle h, parem_proposal pr, uint32
     if (!h || !pr || !d_out || (len && !d_text) || m == 0 || m > 16) return PAREM_EINVAL;
     if (pr->dfa != &h->dev) return PAREM_EINVAL;
     parem::PlainPlan p;
-    parem_status st = parem::plan_learned(h->dev, *pr, len, m, &p);
+    parem_status st = parem::plan_learned(h->dev, *pr, len, m, h->dev.opt, &p);
     if (st != PAREM_OK) return st;
     if (len && (!d_workspace || workspace_bytes < p.bytes)) return PAREM_EINVAL;
     return parem::launch_learned(h->dev, *pr, p, d_text, d_workspace, reinterpret_cast<hipStream_t>(stream), d_out,

@@ -144,6 +144,12 @@ struct parem_batch_s {
     std::vector<parem::BatchVariant> variants;
     std::vector<parem::BatchLevel> levels;
     std::vector<uint32_t> empties;
+    std::vector<uint32_t> learned;                 // pairs with a proposal
+    std::vector<const parem::Proposal *> props;    // per pair (null: plain)
+    std::vector<uint64_t> ws_off;                  // per pair workspace offset
+    std::vector<const uint8_t *> cap_texts;        // learned pairs' texts in the captured graph
+    hipStream_t lstream = nullptr;                 // branch of the learned pairs
+    hipEvent_t lfork = nullptr, ljoin = nullptr;
     std::vector<uint32_t> look_pairs;
     std::vector<parem::LookItem> look_items;
     uint32_t look_wave = 0;
@@ -180,6 +186,9 @@ static void batch_release(parem_batch_s *b) {
         if (b->join[i]) (void)hipEventDestroy(b->join[i]);
     }
     if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->lstream) (void)hipStreamDestroy(b->lstream);
+    if (b->lfork) (void)hipEventDestroy(b->lfork);
+    if (b->ljoin) (void)hipEventDestroy(b->ljoin);
     if (b->staged) (void)hipEventDestroy(b->staged);
     if (b->h_texts) (void)hipHostFree(b->h_texts);
     (void)hipFree(b->d_meta);
@@ -188,7 +197,7 @@ static void batch_release(parem_batch_s *b) {
 }
 
 static parem_status batch_plan(const parem_handle *dfas, const uint64_t *lens, uint32_t n, const parem_options *opts,
-                               parem_batch_s *b) {
+                               const parem_proposal *props, const uint32_t *m, parem_batch_s *b) {
     if (hipGetDevice(&b->device) != hipSuccess) return PAREM_EDEVICE;
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess)
@@ -197,7 +206,9 @@ static parem_status batch_plan(const parem_handle *dfas, const uint64_t *lens, u
     b->dfas.resize(n);
     b->lens.assign(lens, lens + n);
     b->plans.resize(n);
-    std::vector<uint64_t> ws_off(n, 0);
+    std::vector<uint64_t> &ws_off = b->ws_off;
+    ws_off.assign(n, 0);
+    b->props.assign(n, nullptr);
     std::vector<int> pair_var(n, -1);
     uint64_t ws = 0;
     for (uint32_t i = 0; i < n; ++i) {
@@ -209,6 +220,24 @@ static parem_status batch_plan(const parem_handle *dfas, const uint64_t *lens, u
         if (o.kgram != 0 || o.reserved || o.lookback > kLookMax) return PAREM_EINVAL;
         if (o.chunk_len == 0) o.chunk_len = batch_chunk_len(lens[i]);
         PlainPlan &p = b->plans[i];
+        const Proposal *pr = props ? props[i] : nullptr;
+        if (pr) {
+            // learned speculation: its own launch sequence, on the learned branch
+            if (pr->dfa != &d || !m || m[i] < 1 || m[i] > 16) return PAREM_EINVAL;
+            parem_status st = plan_learned(d, *pr, lens[i], m[i], o, &p);
+            if (st != PAREM_OK) return st;
+            b->text_bytes += lens[i];
+            if (lens[i] == 0) {
+                b->empties.push_back(i);
+                continue;
+            }
+            b->props[i] = pr;
+            b->learned.push_back(i);
+            b->chunks += p.chunks;
+            ws_off[i] = ws;
+            ws = align256(ws + p.bytes);
+            continue;
+        }
         parem_status st = plan_chunks(d, lens[i], o, false, &p);
         if (st != PAREM_OK) return st;
         if (p.G < 4) return PAREM_EUNSUPPORTED;  // batch kernels lock-step 4, 8 or 16 walks
@@ -300,10 +329,10 @@ static parem_status batch_plan(const parem_handle *dfas, const uint64_t *lens, u
     // composition levels
     size_t nlev = 0;
     for (uint32_t i = 0; i < n; ++i)
-        if (lens[i]) nlev = std::max(nlev, b->plans[i].levels.size());
+        if (lens[i] && !b->props[i]) nlev = std::max(nlev, b->plans[i].levels.size());
     b->levels.resize(nlev);
     for (uint32_t i = 0; i < n; ++i) {
-        if (!lens[i]) continue;
+        if (!lens[i] || b->props[i]) continue;
         const PlainPlan &p = b->plans[i];
         const DeviceDfa &d = *b->dfas[i];
         const size_t lds = compose_lds(p.P, p.RM, d.inv_lds);
@@ -314,6 +343,12 @@ static parem_status batch_plan(const parem_handle *dfas, const uint64_t *lens, u
             const uint32_t last = l + 1 == p.levels.size() ? 1u : 0u;
             for (uint64_t s = 0; s < p.levels[l]; ++s) lv.items.push_back(ComposeItem{i, last, s, nin});
         }
+    }
+    if (!b->learned.empty()) {
+        if (hipStreamCreateWithFlags(&b->lstream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&b->lfork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&b->ljoin, hipEventDisableTiming) != hipSuccess)
+            return PAREM_EDEVICE;
     }
     for (BatchLevel &lv : b->levels) {
         if (lv.lds > 64 * 1024 &&
@@ -355,7 +390,7 @@ static parem_status batch_plan(const parem_handle *dfas, const uint64_t *lens, u
         q.start = d.start;
         q.out = d_res + i;
         q.ca = compose_args(d, p);
-        if (lens[i] == 0) continue;
+        if (lens[i] == 0 || b->props[i]) continue;
         q.w = walk_args(d, p, nullptr, pws);
         q.table = d.d_table;
         q.table_bytes = d.table_bytes;
@@ -388,9 +423,22 @@ static parem_status batch_plan(const parem_handle *dfas, const uint64_t *lens, u
     return ok ? PAREM_OK : PAREM_EDEVICE;
 }
 
-// the launches of one run (no host synchronisation: capturable)
-static parem_status batch_enqueue(const parem_batch_s *b, hipStream_t s) {
+// the launches of one run (no host synchronisation: capturable); `host_texts`
+// are the run's text pointers (only learned pairs take them as arguments)
+static parem_status batch_enqueue(const parem_batch_s *b, hipStream_t s, const uint8_t *const *host_texts) {
     const BatchPair *pairs = reinterpret_cast<const BatchPair *>(b->d_meta + b->off_pairs);
+    if (!b->learned.empty()) {
+        // learned pairs: each its own sequence (selection, walk, coverage, composition)
+        parem_result *res = reinterpret_cast<parem_result *>(b->d_meta + b->off_results);
+        if (hipEventRecord(b->lfork, s) != hipSuccess || hipStreamWaitEvent(b->lstream, b->lfork, 0) != hipSuccess)
+            return PAREM_EDEVICE;
+        for (uint32_t i : b->learned) {
+            parem_status st = launch_learned(*b->dfas[i], *b->props[i], b->plans[i], host_texts[i],
+                                             b->d_ws + b->ws_off[i], b->lstream, res + i, nullptr, nullptr);
+            if (st != PAREM_OK) return st;
+        }
+        if (hipEventRecord(b->ljoin, b->lstream) != hipSuccess) return PAREM_EDEVICE;
+    }
     const uint8_t *const *texts = reinterpret_cast<const uint8_t *const *>(b->d_meta + b->off_texts);
     uint32_t *queue = reinterpret_cast<uint32_t *>(b->d_meta + b->off_queue);
     if (!b->look_items.empty())
@@ -431,14 +479,21 @@ static parem_status batch_enqueue(const parem_batch_s *b, hipStream_t s) {
     if (!b->look_pairs.empty())
         hipLaunchKernelGGL(k_batch_look_stats, dim3((uint32_t)b->look_pairs.size()), dim3(256), 0, s, pairs,
                            reinterpret_cast<const uint32_t *>(b->d_meta + b->off_look_pairs));
+    if (!b->learned.empty() && hipStreamWaitEvent(s, b->ljoin, 0) != hipSuccess) return PAREM_EDEVICE;
     return hipGetLastError() == hipSuccess ? PAREM_OK : PAREM_EDEVICE;
 }
 
-static parem_status batch_capture(parem_batch_s *b) {
+static parem_status batch_capture(parem_batch_s *b, const uint8_t *const *host_texts) {
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
+    }
     if (!b->cap_stream && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess)
         return PAREM_EDEVICE;
     if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return PAREM_EDEVICE;
-    parem_status st = batch_enqueue(b, b->cap_stream);
+    parem_status st = batch_enqueue(b, b->cap_stream, host_texts);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
     if (st != PAREM_OK || e != hipSuccess) {
@@ -455,6 +510,8 @@ static parem_status batch_capture(parem_batch_s *b) {
     b->graph = g;
     b->exec = x;
     b->graph_nodes = nodes;
+    b->cap_texts.clear();
+    for (uint32_t i : b->learned) b->cap_texts.push_back(host_texts[i]);
     return PAREM_OK;
 }
 
@@ -475,13 +532,15 @@ static parem_status batch_run(parem_batch_s *b, const uint8_t *const *d_texts, h
     if (hipEventRecord(b->staged, s) != hipSuccess) return PAREM_EDEVICE;
     b->staged_pending = true;
     if (use_graph) {
-        if (!b->exec) {
-            parem_status st = batch_capture(b);
+        bool same = b->exec != nullptr;
+        for (size_t k = 0; same && k < b->learned.size(); ++k) same = b->cap_texts[k] == d_texts[b->learned[k]];
+        if (!same) {
+            parem_status st = batch_capture(b, d_texts);
             if (st != PAREM_OK) return st;
         }
         if (hipGraphLaunch(b->exec, s) != hipSuccess) return PAREM_EDEVICE;
     } else {
-        parem_status st = batch_enqueue(b, s);
+        parem_status st = batch_enqueue(b, s, d_texts);
         if (st != PAREM_OK) return st;
     }
     if (b->n && hipMemcpyAsync(d_out, b->d_meta + b->off_results, (size_t)b->n * sizeof(parem_result),
@@ -495,12 +554,13 @@ static parem_status batch_run(parem_batch_s *b, const uint8_t *const *d_texts, h
 extern "C" {
 
 parem_status parem_batch_create(const parem_handle *dfas, const uint64_t *lens, uint32_t n,
-                                const parem_options *opts, parem_batch *out) {
+                                const parem_options *opts, const parem_proposal *props, const uint32_t *m,
+                                parem_batch *out) {
     if (!out || (n && (!dfas || !lens))) return PAREM_EINVAL;
     *out = nullptr;
     parem_batch_s *b = new (std::nothrow) parem_batch_s;
     if (!b) return PAREM_ENOMEM;
-    parem_status st = parem::batch_plan(dfas, lens, n, opts, b);
+    parem_status st = parem::batch_plan(dfas, lens, n, opts, props, m, b);
     if (st != PAREM_OK) {
         parem::batch_release(b);
         return st;
@@ -525,6 +585,7 @@ parem_status parem_batch_describe(parem_batch b, parem_batch_info *info) {
         for (const parem::BatchLevel &l : b->levels) lv += l.items.empty() ? 0u : 1u;
         info->levels = lv;
         info->graph_nodes = (uint32_t)b->graph_nodes;
+        info->learned_pairs = (uint32_t)b->learned.size();
         info->chunks = b->chunks;
         info->text_bytes = b->text_bytes;
         info->workspace_bytes = b->ws_bytes;
@@ -537,7 +598,7 @@ void parem_batch_free(parem_batch b) { parem::batch_release(b); }
 parem_status parem_match_batch(const parem_handle *dfas, const uint8_t *const *d_texts, const uint64_t *lens,
                                uint32_t n, void *stream, parem_result *d_out) {
     parem_batch b = nullptr;
-    parem_status st = parem_batch_create(dfas, lens, n, nullptr, &b);
+    parem_status st = parem_batch_create(dfas, lens, n, nullptr, nullptr, nullptr, &b);
     if (st != PAREM_OK) return st;
     st = parem_batch_run(b, d_texts, stream, d_out, 1);
     if (st == PAREM_OK && hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) st = PAREM_EDEVICE;
@@ -585,7 +646,8 @@ parem_status parem_tune(parem_handle h, const uint8_t *d_sample, uint64_t sample
         std::vector<const uint8_t *> texts(k, d_sample);
         std::vector<parem_options> o(k, oc);
         parem_batch b = nullptr;
-        if (parem_batch_create(hs.data(), lens.data(), (uint32_t)k, o.data(), &b) != PAREM_OK) continue;
+        if (parem_batch_create(hs.data(), lens.data(), (uint32_t)k, o.data(), nullptr, nullptr, &b) != PAREM_OK)
+            continue;
         // warm-up run (captures the graph), then the timed replays
         st = parem_batch_run(b, texts.data(), stream, d_out, 1);
         if (st == PAREM_OK && hipEventRecord(e0, s) != hipSuccess) st = PAREM_EDEVICE;

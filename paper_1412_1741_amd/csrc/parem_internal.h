@@ -151,7 +151,8 @@ parem_status launch_plain(const DeviceDfa &d, const PlainPlan &p, const uint8_t 
 parem_status plan_boundary(const DeviceDfa &d, uint64_t len, uint32_t L, PlainPlan *p);
 parem_status launch_boundary(const DeviceDfa &d, const PlainPlan &p, const uint8_t *d_text, uint32_t *d_states,
                              void *d_ws, hipStream_t stream);
-parem_status plan_learned(const DeviceDfa &d, const Proposal &pr, uint64_t len, uint32_t m, PlainPlan *p);
+parem_status plan_learned(const DeviceDfa &d, const Proposal &pr, uint64_t len, uint32_t m, const parem_options &o,
+                          PlainPlan *p);
 parem_status launch_learned(const DeviceDfa &d, const Proposal &pr, const PlainPlan &p, const uint8_t *d_text,
                             void *d_ws, hipStream_t stream, parem_result *d_out, hipEvent_t ev_begin,
                             hipEvent_t ev_end);

@@ -477,8 +477,9 @@ parem_status launch_boundary(const DeviceDfa &d, const PlainPlan &p, const uint8
 
 // ---- learned speculation ----
 
-parem_status plan_learned(const DeviceDfa &d, const Proposal &pr, uint64_t len, uint32_t m, PlainPlan *p) {
-    parem_options o = d.opt;
+parem_status plan_learned(const DeviceDfa &d, const Proposal &pr, uint64_t len, uint32_t m, const parem_options &opt,
+                          PlainPlan *p) {
+    parem_options o = opt;
     o.lookback = 0;  // the proposal selects within Algorithm 1's sets
     parem_status st = plan_chunks(d, len, o, false, p);
     if (st != PAREM_OK) return st;

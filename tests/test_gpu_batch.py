@@ -257,3 +257,48 @@ def test_batch_uneven_4096_full_size():
     for i, r in enumerate(got):
         assert r.final_state < dfas[i].num_states, i
         assert r.chunks == 0 or r.spec_runs >= r.chunks
+
+
+def test_batch_learned_pairs():
+    """Pairs with a proposal run learned speculation inside the batch (on a
+    branch of their own); results stay exact with an untrained proposal (many
+    re-walks) and a briefly trained one, in graph and eager runs and across
+    replays with new texts (new pointers re-capture the graph)."""
+    rng = np.random.default_rng(77)
+    pairs = random_pairs(606, 12, max_states=300, max_len=200_000)
+    dna, dtext = W.config2(n=(1 << 20) + 13)
+    dense = W.random_dense_dfa(rng, 1200, bytes(rng.choice(256, size=4, replace=False).astype(np.uint8)),
+                               num_accepting=40)
+    pairs += [(dna, dtext), (dense, W.uniform_text(rng, dense.alphabet, 300_000))]
+    ms = matchers(pairs)
+    lens = [t.size for _, t in pairs]
+    dev = to_device([t for _, t in pairs])
+    say("[case] batch learned: training the DNA proposal")
+    trained, _ = P.train_proposal(ms[-2], dev[-2], W.mlp_init_params(dna.num_states), steps=60, batch=2048,
+                                  lr=2e-3, seed=3)
+    untrained = P.Proposal(ms[-1], W.mlp_init_params(dense.num_states, seed=5))
+    props = [None] * len(pairs)
+    props[-2], props[-1] = trained, untrained
+    mvec = [0] * len(pairs)
+    mvec[-2], mvec[-1] = 4, 2
+    b = P.Batch(ms, lens, [{"chunk_len": 1024}] * len(pairs), props, mvec)
+    assert b.describe()["learned_pairs"] == 2
+    for use_graph in (False, True, True):
+        say(f"[case] batch learned graph={use_graph}")
+        got = b.run(dev, use_graph=use_graph)
+        for i, ((dfa, text), r) in enumerate(zip(pairs, got)):
+            want = oracle.walk_dfa(dfa, text)
+            assert (r.final_state, r.accept, r.count) == (want.final_state, want.accept, want.count), i
+        assert got[-1].rerun_chunks > 0  # the untrained proposal misses
+    # new texts (and pointers) for every pair
+    texts2 = [W.uniform_text(rng, d.alphabet, n) for (d, _), n in zip(pairs, lens)]
+    dev2 = to_device(texts2)
+    say("[case] batch learned: new texts")
+    got = b.run(dev2, use_graph=True)
+    for i, ((dfa, _), text, r) in enumerate(zip(pairs, texts2, got)):
+        want = oracle.walk_dfa(dfa, text)
+        assert (r.final_state, r.accept, r.count) == (want.final_state, want.accept, want.count), i
+    # a proposal of another handle is rejected
+    with pytest.raises(P.ParemError) as e:
+        P.Batch(ms[:1], lens[:1], None, [trained], [4])
+    assert e.value.status == P.PAREM_EINVAL
