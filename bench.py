@@ -103,16 +103,16 @@ def bench_batch(args):
                       file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t0
-    tuner = Autotuner(cache_path=TUNED_CACHE, log=lambda msg: print(f"[bench] tune {msg}", file=sys.stderr,
-                                                                    flush=True))
+    tuner = Autotuner(cache_path=TUNED_CACHE, init_params=W.mlp_init_params,
+                      log=lambda msg: print(f"[bench] tune {msg}", file=sys.stderr, flush=True))
     t0 = time.perf_counter()
-    matchers, opts = tuner.plan(dfas, devs)
+    matchers, opts, props, ms_ = tuner.plan(dfas, devs, proposals=True)
     plan_s = time.perf_counter() - t0
     if args.tune_out:
         tuner.cache_path = args.tune_out
         tuner.save()
     lens = [d.numel() for d in devs]
-    b = P.Batch(matchers, lens, opts)
+    b = P.Batch(matchers, lens, opts, props, ms_)
     out = torch.empty(len(devs) * P.RESULT_BYTES, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
     print("[bench] batch: capture + warm-up", file=sys.stderr, flush=True)
@@ -137,14 +137,24 @@ def bench_batch(args):
         exact &= (r.final_state, r.accept, r.count) == (want.final_state, want.accept, want.count)
     info = b.describe()
     b.close()
+    for pr in props:
+        if pr is not None:
+            pr.close()
     for mm in matchers:
         mm.close()
+    learned_classes = {k: v["learned"] for k, v in tuner.cache.items() if "learned" in v}
     return {"GBps": round(total / (ms * 1e-3) / 1e9, 2), "ms": round(ms, 4), "pairs": len(devs),
             "text_bytes": total, "steps": steps, "use_graph": True, "graph_nodes": info["graph_nodes"],
             "walk_launches": info["walk_launches"], "walk_items": info["walk_items"],
             "compose_levels": info["levels"], "chunks": info["chunks"],
             "workspace_bytes": info["workspace_bytes"], "spec_runs": int(sum(r.spec_runs for r in got)),
             "invalid_pairs": int(sum(r.final_state == P.INVALID_STATE for r in got)),
+            "learned_pairs": info["learned_pairs"], "learned_classes_tried": len(learned_classes),
+            "learned_classes_chosen": sum(1 for v in learned_classes.values() if v.get("use")),
+            "learned_vs_plain": {k: {"learned_ms": round(v["ms"], 4), "m": v["m"],
+                                     "plain_ms": round(tuner.cache[k]["ms_per_copy"], 4),
+                                     "rerun_share": v["rerun_share"]} for k, v in learned_classes.items()},
+            "proposals_trained": tuner.trained, "train_seconds": round(tuner.train_seconds, 2),
             "tuned_classes": len(tuner.cache), "tune_seconds": round(tuner.seconds, 2),
             "tune_candidates_measured": tuner.measured, "plan_seconds": round(plan_s, 2),
             "generate_seconds": round(gen_s, 2), "oracle_checked_pairs": len(host),

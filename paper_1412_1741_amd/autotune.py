@@ -19,6 +19,15 @@ compile step picks, the automatic chunk length, lookback sets when a column
 image is wide): they carry a negligible share of the bytes. Choices persist in a JSON cache keyed by class, so a workload is
 tuned once per machine; ``seconds`` reports the time spent measuring.
 
+For DFAs with at least ``learned_min_states`` states (1024) the tuner also
+tries learned speculation when it is given ``init_params`` (a function of the
+state count returning initial proposal weights): it trains a proposal on the
+pair's own text for ``learned_steps`` AdamW steps (labels: the boundary
+states of the text), times one learned match for top-m in {1, 4, 16}, and
+keeps learned speculation for the class only when it beats the plain
+choice's time per text. Pairs of such classes get a proposal trained on their
+own text when the batch is planned.
+
 Every candidate computes the same result (the sequential run): only speed
 differs, so a choice never affects correctness.
 """
@@ -58,9 +67,15 @@ def size_class(num_states: int, alphabet_size: int, n: int) -> str:
 
 class Autotuner:
     def __init__(self, cache_path: str | None = None, min_tune_bytes: int = 16 << 10, target_bytes: int = 1 << 30,
-                 reps: int = 2, max_copies: int = 256, measure: bool = True, log=None):
+                 reps: int = 2, max_copies: int = 256, measure: bool = True, log=None, init_params=None,
+                 learned_min_states: int = 1024, learned_steps: int = 60):
         self.cache_path = cache_path
         self.log = log
+        self.init_params = init_params
+        self.learned_min_states = learned_min_states
+        self.learned_steps = learned_steps
+        self.trained = 0          # proposals trained while planning
+        self.train_seconds = 0.0
         self.measure = measure  # False: classes missing from the cache keep the defaults
         self.min_tune_bytes = min_tune_bytes
         self.target_bytes = target_bytes
@@ -120,7 +135,49 @@ class Autotuner:
             m.close()
         choice = {"layout": lay, **cands[b], "ms_per_copy": ms[b],
                   "bytes": int(n), "GBps": round(n / (ms[b] * 1e-3) / 1e9, 2) if ms[b] > 0 else None}
+        if self.init_params is not None and dfa.num_states >= self.learned_min_states:
+            choice["learned"] = self._tune_learned(dfa, text, cands[b], ms[b])
         return choice
+
+    def _train(self, matcher, dfa, text):
+        from . import train_proposal
+        t0 = time.perf_counter()
+        prop, _ = train_proposal(matcher, text, self.init_params(dfa.num_states), steps=self.learned_steps,
+                                 batch=2048, lr=2e-3, seed=1)
+        self.train_seconds += time.perf_counter() - t0
+        self.trained += 1
+        return prop
+
+    def _tune_learned(self, dfa, text, plain_opts, plain_ms):
+        """Time learned speculation (one match per top-m) against the plain choice."""
+        import torch
+        from . import Batch
+        m0 = Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting)
+        t0 = time.perf_counter()
+        prop = self._train(m0, dfa, text)
+        opts = [{"chunk_len": int(plain_opts["chunk_len"]), "group": int(plain_opts["group"]),
+                 "tile": int(plain_opts["tile"])}]
+        res = {}
+        for mm in (1, 4, 16):
+            b = Batch([m0], [text.numel()], opts, [prop], [mm])
+            out = b.run_async([text], use_graph=True)  # capture + warm-up
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(self.reps):
+                b.run_async([text], out, use_graph=True)
+            e1.record()
+            torch.cuda.synchronize()
+            r = Batch.results(out, 1)[0]
+            res[mm] = (e0.elapsed_time(e1) / self.reps, r.rerun_chunks / max(r.chunks, 1))
+            b.close()
+        prop.close()
+        m0.close()
+        self.seconds += time.perf_counter() - t0
+        best = min(res, key=lambda k: res[k][0])
+        return {"m": best, "ms": res[best][0], "rerun_share": round(res[best][1], 5),
+                "ms_by_m": {str(k): round(v[0], 4) for k, v in res.items()},
+                "use": bool(res[best][0] < plain_ms)}
 
     # -- planning ------------------------------------------------------------
 
@@ -145,15 +202,37 @@ class Autotuner:
             if self.log:
                 self.log(f"{key}: {self.cache[key]} ({self.seconds:.1f} s so far)")
         c = self.cache[key]
+        if (self.measure and self.init_params is not None and dfa.num_states >= self.learned_min_states
+                and "learned" not in c):
+            c["learned"] = self._tune_learned(dfa, text, c, c["ms_per_copy"])
+            if self.log:
+                self.log(f"{key} learned: {c['learned']} (plain {c['ms_per_copy']:.4f} ms)")
         return int(c["layout"]), {"chunk_len": int(c["chunk_len"]), "group": int(c["group"]),
                                   "tile": int(c["tile"]), "lookback": int(c.get("lookback", 0))}
 
-    def plan(self, dfas, texts):
-        """Matchers compiled with the chosen layouts and per-pair options."""
-        matchers, opts = [], []
+    def learned_m(self, dfa, text) -> int:
+        """top-m when learned speculation was chosen for the pair's class, else 0."""
+        n = text.numel()
+        if self.init_params is None or n < self.min_tune_bytes or dfa.num_states < self.learned_min_states:
+            return 0
+        c = self.cache.get(size_class(dfa.num_states, dfa.alphabet_size, n), {})
+        lr = c.get("learned")
+        return int(lr["m"]) if lr and lr.get("use") else 0
+
+    def plan(self, dfas, texts, proposals: bool = False):
+        """Matchers compiled with the chosen layouts and per-pair options; with
+        ``proposals``, also (proposals, m) for the batch (None / 0 for plain
+        pairs), training a proposal for every pair whose class chose learned
+        speculation."""
+        matchers, opts, props, ms = [], [], [], []
         for dfa, text in zip(dfas, texts):
             lay, o = self.choose(dfa, text)
             m = Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, layout=lay)
             matchers.append(m)
             opts.append(o if o else {"chunk_len": 0})
+            mm = self.learned_m(dfa, text) if proposals else 0
+            props.append(self._train(m, dfa, text) if mm else None)
+            ms.append(mm)
+        if proposals:
+            return matchers, opts, props, ms
         return matchers, opts
