@@ -397,3 +397,17 @@ def test_lookback_invalid_bytes():
                 m.match(dev)
             assert e.value.status == P.PAREM_ESYMBOL
             m.close()
+
+
+def test_config3_full_size():
+    """The large sparse byte DFA over its full 4 GiB Zipf text (the
+    benchmark's sparse workload), hot-row layout, against the oracle."""
+    dfa, text = W.config3()
+    say(f"[case] config3 full: n={text.size}")
+    m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting)
+    assert m.describe()["layout"] == P.LAYOUT_HOT_LDS
+    dev = torch.from_numpy(text).cuda()
+    got = m.match(dev)
+    m.close()
+    want = oracle.walk_dfa(dfa, text)
+    assert (got.final_state, got.accept, got.count) == (want.final_state, want.accept, want.count)

@@ -136,15 +136,29 @@ def zipf_lut(symbols: np.ndarray, s: float = 1.1) -> np.ndarray:
     return lut
 
 
-def zipf_text(rng: np.random.Generator, symbols: np.ndarray, n: int, s: float = 1.1) -> np.ndarray:
+def zipf_text(rng: np.random.Generator, symbols: np.ndarray, n: int, s: float = 1.1,
+              threads: int = 16) -> np.ndarray:
+    """``n`` bytes i.i.d. Zipf(s) over ``symbols`` (rank order). Each 64 MiB
+    block draws from its own generator, seeded from ``rng``, so blocks are
+    generated by several threads with the same result."""
     lut = zipf_lut(symbols, s)
     out = np.empty(n, dtype=np.uint8)
-    pos = 0
-    while pos < n:
+    nblk = (n + _BLOCK - 1) // _BLOCK
+    seeds = rng.integers(0, 2 ** 63, size=nblk)
+
+    def block(k):
+        pos = k * _BLOCK
         m = min(_BLOCK, n - pos)
-        u = np.frombuffer(rng.bytes(2 * m), dtype=np.uint16)
+        u = _random_bytes(np.random.default_rng(int(seeds[k])), 2 * m).view(np.uint16)
         out[pos:pos + m] = lut[u]
-        pos += m
+
+    if nblk <= 1:
+        for k in range(nblk):
+            block(k)
+    else:
+        import concurrent.futures as cf
+        with cf.ThreadPoolExecutor(min(threads, nblk)) as ex:
+            list(ex.map(block, range(nblk)))
     return out
 
 
