@@ -40,6 +40,9 @@ __device__ __forceinline__ uint32_t lds_u16(const uint8_t *base, uint32_t byte_o
 template <typename E, uint32_t ROW>
 struct ByteStep {
     static constexpr bool kRedo = false;  // pieces never need a second pass
+    // byte-at-a-time tables serve large speculated sets: many short passes,
+    // which share one load of the chunk's first 64 bytes
+    static constexpr bool kPrefixPasses = true;
     static constexpr uint32_t kAcc = sizeof(E) * 8 - 1;
     static constexpr uint32_t kMask = (1u << kAcc) - 1u;
     const E *__restrict__ T;
@@ -76,6 +79,7 @@ struct ByteStep {
 // bytes); the sentinel row stays in the sentinel.
 struct ClassStep {
     static constexpr bool kRedo = false;
+    static constexpr bool kPrefixPasses = true;
     const uint8_t *__restrict__ col;   // LDS: [256]
     const uint16_t *__restrict__ T;    // LDS: (Q+1) x (A+1)
     uint32_t A1;                       // A + 1
@@ -116,6 +120,7 @@ struct ClassStep {
 // from the saved states with the global rows for cold states.
 struct HotStep {
     static constexpr bool kRedo = true;
+    static constexpr bool kPrefixPasses = true;
     const uint16_t *__restrict__ hot;   // LDS: H + 1 rows of kHotRow entries
     const uint16_t *__restrict__ ids;   // LDS: state id of each hot slot
     const uint16_t *__restrict__ full;  // global: (Q+1) x 256 entries
@@ -181,6 +186,7 @@ struct HotStep {
 template <int B>
 struct KgStep {
     static constexpr bool kRedo = false;
+    static constexpr bool kPrefixPasses = false;  // small alphabets: few passes
     static constexpr uint32_t K = (B == 3) ? 2 : 4;   // symbols per lookup
     static constexpr uint32_t RS = K * B + 1;         // row bytes = 1 << RS
     static constexpr uint32_t LOW = (1u << RS) - 1u;  // count field
@@ -578,11 +584,31 @@ __device__ __forceinline__ void walk_chunk(const ST &st, const WalkArgs &a, uint
     }
     walk_direct<G, ST, ALIGNED>(st, w, p, ntiles * TILE, len, true, bad);
     bool nonuni = store_pass<G>(st, w, pos, 1, nwalk, true, lead_end, lead_cnt, out, a.nchunks);
-    for (uint32_t first = G; first < nwalk; first += G - 1) {
-        walks_init<G>(st, w, list, pos, nwalk, first);
-        w.merge = a.merge != 0;
-        walk_direct<G, ST, ALIGNED>(st, w, p, 0, len, false, bad);
-        nonuni |= store_pass<G>(st, w, pos, first, nwalk, false, lead_end, lead_cnt, out, a.nchunks);
+    if (nwalk > (uint32_t)G) {
+        // further passes restart at the chunk start and usually merge within a
+        // few bytes: with many passes the first 64 bytes are loaded once for
+        // all of them
+        const bool pre = ST::kPrefixPasses && ALIGNED && len >= 64 && nwalk > 4u * (uint32_t)G;
+        uint4 q0 = make_uint4(0, 0, 0, 0), q1 = q0, q2 = q0, q3 = q0;
+        if (pre) {
+            q0 = load16<true>(p);
+            q1 = load16<true>(p + 16);
+            q2 = load16<true>(p + 32);
+            q3 = load16<true>(p + 48);
+        }
+        for (uint32_t first = G; first < nwalk; first += G - 1) {
+            walks_init<G>(st, w, list, pos, nwalk, first);
+            w.merge = a.merge != 0;
+            uint32_t at = 0;
+            if (pre) {
+                if (w.wave_pending) { piece<G>(st, w, q0, bad); at = 16; }
+                if (w.wave_pending) { piece<G>(st, w, q1, bad); at = 32; }
+                if (w.wave_pending) { piece<G>(st, w, q2, bad); at = 48; }
+                if (w.wave_pending) { piece<G>(st, w, q3, bad); at = 64; }
+            }
+            walk_direct<G, ST, ALIGNED>(st, w, p, at, len, false, bad);
+            nonuni |= store_pass<G>(st, w, pos, first, nwalk, false, lead_end, lead_cnt, out, a.nchunks);
+        }
     }
     if (bad) {
         // a byte outside the alphabet: every walk of this chunk ends in the sentinel
