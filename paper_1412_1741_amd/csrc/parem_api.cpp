@@ -28,6 +28,8 @@ void release(DeviceDfa &d) {
     hipFree(d.d_table);
     hipFree(d.d_cls);
     hipFree(d.d_loff);
+    if (d.d_llist_walk != d.d_llist) hipFree(d.d_llist_walk);
+    d.d_llist_walk = nullptr;
     hipFree(d.d_llist);
     hipFree(d.d_final);
     hipFree(d.d_verify);
@@ -332,6 +334,7 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
     }
 
     parem_status st = PAREM_OK;
+    std::vector<uint16_t> hot_enc;
     if (hipGetDevice(&d.device) != hipSuccess) st = PAREM_EDEVICE;
     if (st == PAREM_OK) {
         if (layout == PAREM_LAYOUT_KGRAM_LDS) {
@@ -374,6 +377,7 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
             std::vector<uint16_t> full, enc;
             if (hot_order.empty()) hot_share(d, t, hot_order);
             hot_tables(d, t, hot_order, image, full, enc);
+            hot_enc = enc;
             d.entry_bytes = 2;
             d.row_stride = parem::kHotRow;
             d.table_bytes = (uint32_t)image.size();
@@ -397,6 +401,13 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
     if (st == PAREM_OK) st = upload(d.cls, &d.d_cls);
     if (st == PAREM_OK) st = upload(d.loff, &d.d_loff);
     if (st == PAREM_OK) st = upload(d.llist, &d.d_llist);
+    d.d_llist_walk = d.d_llist;
+    if (st == PAREM_OK && layout == PAREM_LAYOUT_HOT_LDS) {
+        // walks start from encoded ids: no lookup of the encoding per walk
+        std::vector<uint32_t> enc_list(d.llist.size());
+        for (size_t k = 0; k < d.llist.size(); ++k) enc_list[k] = hot_enc[d.llist[k]];
+        st = upload(enc_list, &d.d_llist_walk);
+    }
     if (st == PAREM_OK) st = upload(d.final_flag, &d.d_final);
     if (st == PAREM_OK && d.Q + 1 <= parem::kLookStates) {
         // next state by class for lookback sets; the sentinel row stays in the sentinel

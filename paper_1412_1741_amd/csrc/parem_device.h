@@ -124,10 +124,11 @@ struct HotStep {
     const uint16_t *__restrict__ hot;   // LDS: H + 1 rows of kHotRow entries
     const uint16_t *__restrict__ ids;   // LDS: state id of each hot slot
     const uint16_t *__restrict__ full;  // global: (Q+1) x 256 entries
-    const uint16_t *__restrict__ enc;   // global: encoded id of each state
+    const uint16_t *__restrict__ enc;   // global: encoded id of each state (unused by the walk)
     uint32_t H;
 
-    __device__ __forceinline__ uint32_t init(uint32_t s) const { return enc[s]; }
+    // walks start from the encoded lists
+    __device__ __forceinline__ uint32_t init(uint32_t s) const { return s; }
     __device__ __forceinline__ uint32_t id(uint32_t r) const { return r < H ? ids[r] : (r & 0x3fffu); }
     __device__ __forceinline__ bool same(uint32_t a, uint32_t b) const { return a == b; }
     __device__ __forceinline__ void fast(uint32_t &s, uint32_t &c, uint32_t byte) const {
@@ -641,6 +642,8 @@ struct LookArgs {
     uint32_t Q, A;
     uint32_t words;         // bitmap words: ceil((Q + 1) / 32)
     const uint8_t *cls;     // byte -> class (A or more: invalid)
+    const uint32_t *loff;   // class lists (the image of every state under one byte)
+    const uint32_t *llist;
     const uint16_t *next;   // (Q+1) x A next state by class
     const uint16_t *inv;    // (A+2) x (Q+1) position of a state in a class list
     uint16_t *sel;          // [nchunks][kLookCap]
@@ -672,15 +675,23 @@ __device__ __forceinline__ bool look_image(const LookArgs &a, uint32_t start, bo
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t W = a.words;
     for (uint32_t w = lane; w < W; w += 64) {
-        const uint32_t lo = w * 32u;  // states 0 .. Q-1 (not the sentinel)
-        uint32_t v;
-        if (from_start) v = (start >> 5) == w ? 1u << (start & 31u) : 0u;
-        else v = lo + 32u <= a.Q ? 0xffffffffu : (a.Q > lo ? (1u << (a.Q - lo)) - 1u : 0u);
-        cur[w] = v;
+        cur[w] = (from_start && (start >> 5) == w) ? 1u << (start & 31u) : 0u;
         nxt[w] = 0;
     }
+    uint32_t k0 = 0;
+    if (!from_start && K > 0) {
+        // the image of every state under the first byte is its column's list
+        const uint32_t col = cl[win[0]];
+        if (col >= a.A) return false;
+        wave_sync();
+        for (uint32_t i = a.loff[col] + lane; i < a.loff[col + 1]; i += 64) {
+            const uint32_t q = a.llist[i];
+            atomicOr(&cur[q >> 5], 1u << (q & 31u));
+        }
+        k0 = 1;
+    }
     wave_sync();
-    for (uint32_t k = 0; k < K; ++k) {
+    for (uint32_t k = k0; k < K; ++k) {
         const uint32_t col = cl[win[k]];
         if (col >= a.A) return false;  // uniform: every lane reads the same byte
         for (uint32_t w = lane; w < W; w += 64) {
@@ -1244,7 +1255,7 @@ inline WalkArgs walk_args(const DeviceDfa &d, const PlainPlan &p, const uint8_t 
     a.nchunks = p.chunks;
     a.cls = d.d_cls;
     a.loff = d.d_loff;
-    a.llist = d.d_llist;
+    a.llist = d.d_llist_walk;
     a.start_class = d.A + 1;
     a.sent = d.sent;
     a.merge = p.merge;
@@ -1264,6 +1275,8 @@ inline LookArgs look_args(const DeviceDfa &d, const PlainPlan &p, const uint8_t 
     a.A = d.A;
     a.words = (d.Q + 1 + 31) / 32;
     a.cls = d.d_cls;
+    a.loff = d.d_loff;
+    a.llist = d.d_llist;
     a.next = d.d_next;
     a.inv = d.d_inv;
     a.sel = reinterpret_cast<uint16_t *>(ws + p.off_sel);

@@ -58,6 +58,7 @@ struct DeviceDfa {
     uint8_t *d_cls = nullptr;
     uint32_t *d_loff = nullptr;
     uint32_t *d_llist = nullptr;
+    uint32_t *d_llist_walk = nullptr; // the lists as walks start from them (hot rows: encoded ids), else d_llist
     uint8_t *d_final = nullptr;
     uint8_t *d_verify = nullptr;     // unused (kept null)
     uint16_t *d_inv = nullptr;       // [(A+2) * (Q+1)] position of a state in each class list, 0xffff if absent
