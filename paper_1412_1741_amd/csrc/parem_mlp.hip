@@ -433,6 +433,224 @@ __global__ void k_topm(const float *__restrict__ Z, uint32_t rows, uint32_t S, c
 }
 
 // ---------------------------------------------------------------------------
+// fused inference: windows -> embeddings -> two GELU layers -> head -> top-m
+// for 128 chunk boundaries per workgroup, intermediates in LDS (heads of at
+// most 64 states). The arithmetic is that of forward_rows: bf16 operands,
+// MFMA fp32 accumulation in the same k order, bf16(gelu(acc + b)) hidden
+// activations, fp32 logits acc + b3, so the logits are the same numbers.
+// ---------------------------------------------------------------------------
+
+constexpr int kFuseRows = 128;            // chunk boundaries per workgroup
+constexpr int kFuseThreads = 512;         // 8 waves, each a 64 x 64 output block
+constexpr int kFuseHeadMax = 64;          // head rows the fused kernel handles
+constexpr int kFuseHRow = kMlpHid + 8;    // LDS row of hidden activations (elements)
+constexpr int kFuseBRow = kKT + 8;        // LDS row of a staged weight k-slice (elements)
+
+struct FuseLds {
+    static constexpr size_t kB = 2 * (size_t)kMlpHid * kFuseBRow * 2;     // double-buffered weight slices
+    static constexpr size_t kH = (size_t)kFuseRows * kFuseHRow * 2;        // hidden activations / logits
+    static constexpr size_t kE = 256 * kMlpEmb * 2;                        // embedding table (bf16)
+    static constexpr size_t kW = (size_t)kFuseRows * kMlpWindow;           // window bytes
+    static constexpr size_t kC = (size_t)kFuseRows * 4;                    // class of each row
+    static constexpr size_t kBytes = kB + kH + kE + kW + kC;
+};
+
+// weight rows [0, R) of W (row length K, bf16) at k-slice k0 .. k0+31 into Bs;
+// rows >= valid are zero
+__device__ __forceinline__ void fuse_load_w(const uint16_t *__restrict__ W, int K, int R, int valid, int k0,
+                                            uint4 (&r)[2]) {
+    const int t = threadIdx.x;
+    const int row = t >> 1, kof = (t & 1) * 16;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        r[h] = make_uint4(0, 0, 0, 0);
+        if (row < R && row < valid) r[h] = *reinterpret_cast<const uint4 *>(W + (size_t)row * K + k0 + kof + 8 * h);
+    }
+}
+__device__ __forceinline__ void fuse_store_w(uint16_t *Bs, int R, const uint4 (&r)[2]) {
+    const int t = threadIdx.x;
+    const int row = t >> 1, kof = (t & 1) * 16;
+    if (row < R) {
+        *reinterpret_cast<uint4 *>(Bs + row * kFuseBRow + kof) = r[0];
+        *reinterpret_cast<uint4 *>(Bs + row * kFuseBRow + kof + 8) = r[1];
+    }
+}
+
+// One dense layer over the workgroup's 128 rows: acc[i][j] (row tile i, col
+// tile j of this wave's block) = sum_k A[row][k] W[col][k]; A from `a_of`.
+template <int TI, int TJ, typename AOf>
+__device__ __forceinline__ void fuse_layer(const uint16_t *__restrict__ W, int K, int R, int valid, uint16_t *Bs,
+                                           int wm, int wn, AOf a_of, f32x16 (&acc)[TI][TJ]) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+    uint4 rb[2];
+    fuse_load_w(W, K, R, valid, 0, rb);
+    fuse_store_w(Bs, R, rb);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = 0; k0 < K; k0 += kKT) {
+        const bool more = k0 + kKT < K;
+        if (more) fuse_load_w(W, K, R, valid, k0 + kKT, rb);
+        const uint16_t *B = Bs + buf * kMlpHid * kFuseBRow;
+#pragma unroll
+        for (int ks = 0; ks < kKT; ks += 8) {
+            const int kk = ks + 4 * (lane >> 5);
+            bf16x4 a[TI], b[TJ];
+#pragma unroll
+            for (int i = 0; i < TI; ++i) a[i] = a_of(wm + 32 * i + (lane & 31), k0 + kk);
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) b[j] = *reinterpret_cast<const bf16x4 *>(B + (wn + 32 * j + (lane & 31)) * kFuseBRow + kk);
+#pragma unroll
+            for (int i = 0; i < TI; ++i)
+#pragma unroll
+                for (int j = 0; j < TJ; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        if (more) fuse_store_w(Bs + (buf ^ 1) * kMlpHid * kFuseBRow, R, rb);
+        __syncthreads();
+        buf ^= 1;
+    }
+}
+
+__global__ __launch_bounds__(kFuseThreads) void k_mlp_select(const uint8_t *__restrict__ text, uint64_t L,
+                                                            uint32_t chunks, const uint8_t *__restrict__ cls,
+                                                            uint32_t start_class, const uint16_t *__restrict__ w16,
+                                                            const float *__restrict__ w32, size_t o_emb, size_t o_W1,
+                                                            size_t o_b1, size_t o_W2, size_t o_b2, size_t o_W3,
+                                                            size_t o_b3, uint32_t S, const uint32_t *__restrict__ loff,
+                                                            const uint32_t *__restrict__ llist, uint32_t m,
+                                                            uint32_t RM, uint16_t *__restrict__ sel,
+                                                            uint8_t *__restrict__ nsel) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    uint16_t *Bs = reinterpret_cast<uint16_t *>(smem);
+    uint16_t *H = reinterpret_cast<uint16_t *>(smem + FuseLds::kB);
+    uint16_t *E = reinterpret_cast<uint16_t *>(smem + FuseLds::kB + FuseLds::kH);
+    uint8_t *Wn = smem + FuseLds::kB + FuseLds::kH + FuseLds::kE;
+    uint32_t *Cl = reinterpret_cast<uint32_t *>(Wn + FuseLds::kW);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t r0 = (uint64_t)blockIdx.x * kFuseRows;
+
+    // windows (chunk 0 has none: its selection is {q0}), classes, embeddings
+    for (int i = tid; i < kFuseRows * kMlpWindow; i += kFuseThreads) {
+        const int r = i / kMlpWindow, k = i % kMlpWindow;
+        const uint64_t c = r0 + r;
+        uint8_t v = 0;
+        if (c > 0 && c < chunks) v = text[c * L - kMlpWindow + k];
+        Wn[i] = v;
+    }
+    for (int r = tid; r < kFuseRows; r += kFuseThreads) {
+        const uint64_t c = r0 + r;
+        Cl[r] = (c == 0 || c >= chunks) ? start_class : (uint32_t)cls[text[c * L - 1]];
+    }
+    for (int i = tid; i < 256 * kMlpEmb / 8; i += kFuseThreads)
+        reinterpret_cast<uint4 *>(E)[i] = reinterpret_cast<const uint4 *>(w16 + o_emb)[i];
+    __syncthreads();
+
+    const int wm = (wave >> 2) * 64, wn = (wave & 3) * 64;
+    f32x16 acc[2][2];
+    // layer 1: A[row][k] = emb[window byte k / 16][k % 16]
+    auto a_emb = [&](int row, int k) {
+        const uint32_t byte = Wn[row * kMlpWindow + (k >> 4)];
+        return *reinterpret_cast<const bf16x4 *>(E + byte * kMlpEmb + (k & 15));
+    };
+    fuse_layer<2, 2>(w16 + o_W1, kMlpIn, kMlpHid, kMlpHid, Bs, wm, wn, a_emb, acc);
+    // h1 = bf16(gelu(acc + b1)) into H
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int n = wn + 32 * j + (lane & 31);
+            const float bn = w32[o_b1 + n];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                H[row * kFuseHRow + n] = f2bf(gelu(acc[i][j][r] + bn));
+            }
+        }
+    __syncthreads();
+    // layer 2: A = h1
+    auto a_h = [&](int row, int k) { return *reinterpret_cast<const bf16x4 *>(H + row * kFuseHRow + k); };
+    fuse_layer<2, 2>(w16 + o_W2, kMlpHid, kMlpHid, kMlpHid, Bs, wm, wn, a_h, acc);
+    // every wave has read h1 (the layer ends with a barrier): overwrite with h2
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int n = wn + 32 * j + (lane & 31);
+            const float bn = w32[o_b2 + n];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int row = wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                H[row * kFuseHRow + n] = f2bf(gelu(acc[i][j][r] + bn));
+            }
+        }
+    __syncthreads();
+    // head: 128 rows x 64 columns (states >= S are zero rows); wave: one 32 x 32 tile
+    f32x16 zacc[1][1];
+    fuse_layer<1, 1>(w16 + o_W3, kMlpHid, kFuseHeadMax, (int)S, Bs, (wave >> 1) * 32, (wave & 1) * 32, a_h, zacc);
+    // the layer ended with a barrier: logits (fp32) over h2
+    float *Z = reinterpret_cast<float *>(H);
+    {
+        const int n = (wave & 1) * 32 + (lane & 31);
+        const float bn = n < (int)S ? w32[o_b3 + n] : 0.0f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = (wave >> 1) * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+            Z[row * kFuseHeadMax + n] = zacc[0][0][r] + bn;
+        }
+    }
+    __syncthreads();
+    // top-m within each row's class list (ties: the lower position), as k_topm
+    if (tid < kFuseRows) {
+        const uint64_t row = r0 + tid;
+        if (row < chunks) {
+            const uint32_t c = Cl[tid];
+            const uint32_t lo = loff[c], sz = loff[c + 1] - lo;
+            uint16_t *out = sel + row * RM;
+            if (sz <= m) {
+                for (uint32_t j = 0; j < sz; ++j) out[j] = (uint16_t)j;
+                nsel[row] = (uint8_t)sz;
+            } else {
+                const float *z = Z + tid * kFuseHeadMax;
+                uint32_t picked[16];
+                float last_v = INFINITY;
+                uint32_t last_j = 0xffffffffu;
+                for (uint32_t t = 0; t < m; ++t) {
+                    float best = -INFINITY;
+                    uint32_t bj = 0xffffffffu;
+                    for (uint32_t j = 0; j < sz; ++j) {
+                        const uint32_t s = llist[lo + j];
+                        const float v = s < S ? z[s] : -INFINITY;
+                        const bool after = t == 0 || v < last_v || (v == last_v && j > last_j);
+                        if (!after) continue;
+                        if (bj == 0xffffffffu || v > best) {
+                            best = v;
+                            bj = j;
+                        }
+                    }
+                    picked[t] = bj;
+                    last_v = best;
+                    last_j = bj;
+                }
+                for (uint32_t a = 1; a < m; ++a)
+                    for (uint32_t b = a; b > 0 && picked[b - 1] > picked[b]; --b) {
+                        const uint32_t x = picked[b];
+                        picked[b] = picked[b - 1];
+                        picked[b - 1] = x;
+                    }
+                for (uint32_t t = 0; t < m; ++t) out[t] = (uint16_t)picked[t];
+                nsel[row] = (uint8_t)m;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 
@@ -584,6 +802,21 @@ size_t proposal_infer_bytes(const Proposal &p, uint64_t rows) {
 parem_status proposal_select(const Proposal &p, const uint8_t *d_text, uint64_t L, uint32_t chunks, uint32_t m,
                              uint32_t RM, void *scratch, hipStream_t s, uint16_t *sel, uint8_t *nsel) {
     const DeviceDfa &d = *p.dfa;
+    if (p.S <= (uint32_t)kFuseHeadMax && L >= 2 * kMlpWindow) {
+        // fused path: no intermediates in memory
+        static bool lds_set = false;
+        if (!lds_set) {
+            if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_mlp_select),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)FuseLds::kBytes) != hipSuccess)
+                return PAREM_EDEVICE;
+            lds_set = true;
+        }
+        hipLaunchKernelGGL(k_mlp_select, dim3((chunks + kFuseRows - 1) / kFuseRows), dim3(kFuseThreads),
+                           FuseLds::kBytes, s, d_text, L, chunks, d.d_cls, d.A + 1, p.d_params16, p.d_params,
+                           p.o_emb, p.o_W1, p.o_b1, p.o_W2, p.o_b2, p.o_W3, p.o_b3, p.S, d.d_loff, d.d_llist, m, RM,
+                           sel, nsel);
+        return hipGetLastError() == hipSuccess ? PAREM_OK : PAREM_EDEVICE;
+    }
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off = round_up(off + bytes, 256); return o; };
     uint16_t *win = at<uint16_t>(scratch, take((size_t)chunks * kMlpWindow * 2));
