@@ -16,6 +16,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -804,13 +805,13 @@ parem_status proposal_select(const Proposal &p, const uint8_t *d_text, uint64_t 
     const DeviceDfa &d = *p.dfa;
     if (p.S <= (uint32_t)kFuseHeadMax && L >= 2 * kMlpWindow) {
         // fused path: no intermediates in memory
-        static bool lds_set = false;
-        if (!lds_set) {
-            if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_mlp_select),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)FuseLds::kBytes) != hipSuccess)
-                return PAREM_EDEVICE;
-            lds_set = true;
-        }
+        static std::once_flag lds_once;
+        static hipError_t lds_err = hipSuccess;
+        std::call_once(lds_once, [] {
+            lds_err = hipFuncSetAttribute(reinterpret_cast<const void *>(k_mlp_select),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)FuseLds::kBytes);
+        });
+        if (lds_err != hipSuccess) return PAREM_EDEVICE;
         hipLaunchKernelGGL(k_mlp_select, dim3((chunks + kFuseRows - 1) / kFuseRows), dim3(kFuseThreads),
                            FuseLds::kBytes, s, d_text, L, chunks, d.d_cls, d.A + 1, p.d_params16, p.d_params,
                            p.o_emb, p.o_W1, p.o_b1, p.o_W2, p.o_b2, p.o_W3, p.o_b3, p.S, d.d_loff, d.d_llist, m, RM,
