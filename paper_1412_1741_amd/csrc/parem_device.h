@@ -26,6 +26,13 @@ struct Stage {
     static constexpr uint32_t kChunksPerLoad = 64 / kPieces;
 };
 
+// u16 at LDS byte address `addr`. The k-gram walk kernels declare no static
+// LDS, so their dynamic LDS (the table first) starts at address 0 and a table
+// offset is an LDS address: the read needs no base addition.
+__device__ __forceinline__ uint32_t lds_u16_abs(uint32_t addr) {
+    return *reinterpret_cast<const __attribute__((address_space(3))) uint16_t *>(static_cast<uintptr_t>(addr));
+}
+
 __device__ __forceinline__ uint32_t lds_u16(const uint8_t *base, uint32_t byte_off) {
     return *reinterpret_cast<const uint16_t *>(base + byte_off);
 }
@@ -183,7 +190,8 @@ struct HotStep {
 };
 
 // k-gram table: a state is carried as its row base (state << RS) plus the
-// count bits of the last entry read.
+// count bits of the last entry read. The table must sit at LDS address 0 (the
+// start of the kernel's dynamic LDS; T is that address).
 template <int B>
 struct KgStep {
     static constexpr bool kRedo = false;
@@ -209,9 +217,9 @@ struct KgStep {
 #pragma unroll
             for (int j = 0; j < G; ++j) {
                 if (j < nw) {
-                    uint32_t e = lds_u16(T, (R[j] & ROWMASK) | i0);
+                    uint32_t e = lds_u16_abs((R[j] & ROWMASK) | i0);
                     S[j] += e;
-                    e = lds_u16(T, (e & ROWMASK) | i1);
+                    e = lds_u16_abs((e & ROWMASK) | i1);
                     R[j] = e;
                     S[j] += e;
                 }
@@ -221,7 +229,7 @@ struct KgStep {
 #pragma unroll
             for (int j = 0; j < G; ++j) {
                 if (j < nw) {
-                    const uint32_t e = lds_u16(T, (R[j] & ROWMASK) | i0);
+                    const uint32_t e = lds_u16_abs((R[j] & ROWMASK) | i0);
                     R[j] = e;
                     S[j] += e;
                 }
@@ -243,7 +251,7 @@ struct KgStep {
         const uint32_t code = (x >> kp.shift) & (kp.cmask4 & 0xffu);
         bad |= (__builtin_amdgcn_perm(kp.vhi, kp.vlo, code) & 0xffu) ^ x;
         const uint32_t row = (R & ROWMASK) >> RS;
-        const uint32_t e = lds_u16(T, kp.t1_off + (((row << B) | code) << 1));
+        const uint32_t e = lds_u16_abs(kp.t1_off + (((row << B) | code) << 1));
         c += e & LOW;
         R = e;
     }
