@@ -293,7 +293,7 @@ static parem_status batch_plan(const parem_handle *dfas, const uint64_t *lens, u
             return pl.RM > pr.RM;
         });
         b->items += x.items.size();
-        x.lds = x.table_cap + (size_t)(x.tile == 64 ? Stage<64>::kBytes : Stage<128>::kBytes);
+        x.lds = x.table_cap + (size_t)(x.tile == 64 ? Stage<64>::kBytes : Stage<128>::kBytes) + 16;  // + queue slot
         if (x.lds > 64 * 1024 &&
             hipFuncSetAttribute(reinterpret_cast<const void *>(x.fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)x.lds) != hipSuccess)

@@ -55,8 +55,10 @@ template <int G, uint32_t TILE, int KIND, int MODE>
 __global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_batch_walk(
     const BatchPair *__restrict__ pairs, const uint8_t *const *__restrict__ texts, const WalkItem *__restrict__ items,
     uint32_t nitems, uint32_t *__restrict__ queue, uint32_t table_cap) {
+    // no static LDS: the k-gram stepper addresses its table as the start of
+    // the dynamic LDS; the queue slot sits after the staging area
     extern __shared__ __align__(16) uint8_t smem[];
-    __shared__ uint32_t s_next;
+    uint32_t &s_next = *reinterpret_cast<uint32_t *>(smem + table_cap + Stage<TILE>::kBytes);
     uint32_t staged = 0xffffffffu;
     for (;;) {
         if (threadIdx.x == 0) s_next = atomicAdd(queue, 1u);
