@@ -9,9 +9,12 @@
 //   z  = W3 h2 + b3                       one logit per state (S = Q rows)
 //   loss = masked softmax cross-entropy over the states of R_c
 //
-// Dense layers run on MFMA (v_mfma_f32_32x32x8_bf16): bf16 operands, fp32
-// accumulation, fp32 master weights updated by AdamW, a bf16 copy feeding the
-// next forward pass. GELU is the erf form.
+// Dense layers run on MFMA: bf16 operands, fp32 accumulation, fp32 master
+// weights updated by AdamW, a bf16 copy feeding the next forward pass. The
+// forward layers (training and inference alike) use v_mfma_f32_32x32x16_bf16,
+// which on gfx950 does twice the work of the 32x32x8 form in about the same
+// time; both forward paths sum k in the same order, so they give the same
+// logits. The backward GEMMs use the 32x32x8 form. GELU is the erf form.
 #include "parem_internal.h"
 
 #include <cmath>
@@ -23,19 +26,51 @@
 namespace parem {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-__device__ __forceinline__ uint16_t f2bf(float f) {
-    // round to nearest, ties to even (finite inputs)
-    uint32_t u = __float_as_uint(f);
-    u += ((u >> 16) & 1u) + 0x7fffu;
-    return (uint16_t)(u >> 16);
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+// bf16 conversions: v_cvt_pk_bf16_f32, round to nearest even
+__device__ __forceinline__ uint32_t f2bf2(float lo, float hi) {
+    const f32x2 v = {lo, hi};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
 }
+__device__ __forceinline__ uint16_t f2bf(float f) { return (uint16_t)f2bf2(f, 0.0f); }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-__device__ __forceinline__ float gelu(float u) { return 0.5f * u * (1.0f + erff(u * 0.70710678118654752f)); }
+// erf by the rational approximation of Abramowitz & Stegun 7.1.26 (after
+// Hastings): |error| <= 1.5e-7 in exact arithmetic, under 5e-7 in fp32 with
+// the hardware reciprocal and exp2. That is far below the bf16 rounding the
+// hidden activations receive, and it has no branches (the library erff
+// evaluates two polynomial branches under divergence).
+__device__ __forceinline__ float erf_fast(float x) {
+    const float ax = fabsf(x);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
+    float p = fmaf(1.061405429f, t, -1.453152027f);
+    p = fmaf(p, t, 1.421413741f);
+    p = fmaf(p, t, -0.284496736f);
+    p = fmaf(p, t, 0.254829592f);
+    p *= t;
+    const float e = __builtin_amdgcn_exp2f(-(ax * ax) * 1.44269504088896341f);  // exp(-x^2)
+    return copysignf(fmaf(-p, e, 1.0f), x);
+}
+// gelu(u) = u Phi(u) = max(u, 0) - |u| Phi(-|u|), with Phi(-|u|) = erfc(|u| / sqrt 2) / 2
+// from the same approximation (erfc(x) = t P(t) exp(-x^2), t = 1 / (1 + p x))
+__device__ __forceinline__ float gelu(float u) {
+    const float au = fabsf(u);
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f * 0.70710678118654752f, au, 1.0f));
+    float p = fmaf(0.5f * 1.061405429f, t, 0.5f * -1.453152027f);
+    p = fmaf(p, t, 0.5f * 1.421413741f);
+    p = fmaf(p, t, 0.5f * -0.284496736f);
+    p = fmaf(p, t, 0.5f * 0.254829592f);
+    p *= t;
+    const float q = p * __builtin_amdgcn_exp2f((u * u) * (-0.5f * 1.44269504088896341f));
+    return fmaf(-au, q, fmaxf(u, 0.0f));
+}
 __device__ __forceinline__ float gelu_grad(float u) {
-    return 0.5f * (1.0f + erff(u * 0.70710678118654752f)) + u * 0.39894228040143268f * expf(-0.5f * u * u);
+    return 0.5f * (1.0f + erf_fast(u * 0.70710678118654752f)) +
+           u * 0.39894228040143268f * __builtin_amdgcn_exp2f(-0.5f * u * u * 1.44269504088896341f);
 }
 
 // ---------------------------------------------------------------------------
@@ -133,7 +168,8 @@ __global__ __launch_bounds__(kGemmT) void k_gemm(const uint16_t *__restrict__ A,
 
 // Forward-layer GEMM, both operands K-contiguous: C[M,N] = A[M,K] B[N,K]^T.
 // 128 x 128 output tile per workgroup; each wave computes a 64 x 64 block as
-// 2 x 2 MFMA 32 x 32 tiles. K advances 32 per stage through double-buffered
+// 2 x 2 MFMA 32 x 32 tiles (32x32x16: lane l holds A[m = l % 32][k = 8 (l / 32)
+// + i] and B[k = 8 (l / 32) + i][n = l % 32], i < 8). K advances 32 per stage through double-buffered
 // LDS tiles filled with 16-byte loads (rows padded to 40 elements). K must be
 // a multiple of 32 and lda/ldb multiples of 8.
 constexpr int kNtRow = 40;
@@ -184,19 +220,19 @@ __global__ __launch_bounds__(kGemmT) void k_gemm_nt(const uint16_t *__restrict__
         const bool more = k0 + kKT < K;
         if (more) load(k0 + kKT, ra, rb);
 #pragma unroll
-        for (int ks = 0; ks < kKT; ks += 8) {
-            const int kk = ks + 4 * (lane >> 5);
-            bf16x4 a[2], b[2];
+        for (int ks = 0; ks < kKT; ks += 16) {
+            const int kk = ks + 8 * (lane >> 5);
+            bf16x8 a[2], b[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                a[i] = *reinterpret_cast<const bf16x4 *>(&As[buf][wm + 32 * i + (lane & 31)][kk]);
-                b[i] = *reinterpret_cast<const bf16x4 *>(&Bs[buf][wn + 32 * i + (lane & 31)][kk]);
+                a[i] = *reinterpret_cast<const bf16x8 *>(&As[buf][wm + 32 * i + (lane & 31)][kk]);
+                b[i] = *reinterpret_cast<const bf16x8 *>(&Bs[buf][wn + 32 * i + (lane & 31)][kk]);
             }
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         }
         if (more) store(buf ^ 1, ra, rb);
         __syncthreads();
@@ -445,40 +481,46 @@ constexpr int kFuseRows = 128;            // chunk boundaries per workgroup
 constexpr int kFuseThreads = 512;         // 8 waves, each a 64 x 64 output block
 constexpr int kFuseHeadMax = 64;          // head rows the fused kernel handles
 constexpr int kFuseHRow = kMlpHid + 8;    // LDS row of hidden activations (elements)
-constexpr int kFuseBRow = kKT + 8;        // LDS row of a staged weight k-slice (elements)
+constexpr int kFuseKT = 64;               // weight k-slice per stage (elements)
+constexpr int kFuseBRow = kFuseKT + 8;    // LDS row of a staged weight k-slice (elements)
 
 struct FuseLds {
     static constexpr size_t kB = 2 * (size_t)kMlpHid * kFuseBRow * 2;     // double-buffered weight slices
     static constexpr size_t kH = (size_t)kFuseRows * kFuseHRow * 2;        // hidden activations / logits
     static constexpr size_t kE = 256 * kMlpEmb * 2;                        // embedding table (bf16)
     static constexpr size_t kW = (size_t)kFuseRows * kMlpWindow;           // window bytes
-    static constexpr size_t kC = (size_t)kFuseRows * 4;                    // class of each row
+    static constexpr size_t kC = (size_t)kFuseRows * 8;                    // class list (offset, size) per row
     static constexpr size_t kBytes = kB + kH + kE + kW + kC;
 };
+// after the head, the weight slices' space holds each row's logits in class
+// list order (padded row against bank conflicts)
+constexpr int kFuseKeyRow = kFuseHeadMax + 1;
+static_assert((size_t)kFuseRows * kFuseKeyRow * 4 <= FuseLds::kB, "list logits fit the weight slices");
 
-// weight rows [0, R) of W (row length K, bf16) at k-slice k0 .. k0+31 into Bs;
-// rows >= valid are zero
+// weight rows [0, R) of W (row length K, bf16) at k-slice k0 .. k0+63 into Bs;
+// rows >= valid are zero. Thread t stages 32 elements of row t / 2.
 __device__ __forceinline__ void fuse_load_w(const uint16_t *__restrict__ W, int K, int R, int valid, int k0,
-                                            uint4 (&r)[2]) {
+                                            uint4 (&r)[4]) {
     const int t = threadIdx.x;
-    const int row = t >> 1, kof = (t & 1) * 16;
+    const int row = t >> 1, kof = (t & 1) * 32;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < 4; ++h) {
         r[h] = make_uint4(0, 0, 0, 0);
         if (row < R && row < valid) r[h] = *reinterpret_cast<const uint4 *>(W + (size_t)row * K + k0 + kof + 8 * h);
     }
 }
-__device__ __forceinline__ void fuse_store_w(uint16_t *Bs, int R, const uint4 (&r)[2]) {
+__device__ __forceinline__ void fuse_store_w(uint16_t *Bs, int R, const uint4 (&r)[4]) {
     const int t = threadIdx.x;
-    const int row = t >> 1, kof = (t & 1) * 16;
+    const int row = t >> 1, kof = (t & 1) * 32;
     if (row < R) {
-        *reinterpret_cast<uint4 *>(Bs + row * kFuseBRow + kof) = r[0];
-        *reinterpret_cast<uint4 *>(Bs + row * kFuseBRow + kof + 8) = r[1];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) *reinterpret_cast<uint4 *>(Bs + row * kFuseBRow + kof + 8 * h) = r[h];
     }
 }
 
 // One dense layer over the workgroup's 128 rows: acc[i][j] (row tile i, col
-// tile j of this wave's block) = sum_k A[row][k] W[col][k]; A from `a_of`.
+// tile j of this wave's block) = sum_k A[row][k] W[col][k]; A from `a_of`
+// (8 consecutive k per lane, the 32x32x16 operand layout of k_gemm_nt).
 template <int TI, int TJ, typename AOf>
 __device__ __forceinline__ void fuse_layer(const uint16_t *__restrict__ W, int K, int R, int valid, uint16_t *Bs,
                                            int wm, int wn, AOf a_of, f32x16 (&acc)[TI][TJ]) {
@@ -489,28 +531,28 @@ __device__ __forceinline__ void fuse_layer(const uint16_t *__restrict__ W, int K
         for (int j = 0; j < TJ; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
-    uint4 rb[2];
+    uint4 rb[4];
     fuse_load_w(W, K, R, valid, 0, rb);
     fuse_store_w(Bs, R, rb);
     __syncthreads();
     int buf = 0;
-    for (int k0 = 0; k0 < K; k0 += kKT) {
-        const bool more = k0 + kKT < K;
-        if (more) fuse_load_w(W, K, R, valid, k0 + kKT, rb);
+    for (int k0 = 0; k0 < K; k0 += kFuseKT) {
+        const bool more = k0 + kFuseKT < K;
+        if (more) fuse_load_w(W, K, R, valid, k0 + kFuseKT, rb);
         const uint16_t *B = Bs + buf * kMlpHid * kFuseBRow;
 #pragma unroll
-        for (int ks = 0; ks < kKT; ks += 8) {
-            const int kk = ks + 4 * (lane >> 5);
-            bf16x4 a[TI], b[TJ];
+        for (int ks = 0; ks < kFuseKT; ks += 16) {
+            const int kk = ks + 8 * (lane >> 5);
+            bf16x8 a[TI], b[TJ];
 #pragma unroll
             for (int i = 0; i < TI; ++i) a[i] = a_of(wm + 32 * i + (lane & 31), k0 + kk);
 #pragma unroll
-            for (int j = 0; j < TJ; ++j) b[j] = *reinterpret_cast<const bf16x4 *>(B + (wn + 32 * j + (lane & 31)) * kFuseBRow + kk);
+            for (int j = 0; j < TJ; ++j) b[j] = *reinterpret_cast<const bf16x8 *>(B + (wn + 32 * j + (lane & 31)) * kFuseBRow + kk);
 #pragma unroll
             for (int i = 0; i < TI; ++i)
 #pragma unroll
                 for (int j = 0; j < TJ; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         }
         if (more) fuse_store_w(Bs + (buf ^ 1) * kMlpHid * kFuseBRow, R, rb);
         __syncthreads();
@@ -536,20 +578,35 @@ __global__ __launch_bounds__(kFuseThreads) void k_mlp_select(const uint8_t *__re
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint64_t r0 = (uint64_t)blockIdx.x * kFuseRows;
 
-    // windows (chunk 0 has none: its selection is {q0}), classes, embeddings
-    for (int i = tid; i < kFuseRows * kMlpWindow; i += kFuseThreads) {
-        const int r = i / kMlpWindow, k = i % kMlpWindow;
+    // windows (chunk 0 has none: its selection is {q0}) and the embedding
+    // table, every load issued before the first wait. Row r's window is
+    // text[c L - 32, c L) with c = r0 + r; thread 2r + h holds its half h.
+    // The class of the byte before the boundary (the window's last byte) is
+    // looked up by thread 2r + 1 and used only at the end.
+    uint32_t cls_row = start_class;
+    if (tid < 2 * kFuseRows) {
+        const int r = tid >> 1, h = tid & 1;
         const uint64_t c = r0 + r;
-        uint8_t v = 0;
-        if (c > 0 && c < chunks) v = text[c * L - kMlpWindow + k];
-        Wn[i] = v;
+        const bool live = c > 0 && c < chunks;
+        const uint8_t *src = text + c * L - kMlpWindow + 16 * h;
+        uint32_t last = 0;
+        if (((reinterpret_cast<uintptr_t>(text) | L) & 15) == 0) {
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (live) v = *reinterpret_cast<const uint4 *>(src);
+            reinterpret_cast<uint4 *>(Wn)[tid] = v;
+            last = v.w >> 24;
+        } else {
+            uint8_t v[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) v[k] = live ? src[k] : (uint8_t)0;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) Wn[16 * tid + k] = v[k];
+            last = v[15];
+        }
+        if (h == 1 && live) cls_row = cls[last];
     }
-    for (int r = tid; r < kFuseRows; r += kFuseThreads) {
-        const uint64_t c = r0 + r;
-        Cl[r] = (c == 0 || c >= chunks) ? start_class : (uint32_t)cls[text[c * L - 1]];
-    }
-    for (int i = tid; i < 256 * kMlpEmb / 8; i += kFuseThreads)
-        reinterpret_cast<uint4 *>(E)[i] = reinterpret_cast<const uint4 *>(w16 + o_emb)[i];
+    reinterpret_cast<uint4 *>(E)[tid] = reinterpret_cast<const uint4 *>(w16 + o_emb)[tid];
+    static_assert(256 * kMlpEmb / 8 == kFuseThreads, "one 16-byte piece of the embedding table per thread");
     __syncthreads();
 
     const int wm = (wave >> 2) * 64, wn = (wave & 3) * 64;
@@ -557,7 +614,7 @@ __global__ __launch_bounds__(kFuseThreads) void k_mlp_select(const uint8_t *__re
     // layer 1: A[row][k] = emb[window byte k / 16][k % 16]
     auto a_emb = [&](int row, int k) {
         const uint32_t byte = Wn[row * kMlpWindow + (k >> 4)];
-        return *reinterpret_cast<const bf16x4 *>(E + byte * kMlpEmb + (k & 15));
+        return *reinterpret_cast<const bf16x8 *>(E + byte * kMlpEmb + (k & 15));
     };
     fuse_layer<2, 2>(w16 + o_W1, kMlpIn, kMlpHid, kMlpHid, Bs, wm, wn, a_emb, acc);
     // h1 = bf16(gelu(acc + b1)) into H
@@ -567,15 +624,17 @@ __global__ __launch_bounds__(kFuseThreads) void k_mlp_select(const uint8_t *__re
         for (int j = 0; j < 2; ++j) {
             const int n = wn + 32 * j + (lane & 31);
             const float bn = w32[o_b1 + n];
+            uint16_t *hp = H + (wm + 32 * i + 4 * (lane >> 5)) * kFuseHRow + n;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                H[row * kFuseHRow + n] = f2bf(gelu(acc[i][j][r] + bn));
+            for (int r = 0; r < 16; r += 2) {
+                const uint32_t pk = f2bf2(gelu(acc[i][j][r] + bn), gelu(acc[i][j][r + 1] + bn));
+                hp[(8 * (r >> 2) + (r & 3)) * kFuseHRow] = (uint16_t)pk;
+                hp[(8 * (r >> 2) + (r & 3) + 1) * kFuseHRow] = (uint16_t)(pk >> 16);
             }
         }
     __syncthreads();
     // layer 2: A = h1
-    auto a_h = [&](int row, int k) { return *reinterpret_cast<const bf16x4 *>(H + row * kFuseHRow + k); };
+    auto a_h = [&](int row, int k) { return *reinterpret_cast<const bf16x8 *>(H + row * kFuseHRow + k); };
     fuse_layer<2, 2>(w16 + o_W2, kMlpHid, kMlpHid, kMlpHid, Bs, wm, wn, a_h, acc);
     // every wave has read h1 (the layer ends with a barrier): overwrite with h2
 #pragma unroll
@@ -584,10 +643,12 @@ __global__ __launch_bounds__(kFuseThreads) void k_mlp_select(const uint8_t *__re
         for (int j = 0; j < 2; ++j) {
             const int n = wn + 32 * j + (lane & 31);
             const float bn = w32[o_b2 + n];
+            uint16_t *hp = H + (wm + 32 * i + 4 * (lane >> 5)) * kFuseHRow + n;
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int row = wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                H[row * kFuseHRow + n] = f2bf(gelu(acc[i][j][r] + bn));
+            for (int r = 0; r < 16; r += 2) {
+                const uint32_t pk = f2bf2(gelu(acc[i][j][r] + bn), gelu(acc[i][j][r + 1] + bn));
+                hp[(8 * (r >> 2) + (r & 3)) * kFuseHRow] = (uint16_t)pk;
+                hp[(8 * (r >> 2) + (r & 3) + 1) * kFuseHRow] = (uint16_t)(pk >> 16);
             }
         }
     __syncthreads();
@@ -605,48 +666,75 @@ __global__ __launch_bounds__(kFuseThreads) void k_mlp_select(const uint8_t *__re
             Z[row * kFuseHeadMax + n] = zacc[0][0][r] + bn;
         }
     }
+    // each row's class list: (offset, size)
+    if (tid < 2 * kFuseRows && (tid & 1)) {
+        const uint32_t lo = loff[cls_row];
+        Cl[2 * (tid >> 1)] = lo;
+        Cl[2 * (tid >> 1) + 1] = loff[cls_row + 1] - lo;
+    }
     __syncthreads();
-    // top-m within each row's class list (ties: the lower position), as k_topm
+    // logits in list order into the weight slices' space (free after the head)
+    // (every list load is issued before the first is used)
+    float *Key = reinterpret_cast<float *>(Bs);
+    constexpr int kKeyIters = kFuseRows * kFuseHeadMax / kFuseThreads;
+    uint32_t stv[kKeyIters];
+#pragma unroll
+    for (int q = 0; q < kKeyIters; ++q) {
+        const int i = tid + q * kFuseThreads, r = i / kFuseHeadMax, j = i % kFuseHeadMax;
+        stv[q] = j < (int)Cl[2 * r + 1] ? llist[Cl[2 * r] + j] : 0xffffffffu;
+    }
+#pragma unroll
+    for (int q = 0; q < kKeyIters; ++q) {
+        const int i = tid + q * kFuseThreads, r = i / kFuseHeadMax, j = i % kFuseHeadMax;
+        if (stv[q] != 0xffffffffu) Key[r * kFuseKeyRow + j] = Z[r * kFuseHeadMax + stv[q]];
+    }
+    __syncthreads();
+    // top-m within each row's class list (at most 64 positions), in the order
+    // (logit descending, position ascending) as k_topm: min(m, sz - m) passes,
+    // each taking the best remaining position or dropping the worst kept one
+    // (the last of the order); the kept positions are written ascending.
     if (tid < kFuseRows) {
         const uint64_t row = r0 + tid;
         if (row < chunks) {
-            const uint32_t c = Cl[tid];
-            const uint32_t lo = loff[c], sz = loff[c + 1] - lo;
-            uint16_t *out = sel + row * RM;
-            if (sz <= m) {
-                for (uint32_t j = 0; j < sz; ++j) out[j] = (uint16_t)j;
-                nsel[row] = (uint8_t)sz;
-            } else {
-                const float *z = Z + tid * kFuseHeadMax;
-                uint32_t picked[16];
-                float last_v = INFINITY;
-                uint32_t last_j = 0xffffffffu;
-                for (uint32_t t = 0; t < m; ++t) {
-                    float best = -INFINITY;
-                    uint32_t bj = 0xffffffffu;
+            const uint32_t sz = Cl[2 * tid + 1];
+            const float *z = Key + tid * kFuseKeyRow;
+            const uint32_t take = sz < m ? sz : m;
+            uint64_t keep = sz >= 64 ? ~0ull : (1ull << sz) - 1;
+            if (take < sz && take <= sz - take) {
+                keep = 0;
+                for (uint32_t t = 0; t < take; ++t) {
+                    float best = 0.0f;
+                    int bj = -1;
+#pragma unroll 8
                     for (uint32_t j = 0; j < sz; ++j) {
-                        const uint32_t s = llist[lo + j];
-                        const float v = s < S ? z[s] : -INFINITY;
-                        const bool after = t == 0 || v < last_v || (v == last_v && j > last_j);
-                        if (!after) continue;
-                        if (bj == 0xffffffffu || v > best) {
+                        const float v = z[j];
+                        if (!((keep >> j) & 1ull) && (bj < 0 || v > best)) {
                             best = v;
-                            bj = j;
+                            bj = (int)j;
                         }
                     }
-                    picked[t] = bj;
-                    last_v = best;
-                    last_j = bj;
+                    keep |= 1ull << bj;
                 }
-                for (uint32_t a = 1; a < m; ++a)
-                    for (uint32_t b = a; b > 0 && picked[b - 1] > picked[b]; --b) {
-                        const uint32_t x = picked[b];
-                        picked[b] = picked[b - 1];
-                        picked[b - 1] = x;
+            } else if (take < sz) {
+                for (uint32_t t = 0; t < sz - take; ++t) {
+                    float worst = 0.0f;
+                    int wj = -1;
+#pragma unroll 8
+                    for (uint32_t j = 0; j < sz; ++j) {
+                        const float v = z[j];
+                        if (((keep >> j) & 1ull) && (wj < 0 || v <= worst)) {
+                            worst = v;
+                            wj = (int)j;
+                        }
                     }
-                for (uint32_t t = 0; t < m; ++t) out[t] = (uint16_t)picked[t];
-                nsel[row] = (uint8_t)m;
+                    keep &= ~(1ull << wj);
+                }
             }
+            uint16_t *out = sel + row * RM;
+            uint32_t o = 0;
+            for (uint32_t j = 0; j < sz; ++j)
+                if ((keep >> j) & 1ull) out[o++] = (uint16_t)j;
+            nsel[row] = (uint8_t)take;
         }
     }
 }
