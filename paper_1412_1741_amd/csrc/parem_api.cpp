@@ -37,7 +37,9 @@ void release(DeviceDfa &d) {
     hipFree(d.d_full);
     hipFree(d.d_enc);
     hipFree(d.d_next);
+    hipFree(d.d_step);
     d.d_next = nullptr;
+    d.d_step = nullptr;
     d.d_inv = nullptr;
     d.d_full = nullptr;
     d.d_enc = nullptr;
@@ -416,6 +418,17 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
             for (uint32_t a = 0; a < d.A; ++a)
                 nx[(size_t)q * d.A + a] = (uint16_t)(q < d.Q ? t[(size_t)q * d.A + a] : d.sent);
         st = upload(nx, &d.d_next);
+    }
+    if (st == PAREM_OK && (uint64_t)(d.Q + 1) * (d.A + 1) <= parem::kSplitTable) {
+        // next state by class with the invalid class A, final flag in bit 15
+        // (the sub-chunk re-walk of learned speculation stages it in LDS)
+        std::vector<uint16_t> sx((size_t)(d.Q + 1) * (d.A + 1));
+        for (uint32_t q = 0; q <= d.Q; ++q)
+            for (uint32_t a = 0; a <= d.A; ++a) {
+                const uint32_t e = (q < d.Q && a < d.A) ? t[(size_t)q * d.A + a] : d.sent;
+                sx[(size_t)q * (d.A + 1) + a] = (uint16_t)(e | (e < d.Q && d.final_flag[e] ? 0x8000u : 0u));
+            }
+        st = upload(sx, &d.d_step);
     }
     // inverse index of the class lists (composition looks up the position of
     // an end state in the next chunk's list); skipped when it would be huge

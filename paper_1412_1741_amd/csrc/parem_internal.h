@@ -67,6 +67,7 @@ struct DeviceDfa {
     uint16_t *d_full = nullptr;      // (Q+1) x 256 byte table with encoded destinations
     uint16_t *d_next = nullptr;      // [(Q+1) x A] next state by class (lookback sets); row Q: the sentinel
     uint16_t *d_enc = nullptr;       // [Q+1] encoded id of each state (slot when hot, 0x4000 | id else)
+    uint16_t *d_step = nullptr;      // [(Q+1) x (A+1)] next state by class | final << 15 (small tables only)
     uint32_t hot_rows = 0;
 };
 
@@ -131,13 +132,15 @@ struct PlainPlan {
     std::vector<uint64_t> entries; // boundary states: entry states per level
     uint64_t bytes = 0;
     uint64_t off_map = 0, off_mcls = 0, off_mlead = 0, off_dummy = 0;
-    uint64_t off_sel = 0, off_nsel = 0, off_redo = 0, off_done = 0, off_flags = 0, off_mlp = 0;
+    uint64_t off_sel = 0, off_nsel = 0, off_redo = 0, off_done = 0, off_flags = 0, off_mlp = 0, off_rlist = 0, off_part = 0;
 };
 
 constexpr uint32_t kByteLdsRow = 260;  // row stride of the LDS byte table
 constexpr uint32_t kMaxChunk = 32768;  // chunk maps pack a count < 2^16 beside the end state
 
 constexpr int kCoverRounds = 3;         // coverage rounds before every incomplete chunk is walked again
+constexpr uint32_t kSplitMax = 2048;    // most chunks of a round walked again in sub-chunks
+constexpr uint32_t kSplitTable = 8192;  // largest (Q+1) x (A+1) table for the sub-chunk walk
 
 constexpr uint32_t kLookMax = 4096;     // longest lookback window
 constexpr uint32_t kLookCap = 64;       // largest lookback set walked as a selection

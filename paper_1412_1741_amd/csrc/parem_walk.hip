@@ -34,6 +34,8 @@
 // {q0}) remains, whose single entry is the result.
 #include "parem_device.h"
 
+#include <mutex>
+
 namespace parem {
 
 __global__ __launch_bounds__(kComposeThreads) void k_compose_chunks(const uint32_t *__restrict__ map,
@@ -88,11 +90,15 @@ __device__ __forceinline__ int chunk_present(const uint32_t *__restrict__ map, u
 __global__ void k_cover(const uint32_t *__restrict__ map, const uint16_t *__restrict__ map_cls,
                         const uint16_t *__restrict__ map_lead, uint64_t C, const uint32_t *__restrict__ loff,
                         const uint16_t *__restrict__ inv, uint32_t Q1, uint32_t sent, uint8_t *__restrict__ redo,
-                        uint8_t *__restrict__ done, uint32_t *__restrict__ flags, uint32_t escalate) {
+                        uint8_t *__restrict__ done, uint32_t *__restrict__ flags, uint32_t escalate,
+                        uint32_t *__restrict__ round_count, uint32_t *__restrict__ rlist, uint32_t first) {
     const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= C) return;
     redo[c] = 0;
-    if (c == 0 || done[c]) return;
+    // the first round starts every chunk as not walked from its whole set
+    const bool was_done = first ? false : done[c] != 0;
+    if (first) done[c] = 0;
+    if (c == 0 || was_done) return;
     const uint32_t pv = map_cls[c - 1], cv = map_cls[c];
     const uint32_t pcls = pv & 0x7fffu, ccls = cv & 0x7fffu;
     bool covered = true;
@@ -115,52 +121,284 @@ __global__ void k_cover(const uint32_t *__restrict__ map, const uint16_t *__rest
             redo[c] = 1;
             done[c] = 1;
             atomicAdd(&flags[0], 1u);
+            const uint32_t at = atomicAdd(round_count, 1u);
+            if (at < kSplitMax) rlist[at] = (uint32_t)c;
         }
     }
 }
 
 // second half of an escalation: if some chunk is still uncovered, every
-// chunk not yet walked from its whole set is marked
+// chunk not yet walked from its whole set is marked. The marks are final
+// here, so the statistics are summed too: walks started (the selection, plus
+// the whole set of a marked chunk) and chunks walked again; one partial pair
+// per block (256 threads), added up by k_stats_total.
 __global__ void k_escalate(uint64_t C, uint8_t *__restrict__ redo, uint8_t *__restrict__ done,
-                           uint32_t *__restrict__ flags) {
+                           uint32_t *__restrict__ flags, uint32_t *__restrict__ round_count,
+                           uint32_t *__restrict__ rlist, const uint8_t *__restrict__ nsel,
+                           const uint16_t *__restrict__ map_cls, const uint32_t *__restrict__ loff,
+                           unsigned long long *__restrict__ part_out) {
     const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= C || flags[1] == 0 || c == 0) return;
-    if (!done[c]) {
-        redo[c] = 1;
-        done[c] = 1;
-        atomicAdd(&flags[0], 1u);
-    }
-}
-
-// walks started and chunks walked again: block partial sums, then the
-// result is written by k_learned_total
-__global__ void k_learned_stats(const uint8_t *__restrict__ nsel, const uint8_t *__restrict__ done,
-                                const uint16_t *__restrict__ map_cls, const uint32_t *__restrict__ loff, uint64_t C,
-                                unsigned long long *__restrict__ acc) {
-    const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    unsigned long long runs = 0, redo = 0;
+    unsigned long long runs = 0, again = 0;
     if (c < C) {
+        bool dn = done[c] != 0;
+        if (c > 0 && !dn && flags[1] != 0) {
+            redo[c] = 1;
+            done[c] = 1;
+            atomicAdd(&flags[0], 1u);
+            const uint32_t at = atomicAdd(round_count, 1u);
+            if (at < kSplitMax) rlist[at] = (uint32_t)c;
+            dn = true;
+        }
         runs = nsel[c];
-        if (done[c]) {
+        if (dn) {
             const uint32_t cl = map_cls[c] & 0x7fffu;
             runs += loff[cl + 1] - loff[cl];
-            redo = 1;
+            again = 1;
         }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         runs += (unsigned long long)__shfl_xor((long long)runs, o, 64);
-        redo += (unsigned long long)__shfl_xor((long long)redo, o, 64);
+        again += (unsigned long long)__shfl_xor((long long)again, o, 64);
     }
-    __shared__ unsigned long long part[2][4];
+    __shared__ unsigned long long sum[2][4];
     if ((threadIdx.x & 63u) == 0) {
-        part[0][threadIdx.x >> 6] = runs;
-        part[1][threadIdx.x >> 6] = redo;
+        sum[0][threadIdx.x >> 6] = runs;
+        sum[1][threadIdx.x >> 6] = again;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        atomicAdd(&acc[0], part[0][0] + part[0][1] + part[0][2] + part[0][3]);
-        atomicAdd(&acc[1], part[1][0] + part[1][1] + part[1][2] + part[1][3]);
+        part_out[2 * blockIdx.x] = sum[0][0] + sum[0][1] + sum[0][2] + sum[0][3];
+        part_out[2 * blockIdx.x + 1] = sum[1][0] + sum[1][1] + sum[1][2] + sum[1][3];
+    }
+}
+
+// the learned statistics into the result: sums of n partial pairs
+__global__ void k_stats_total(const unsigned long long *__restrict__ part, uint32_t n,
+                              parem_result *__restrict__ result) {
+    unsigned long long r = 0, g = 0;
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        r += part[2 * i];
+        g += part[2 * i + 1];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        r += (unsigned long long)__shfl_xor((long long)r, o, 64);
+        g += (unsigned long long)__shfl_xor((long long)g, o, 64);
+    }
+    if (threadIdx.x == 0) {
+        result->spec_runs = r;
+        result->rerun_chunks = g;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// sub-chunk re-walk (learned speculation). A chunk marked for a walk from its
+// whole set R_c is walked by one workgroup as up to 64 sub-chunks at once:
+// sub-chunk k runs from every state of Algorithm 1's set for its own start
+// (the image of the column of the byte before it; R_c for k = 0), and the
+// sub-chunk maps are then chained for every state of R_c, which is the
+// composition of Algorithm 1 applied inside the chunk. The entries written
+// equal those of the whole-set walk (end | count << 16, the class with bit 15
+// when the ends differ, the end from position 0; the sentinel for every
+// entry when the chunk holds a byte outside the alphabet), and the chunk is
+// unmarked, so the whole-set walk launched after this kernel skips it. One
+// chunk's serial walk of L bytes becomes 64 walks of L / 64 bytes; with more
+// than kSplitMax chunks marked in a round the kernel leaves every chunk to
+// the whole-set walk, whose lanes then carry the load. After a chunk, its
+// successor (when not marked already) is checked against the new ends, as the
+// next coverage round would, and walked the same way when uncovered (at most
+// kSplitHops successors, so that a chain of uncovered chunks is not walked
+// serially: the escalation takes what is left): only the workgroup of chunk
+// c ever reaches c + 1 this way, and a marked successor is walked from its
+// whole set anyway, so no chunk is walked twice at once.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kSplitSub = 64;
+constexpr uint32_t kSplitThreads = 1024;
+constexpr uint32_t kSplitHops = 4;  // successors one workgroup walks after a marked chunk
+
+struct SplitArgs {
+    const uint8_t *text;
+    uint64_t n;
+    uint32_t L;
+    uint64_t C;
+    const uint8_t *cls;
+    const uint32_t *loff;
+    const uint32_t *llist;
+    const uint16_t *step;  // [(Q+1) x (A+1)] next | final << 15
+    const uint16_t *inv;   // [(A+2) x (Q+1)] position in each class list
+    uint32_t Q1, A1, sent;
+    uint32_t inv_lds;      // bytes of inv staged in LDS (0: read from L2)
+    uint32_t *map;
+    uint16_t *map_cls;
+    uint16_t *map_lead;
+    uint8_t *redo;
+    uint8_t *done;
+    uint32_t *marked;      // chunks marked so far (flags[0])
+    const uint32_t *rlist;
+    const uint32_t *count;
+};
+
+struct SplitLds {
+    uint32_t step, inv, ctab, cb, sub, kinfo, bytes;
+};
+__host__ __device__ static SplitLds split_lds(uint32_t Q1, uint32_t A1, uint32_t inv_lds, uint32_t L) {
+    SplitLds o;
+    uint32_t off = 0;
+    o.step = off;
+    off += (Q1 * A1 * 2 + 15) & ~15u;
+    o.inv = off;
+    off += (inv_lds + 15) & ~15u;
+    o.ctab = off;
+    off += 256;
+    o.cb = off;
+    off += (L + 15) & ~15u;
+    o.sub = off;
+    off += kSplitSub * 64 * 4;
+    o.kinfo = off;
+    off += (4 * kSplitSub + kSplitSub + 1) * 4;
+    o.bytes = off;
+    return o;
+}
+
+__global__ __launch_bounds__(kSplitThreads) void k_redo_split(SplitArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const uint32_t marked = *a.count;
+    if (marked == 0 || marked > kSplitMax || blockIdx.x >= marked) return;
+    const uint32_t tid = threadIdx.x;
+    const SplitLds o = split_lds(a.Q1, a.A1, a.inv_lds, a.L);
+    uint16_t *T = reinterpret_cast<uint16_t *>(smem + o.step);
+    uint16_t *IV = reinterpret_cast<uint16_t *>(smem + o.inv);
+    uint8_t *CT = smem + o.ctab;
+    uint8_t *CB = smem + o.cb;
+    uint32_t *SUB = reinterpret_cast<uint32_t *>(smem + o.sub);
+    uint32_t *kcls = reinterpret_cast<uint32_t *>(smem + o.kinfo);
+    uint32_t *klo = kcls + kSplitSub, *ksz = klo + kSplitSub, *kfrom = ksz + kSplitSub, *koff = kfrom + kSplitSub;
+    for (uint32_t i = tid; i < a.Q1 * a.A1; i += kSplitThreads) T[i] = a.step[i];
+    for (uint32_t i = tid; i < a.inv_lds / 2; i += kSplitThreads) IV[i] = a.inv[i];
+    if (tid < 256) CT[tid] = a.cls[tid];
+    __syncthreads();
+    __shared__ uint32_t s_next;
+    for (uint32_t it = blockIdx.x; it < marked; it += gridDim.x) {
+      for (uint64_t c = a.rlist[it], hop = 0;; ++c, ++hop) {  // c >= 1: chunk 0 is never marked
+        const uint64_t b = c * (uint64_t)a.L;
+        const uint32_t len = (uint32_t)min((uint64_t)a.L, a.n - b);
+        const uint32_t P = min(kSplitSub, len);
+        // classes of the chunk's bytes
+        const uint8_t *src = a.text + b;
+        if ((reinterpret_cast<uintptr_t>(src) & 15u) == 0) {
+            for (uint32_t i = 16 * tid; i < len; i += 16 * kSplitThreads) {
+                if (i + 16 <= len) {
+                    const uint4 q = *reinterpret_cast<const uint4 *>(src + i);
+                    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                    for (int h = 0; h < 16; ++h) CB[i + h] = CT[(w[h >> 2] >> (8 * (h & 3))) & 0xffu];
+                } else {
+                    for (uint32_t h = i; h < len; ++h) CB[h] = CT[src[h]];
+                }
+            }
+        } else {
+            for (uint32_t i = tid; i < len; i += kSplitThreads) CB[i] = CT[src[i]];
+        }
+        // sub-chunk k covers [k len / P, (k+1) len / P); its set follows the byte before it
+        if (tid < P) {
+            const uint32_t from = tid * len / P;
+            const uint32_t cl = CT[a.text[b + from - 1]];
+            const uint32_t lo = a.loff[cl];
+            kcls[tid] = cl;
+            klo[tid] = lo;
+            ksz[tid] = a.loff[cl + 1] - lo;
+            kfrom[tid] = from;
+        }
+        __syncthreads();
+        if (tid < 64) {
+            // offsets of the sub-chunk walks (inclusive scan over the wave)
+            uint32_t v = tid < P ? ksz[tid] : 0u;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t u = (uint32_t)__shfl_up((int)v, d, 64);
+                if ((int)tid >= d) v += u;
+            }
+            koff[tid + 1] = v;
+            if (tid == 0) koff[0] = 0;
+        }
+        __syncthreads();
+        const uint32_t total = koff[P];
+        for (uint32_t task = tid; task < total; task += kSplitThreads) {
+            uint32_t lo = 0, hi = P;  // koff[lo] <= task < koff[hi]
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (koff[mid] <= task) lo = mid;
+                else hi = mid;
+            }
+            const uint32_t k = lo, j = task - koff[k];
+            const uint32_t to = k + 1 < P ? kfrom[k + 1] : len;
+            uint32_t e = a.llist[klo[k] + j], cnt = 0;
+#pragma unroll 4
+            for (uint32_t i = kfrom[k]; i < to; ++i) {
+                const uint32_t v = T[e * a.A1 + CB[i]];
+                e = v & 0x7fffu;
+                cnt += v >> 15;
+            }
+            // the chain needs the end's position in the next sub-chunk's set
+            // (0xffff: the sentinel, or not in the set); the last keeps the state
+            uint32_t out = e;
+            if (k + 1 < P) {
+                const uint32_t ix = kcls[k + 1] * a.Q1 + e;
+                const uint32_t pos = e == a.sent ? 0xffffu : (a.inv_lds ? IV[ix] : a.inv[ix]);
+                out = pos < ksz[k + 1] ? pos : 0xffffu;
+            }
+            SUB[task] = out | (cnt << 16);
+        }
+        __syncthreads();
+        if (tid < 64) {
+            // chain every state of R_c through the sub-chunk maps
+            const uint32_t sz0 = ksz[0];
+            const bool act = tid < sz0;
+            uint32_t e = 0, cnt = 0;
+            if (act) {
+                uint32_t pos = tid;
+                for (uint32_t k = 0; k < P; ++k) {
+                    const uint32_t v = SUB[koff[k] + pos];
+                    cnt += v >> 16;
+                    pos = v & 0xffffu;
+                    if (k + 1 == P) {
+                        e = pos;
+                    } else if (pos == 0xffffu) {
+                        e = a.sent;
+                        break;
+                    }
+                }
+            }
+            const uint32_t lead = (uint32_t)__shfl((int)e, 0, 64);
+            const bool nonuni = __any(act && e != lead);
+            if (act) a.map[(uint64_t)tid * a.C + c] = e == a.sent ? a.sent : (e | (cnt << 16));
+            // the successor's coverage of the new ends (as chunk_present)
+            bool go = false;
+            if (hop < kSplitHops && c + 1 < a.C && a.done[c + 1] == 0) {
+                const uint32_t ncl = a.map_cls[c + 1] & 0x7fffu;
+                bool miss = false;
+                if (act && e != a.sent) {
+                    const uint32_t ix = ncl * a.Q1 + e;
+                    const uint32_t pos = a.inv_lds ? IV[ix] : a.inv[ix];
+                    miss = pos == 0xffffu || (a.map[(uint64_t)pos * a.C + c + 1] & 0xffffu) == kAbsent16;
+                }
+                go = __any(miss);
+            }
+            if (tid == 0) {
+                a.map_cls[c] = (uint16_t)(kcls[0] | (nonuni ? 0x8000u : 0u));
+                a.map_lead[c] = (uint16_t)lead;
+                a.redo[c] = 0;
+                if (go) {
+                    a.done[c + 1] = 1;
+                    atomicAdd(a.marked, 1u);
+                }
+                s_next = go ? 1u : 0u;
+            }
+        }
+        __syncthreads();
+        if (!s_next) break;
+      }
     }
 }
 
@@ -198,10 +436,6 @@ __global__ void k_learned_total(const unsigned long long *__restrict__ acc, pare
     }
 }
 
-__global__ void k_clear_u8(uint8_t *__restrict__ p, uint64_t n) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0;
-}
 __global__ void k_clear_u32(uint32_t *__restrict__ p, uint32_t n) {
     if (threadIdx.x < n) p[threadIdx.x] = 0;
 }
@@ -495,6 +729,10 @@ parem_status plan_learned(const DeviceDfa &d, const Proposal &pr, uint64_t len, 
     off = align256(off + ch);
     p->off_flags = off;
     off = align256(off + 64);
+    p->off_rlist = off;
+    off = align256(off + kSplitMax * 4);
+    p->off_part = off;
+    off = align256(off + (ch + 255) / 256 * 16);
     p->off_mlp = off;
     off = align256(off + proposal_infer_bytes(pr, ch));
     p->bytes = off;
@@ -531,25 +769,52 @@ parem_status launch_learned(const DeviceDfa &d, const Proposal &pr, const PlainP
     launch_walk<WALK_SELECTED>(d, p, a, stream, aligned);
     if (hipGetLastError() != hipSuccess) return PAREM_EDEVICE;
     // 3. verify coverage, walk uncovered chunks again from their whole set
-    hipLaunchKernelGGL(k_clear_u8, dim3(g), dim3(256), 0, stream, done, (uint64_t)C);
-    hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(64), 0, stream, flags, 8u);
+    //    (flags: 0 chunks marked, 1 escalation, 8 + round: marked in the round)
+    hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(64), 0, stream, flags, 8u + kCoverRounds + 1);
+    unsigned long long *part = reinterpret_cast<unsigned long long *>(ws + p.off_part);
     WalkArgs r = walk_args(d, p, d_text, ws);
     r.redo = redo;
-    for (int it = 0; it <= kCoverRounds; ++it) {
-        const uint32_t escalate = it == kCoverRounds ? 1u : 0u;
+    uint32_t *rlist = reinterpret_cast<uint32_t *>(ws + p.off_rlist);
+    // marked chunks of small-set DFAs are walked in sub-chunks first
+    const bool split = d.d_step && d.max_spec <= 64;
+    SplitArgs sa{};
+    SplitLds sl{};
+    if (split) {
+        sa = SplitArgs{d_text, p.n, p.L, (uint64_t)C, d.d_cls, d.d_loff, d.d_llist, d.d_step, d.d_inv, d.Q + 1,
+                       d.A + 1, d.sent, d.inv_lds, a.map, a.map_cls, a.map_lead, redo, done, flags, rlist, nullptr};
+        sl = split_lds(d.Q + 1, d.A + 1, d.inv_lds, p.L);
+        static std::once_flag lds_once;
+        static hipError_t lds_err = hipSuccess;
+        std::call_once(lds_once, [] {
+            const SplitLds most = split_lds(kSplitTable, 1, 16384, kMaxChunk);
+            lds_err = hipFuncSetAttribute(reinterpret_cast<const void *>(k_redo_split),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)most.bytes);
+        });
+        if (lds_err != hipSuccess) return PAREM_EDEVICE;
+    }
+    // (the sub-chunk walk settles what later coverage rounds would find: one
+    // round before the escalation is enough then)
+    const int rounds = split ? 1 : kCoverRounds;
+    for (int it = 0; it <= rounds; ++it) {
+        const uint32_t escalate = it == rounds ? 1u : 0u;
+        uint32_t *round_count = flags + 8 + it;
         hipLaunchKernelGGL(k_cover, dim3(g), dim3(256), 0, stream, a.map, a.map_cls, a.map_lead, (uint64_t)C, d.d_loff,
-                           d.d_inv, d.Q + 1, d.sent, redo, done, flags, escalate);
-        if (escalate) hipLaunchKernelGGL(k_escalate, dim3(g), dim3(256), 0, stream, (uint64_t)C, redo, done, flags);
+                           d.d_inv, d.Q + 1, d.sent, redo, done, flags, escalate, round_count, rlist,
+                           it == 0 ? 1u : 0u);
+        if (escalate)
+            hipLaunchKernelGGL(k_escalate, dim3(g), dim3(256), 0, stream, (uint64_t)C, redo, done, flags, round_count,
+                               rlist, nsel, a.map_cls, d.d_loff, part);
+        if (split) {
+            sa.count = round_count;
+            hipLaunchKernelGGL(k_redo_split, dim3(512), dim3(kSplitThreads), sl.bytes, stream, sa);
+        }
         launch_walk<WALK_REDO>(d, p, r, stream, aligned);
     }
     if (ev_end && hipEventRecord(ev_end, stream) != hipSuccess) return PAREM_EDEVICE;
     // 4. compose, then the learned statistics
     st = launch_compose(d, p, ws, stream, d_out);
     if (st != PAREM_OK) return st;
-    unsigned long long *acc = reinterpret_cast<unsigned long long *>(flags + 4);
-    hipLaunchKernelGGL(k_learned_stats, dim3(g), dim3(256), 0, stream, nsel, done, a.map_cls, d.d_loff,
-                       (uint64_t)C, acc);  // 256 threads: four waves per partial
-    hipLaunchKernelGGL(k_learned_total, dim3(1), dim3(64), 0, stream, acc, d_out);
+    hipLaunchKernelGGL(k_stats_total, dim3(1), dim3(64), 0, stream, part, g, d_out);
     return hipGetLastError() == hipSuccess ? PAREM_OK : PAREM_EDEVICE;
 }
 

@@ -266,6 +266,17 @@ def test_learned_reruns_equal_misses():
     m.close()
 
 
+@pytest.mark.parametrize("n,L", [(3_000_001, 1024), (1 << 20, 64), (50_017, 64), (200_000, 8192)])
+def test_learned_subchunk_rewalk(n, L):
+    """Chunks walked again from their whole set: up to 2048 marked chunks a
+    round are walked in sub-chunks (64, or single bytes in a tail under 64),
+    more go to the whole-set walk; ragged tails, both ways exact."""
+    dfa, text = W.config2(n=n, copies=100)
+    got = learned_case(f"sub-chunk re-walk n={n} L={L}", dfa, text, random_params(dfa.num_states, 17), 1,
+                       chunk_len=L)
+    assert got.rerun_chunks > 0
+
+
 def test_learned_adversarial_proposal():
     """A proposal that always prefers the highest state id (biases only) on a
     non-synchronising automaton: coverage fails along the whole text and the
