@@ -103,7 +103,7 @@ struct Proposal {
     uint32_t cap_batch = 0;
     size_t t_pos = 0, t_lab = 0, t_win = 0, t_cls = 0, t_X = 0, t_pre1 = 0, t_H1 = 0, t_pre2 = 0, t_H2 = 0,
            t_Z = 0, t_dZ32 = 0, t_dZ16 = 0, t_dA2_32 = 0, t_dA2_16 = 0, t_dA1_32 = 0, t_dA1_16 = 0, t_dX = 0,
-           t_loss = 0;
+           t_loss = 0, t_part = 0;
 };
 
 void proposal_layout(Proposal &p);

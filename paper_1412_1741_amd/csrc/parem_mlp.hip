@@ -78,7 +78,9 @@ __device__ __forceinline__ float gelu_grad(float u) {
 // A is stored [M][K] (TA = false) or [K][M] (TA = true); B is stored [N][K]
 // (TB = true) or [K][N] (TB = false). 64 x 64 output tile per workgroup of
 // four waves (each a 32 x 32 MFMA block), K consumed 32 at a time through
-// LDS tiles kept k-contiguous for both operands.
+// LDS tiles kept k-contiguous for both operands. With split > 0 (EPI_F32
+// only), workgroup z takes k in [z split, (z + 1) split) and writes its
+// partial sums at out32 + z M ldc; k_splitk_sum adds them in order.
 // ---------------------------------------------------------------------------
 
 enum Epi : int {
@@ -98,7 +100,7 @@ __global__ __launch_bounds__(kGemmT) void k_gemm(const uint16_t *__restrict__ A,
                                                  const uint16_t *__restrict__ B, int ldb, int M, int N, int K,
                                                  const float *__restrict__ bias, const float *__restrict__ aux,
                                                  float *__restrict__ out32, uint16_t *__restrict__ out16,
-                                                 int ldc) {
+                                                 int ldc, int split) {
     __shared__ __align__(16) uint16_t As[64][kLdsK];
     __shared__ __align__(16) uint16_t Bs[64][kLdsK];
     const int tid = threadIdx.x;
@@ -108,8 +110,11 @@ __global__ __launch_bounds__(kGemmT) void k_gemm(const uint16_t *__restrict__ A,
     f32x16 acc;
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+    const int kb = split ? (int)blockIdx.z * split : 0;
+    const int ke = split ? min(K, kb + split) : K;
+    if (split) out32 += (size_t)blockIdx.z * M * ldc;
 
-    for (int k0 = 0; k0 < K; k0 += kKT) {
+    for (int k0 = kb; k0 < ke; k0 += kKT) {
         // each thread stages 8 elements of each operand
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -119,14 +124,14 @@ __global__ __launch_bounds__(kGemmT) void k_gemm(const uint16_t *__restrict__ A,
             else { r = e >> 5; kk = e & 31; }      // consecutive threads walk k
             const int gm = m0 + r, gk = k0 + kk;
             uint16_t v = 0;
-            if (gm < M && gk < K) v = TA ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk];
+            if (gm < M && gk < ke) v = TA ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk];
             As[r][kk] = v;
             int rn, kn;
             if (TB) { rn = e >> 5; kn = e & 31; }  // B stored [N][K]: walk k
             else { rn = e & 63; kn = e >> 6; }     // B stored [K][N]: walk n
             const int gn = n0 + rn, gk2 = k0 + kn;
             uint16_t w = 0;
-            if (gn < N && gk2 < K) w = TB ? B[(size_t)gn * ldb + gk2] : B[(size_t)gk2 * ldb + gn];
+            if (gn < N && gk2 < ke) w = TB ? B[(size_t)gn * ldb + gk2] : B[(size_t)gk2 * ldb + gn];
             Bs[rn][kn] = w;
         }
         __syncthreads();
@@ -269,9 +274,28 @@ __global__ __launch_bounds__(kGemmT) void k_gemm_nt(const uint16_t *__restrict__
     }
 }
 
+// k-splits of a weight-gradient GEMM (K = batch rows): enough workgroups to
+// fill the chip, at least 256 rows of K each
+static int splitk_of(int M, int N, int K) {
+    const int tiles = ((N + 63) / 64) * ((M + 63) / 64);
+    int s = 1;
+    while (s < 16 && tiles * s < 256 && K / (2 * s) >= 256) s *= 2;
+    return s;
+}
+
+__global__ void k_splitk_sum(const float *__restrict__ part, int S, int M, int N, int ldc, float *__restrict__ out) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)M * N) return;
+    const size_t o = (i / N) * ldc + i % N;
+    float v = 0.0f;
+    for (int z = 0; z < S; ++z) v += part[(size_t)z * M * ldc + o];
+    out[o] = v;
+}
+
 template <bool TA, bool TB, int EPI>
 static void gemm(hipStream_t s, const uint16_t *A, int lda, const uint16_t *B, int ldb, int M, int N, int K,
-                 const float *bias, const float *aux, float *out32, uint16_t *out16, int ldc) {
+                 const float *bias, const float *aux, float *out32, uint16_t *out16, int ldc,
+                 float *part = nullptr) {
     if (!TA && TB && K % kKT == 0 && lda % 8 == 0 && ldb % 8 == 0 &&
         (reinterpret_cast<uintptr_t>(A) & 15u) == 0 && (reinterpret_cast<uintptr_t>(B) & 15u) == 0) {
         dim3 grid((N + 127) / 128, (M + 127) / 128);
@@ -279,9 +303,22 @@ static void gemm(hipStream_t s, const uint16_t *A, int lda, const uint16_t *B, i
                            out16, ldc);
         return;
     }
+    const int S = (EPI == EPI_F32 && part) ? splitk_of(M, N, K) : 1;
+    if (S > 1) {
+        // split-K: partial sums per k range, then their sum in a fixed order
+        const int split = (K / S + kKT - 1) / kKT * kKT;
+        const int nz = (K + split - 1) / split;
+        dim3 grid((N + 63) / 64, (M + 63) / 64, nz);
+        hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(kGemmT), 0, s, A, lda, B, ldb, M, N, K, bias, aux, part,
+                           out16, ldc, split);
+        const size_t n = (size_t)M * N;
+        hipLaunchKernelGGL(k_splitk_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, nz, M, N, ldc,
+                           out32);
+        return;
+    }
     dim3 grid((N + 63) / 64, (M + 63) / 64);
     hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(kGemmT), 0, s, A, lda, B, ldb, M, N, K, bias, aux, out32,
-                       out16, ldc);
+                       out16, ldc, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -782,6 +819,18 @@ static parem_status ensure_train(Proposal &p, uint32_t B) {
     p.t_dA1_16 = take((size_t)B * kMlpHid * 2);
     p.t_dX = take((size_t)B * kMlpIn * 4);
     p.t_loss = take(256);
+    // split-K partials of the three weight-gradient GEMMs (K = B), laid out
+    // as the dispatcher writes them
+    size_t part = 0;
+    const int shapes[3][2] = {{(int)S, (int)kMlpHid}, {(int)kMlpHid, (int)kMlpHid}, {(int)kMlpHid, (int)kMlpIn}};
+    for (const auto &mn : shapes) {
+        const int sk = splitk_of(mn[0], mn[1], (int)B);
+        if (sk <= 1) continue;
+        const size_t split = ((size_t)B / sk + kKT - 1) / kKT * kKT;
+        const size_t nz = (B + split - 1) / split;
+        part = std::max(part, nz * mn[0] * mn[1] * 4);
+    }
+    p.t_part = take(part ? part : 4);
     if (hipMalloc(&p.t_buf, off) != hipSuccess) {
         p.t_buf = nullptr;
         p.cap_batch = 0;
@@ -845,8 +894,9 @@ parem_status proposal_train_step(Proposal &p, const uint8_t *d_text, uint64_t le
     hipLaunchKernelGGL(k_zero, dim3((unsigned)((256 * kMlpEmb + 255) / 256)), dim3(256), 0, s, g + p.o_emb,
                        (size_t)256 * kMlpEmb);
     // head: dW3 = dZ^T H2, db3 = colsum dZ, dA2 = (dZ W3) * gelu'(pre2)
+    float *part = at<float>(T, p.t_part);
     gemm<true, false, EPI_F32>(s, dZ16, (int)S, H2, kMlpHid, (int)S, kMlpHid, (int)B, nullptr, nullptr, g + p.o_W3,
-                               nullptr, kMlpHid);
+                               nullptr, kMlpHid, part);
     hipLaunchKernelGGL(k_colsum, dim3(S), dim3(256), 0, s, dZ32, B, S, g + p.o_b3);
     float *dA2_32 = at<float>(T, p.t_dA2_32), *dA1_32 = at<float>(T, p.t_dA1_32);
     uint16_t *dA2_16 = at<uint16_t>(T, p.t_dA2_16), *dA1_16 = at<uint16_t>(T, p.t_dA1_16);
@@ -854,13 +904,13 @@ parem_status proposal_train_step(Proposal &p, const uint8_t *d_text, uint64_t le
                                      dA2_32, dA2_16, kMlpHid);
     // layer 2
     gemm<true, false, EPI_F32>(s, dA2_16, kMlpHid, H1, kMlpHid, kMlpHid, kMlpHid, (int)B, nullptr, nullptr,
-                               g + p.o_W2, nullptr, kMlpHid);
+                               g + p.o_W2, nullptr, kMlpHid, part);
     hipLaunchKernelGGL(k_colsum, dim3(kMlpHid), dim3(256), 0, s, dA2_32, B, kMlpHid, g + p.o_b2);
     gemm<false, false, EPI_GELU_BWD>(s, dA2_16, kMlpHid, w16 + p.o_W2, kMlpHid, (int)B, kMlpHid, kMlpHid, nullptr,
                                      pre1, dA1_32, dA1_16, kMlpHid);
     // layer 1
     gemm<true, false, EPI_F32>(s, dA1_16, kMlpHid, X, kMlpIn, kMlpHid, kMlpIn, (int)B, nullptr, nullptr,
-                               g + p.o_W1, nullptr, kMlpIn);
+                               g + p.o_W1, nullptr, kMlpIn, part);
     hipLaunchKernelGGL(k_colsum, dim3(kMlpHid), dim3(256), 0, s, dA1_32, B, kMlpHid, g + p.o_b1);
     float *dX = at<float>(T, p.t_dX);
     gemm<false, false, EPI_F32>(s, dA1_16, kMlpHid, w16 + p.o_W1, kMlpIn, (int)B, kMlpIn, kMlpHid, nullptr, nullptr,
