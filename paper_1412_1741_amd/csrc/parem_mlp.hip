@@ -364,36 +364,44 @@ __global__ void k_embed(const uint16_t *__restrict__ win, uint32_t B, const uint
 // one wave per row: masked softmax cross-entropy; writes dZ = (p - onehot) / B
 // (fp32 and bf16) and accumulates the mean loss. A state is allowed when it
 // belongs to the speculated list of the row's class (inverse index hit).
-__global__ void k_softmax_ce(const float *__restrict__ Z, uint32_t B, uint32_t S, const uint32_t *__restrict__ label,
-                             const uint16_t *__restrict__ wcls, const uint16_t *__restrict__ inv, uint32_t Q1,
-                             float *__restrict__ dZ32, uint16_t *__restrict__ dZ16, float *__restrict__ loss) {
-    const uint32_t row = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-    const uint32_t lane = threadIdx.x & 63;
-    if (row >= B) return;
-    const float *z = Z + (size_t)row * S;
-    const uint16_t *iv = inv + (size_t)wcls[row] * Q1;
-    float mx = -INFINITY;
-    for (uint32_t s = lane; s < S; s += 64)
-        if (iv[s] != 0xffffu) mx = fmaxf(mx, z[s]);
-    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
-    float sum = 0.0f;
-    for (uint32_t s = lane; s < S; s += 64)
-        if (iv[s] != 0xffffu) sum += expf(z[s] - mx);
-    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
-    const uint32_t lab = label[row];
+__global__ __launch_bounds__(256) void k_softmax_ce(const float *__restrict__ Z, uint32_t B, uint32_t S,
+                                                    const uint32_t *__restrict__ label,
+                                                    const uint16_t *__restrict__ wcls,
+                                                    const uint16_t *__restrict__ inv, uint32_t Q1,
+                                                    float *__restrict__ dZ32, uint16_t *__restrict__ dZ16,
+                                                    float *__restrict__ loss) {
+    // one wave per row, rows strided over the grid; the loss is summed per
+    // workgroup and added once (same-address atomics serialise)
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const float invB = 1.0f / (float)B;
-    for (uint32_t s = lane; s < S; s += 64) {
-        float g = 0.0f;
-        if (iv[s] != 0xffffu) g = expf(z[s] - mx) / sum;
-        if (s == lab) g -= 1.0f;
-        g *= invB;
-        dZ32[(size_t)row * S + s] = g;
-        dZ16[(size_t)row * S + s] = f2bf(g);
+    float part = 0.0f;
+    for (uint32_t row = blockIdx.x * 4 + wave; row < B; row += gridDim.x * 4) {
+        const float *z = Z + (size_t)row * S;
+        const uint16_t *iv = inv + (size_t)wcls[row] * Q1;
+        float mx = -INFINITY;
+        for (uint32_t s = lane; s < S; s += 64)
+            if (iv[s] != 0xffffu) mx = fmaxf(mx, z[s]);
+        for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+        float sum = 0.0f;
+        for (uint32_t s = lane; s < S; s += 64)
+            if (iv[s] != 0xffffu) sum += expf(z[s] - mx);
+        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+        const uint32_t lab = label[row];
+        for (uint32_t s = lane; s < S; s += 64) {
+            float g = 0.0f;
+            if (iv[s] != 0xffffu) g = expf(z[s] - mx) / sum;
+            if (s == lab) g -= 1.0f;
+            g *= invB;
+            dZ32[(size_t)row * S + s] = g;
+            dZ16[(size_t)row * S + s] = f2bf(g);
+        }
+        part += (logf(sum) + mx - z[lab]) * invB;
     }
-    if (lane == 0) atomicAdd(loss, (logf(sum) + mx - z[lab]) * invB);
+    __shared__ float red[4];
+    if (lane == 0) red[wave] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(loss, red[0] + red[1] + red[2] + red[3]);
 }
-
-// column sums of an fp32 [B][N] matrix into out[N]
 __global__ void k_colsum(const float *__restrict__ A, uint32_t B, uint32_t N, float *__restrict__ out) {
     const uint32_t n = blockIdx.x;
     float s = 0.0f;
@@ -415,8 +423,9 @@ __global__ void k_zero(float *__restrict__ p, size_t n) {
 
 // embedding gradient: scatter-add the input gradient rows by byte value.
 // Each workgroup accumulates its rows into an LDS copy of the table, then
-// adds the non-zero entries to the global gradient (few, uncontended atomics).
-constexpr uint32_t kEmbRowsPerBlock = 64;
+// adds the non-zero entries to the global gradient. 16 rows per workgroup:
+// the loop is latency-bound, so the batch is spread over many workgroups.
+constexpr uint32_t kEmbRowsPerBlock = 16;
 
 __global__ __launch_bounds__(256) void k_embed_bwd(const uint16_t *__restrict__ win, uint32_t B,
                                                    const float *__restrict__ dX, float *__restrict__ demb) {
@@ -886,8 +895,8 @@ parem_status proposal_train_step(Proposal &p, const uint8_t *d_text, uint64_t le
     forward_rows(p, s, win, B, X, pre1, H1, pre2, H2, Z);
     float *dZ32 = at<float>(T, p.t_dZ32);
     uint16_t *dZ16 = at<uint16_t>(T, p.t_dZ16);
-    hipLaunchKernelGGL(k_softmax_ce, dim3((B + 3) / 4), dim3(256), 0, s, Z, B, S, d_labels, wcls, d.d_inv, d.Q + 1,
-                       dZ32, dZ16, loss);
+    hipLaunchKernelGGL(k_softmax_ce, dim3(std::min<uint32_t>((B + 3) / 4, 256)), dim3(256), 0, s, Z, B, S, d_labels,
+                       wcls, d.d_inv, d.Q + 1, dZ32, dZ16, loss);
     // backward
     float *g = p.d_grad;
     const uint16_t *w16 = p.d_params16;
