@@ -91,7 +91,10 @@ def bench_sparse(args):
     ref = None
     agree = True
     for name, kw in (("hot_rows", {"layout": P.LAYOUT_HOT_LDS}), ("byte_l2", {"layout": P.LAYOUT_BYTE_GLOBAL}),
-                     ("hot_rows_lookback64", {"layout": P.LAYOUT_HOT_LDS, "lookback": 64})):
+                     ("hot_rows_lookback64", {"layout": P.LAYOUT_HOT_LDS, "lookback": 64}),
+                     ("sparse_rows", {"layout": P.LAYOUT_SPARSE_LDS}),
+                     ("sparse_rows_g4", {"layout": P.LAYOUT_SPARSE_LDS, "group": 4}),
+                     ("sparse_rows_g16", {"layout": P.LAYOUT_SPARSE_LDS, "group": 16})):
         m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, **kw)
         res_t = torch.empty(P.RESULT_BYTES, dtype=torch.uint8, device="cuda")
         m.match_async(dev, res_t)

@@ -54,8 +54,14 @@ enum {
     PAREM_LAYOUT_KGRAM_LDS = 3,  /* k-symbol stride table in LDS (small alphabets) */
     PAREM_LAYOUT_HOT_LDS = 4,    /* rows of the most visited states in LDS, the
                                     others read through L2 (up to 16383 states) */
-    PAREM_LAYOUT_CLASS_LDS = 5   /* (Q+1) x (A+1) table indexed by column, plus the
+    PAREM_LAYOUT_CLASS_LDS = 5,  /* (Q+1) x (A+1) table indexed by column, plus the
                                     byte-to-column map, in LDS (up to 48 KiB) */
+    PAREM_LAYOUT_SPARSE_LDS = 6  /* sparse rows in LDS: per state a default next
+                                    state and at most 4 (column, next) exceptions,
+                                    16 bytes a row (up to 5103 states). Chosen
+                                    only when asked for; a table with a row of
+                                    more exceptions, or too many states, falls
+                                    back as AUTO would. Batches do not take it. */
 };
 
 typedef struct {
@@ -266,6 +272,8 @@ parem_status parem_match_learned_async(parem_handle h, parem_proposal p, uint32_
  *                      Allocates the plan's device memory (workspace for
  *                      every pair). Pairs with lens[i] == 0 are allowed.
  *                      The handles and proposals must outlive the plan.
+ *                      PAREM_EUNSUPPORTED for a handle compiled with the
+ *                      sparse-row layout (no batch kernel walks it).
  * parem_batch_run      d_texts: host array of n device pointers, each
  *                      16-byte aligned (PAREM_EINVAL otherwise), holding
  *                      lens[i] bytes. d_out: device array of n results.

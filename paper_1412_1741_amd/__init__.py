@@ -33,6 +33,7 @@ LAYOUT_BYTE_GLOBAL = 2
 LAYOUT_KGRAM_LDS = 3
 LAYOUT_HOT_LDS = 4
 LAYOUT_CLASS_LDS = 5
+LAYOUT_SPARSE_LDS = 6
 
 RESULT_BYTES = 40
 INVALID_STATE = 0xFFFFFFFF

@@ -33,6 +33,9 @@ SOURCES = [
     "parem_walk_class_all.hip",
     "parem_walk_class_sel.hip",
     "parem_walk_class_redo.hip",
+    "parem_walk_sparse_all.hip",
+    "parem_walk_sparse_sel.hip",
+    "parem_walk_sparse_redo.hip",
     "parem_mlp.hip",
     "parem_batch.hip",
     "parem_batch_t64.hip",

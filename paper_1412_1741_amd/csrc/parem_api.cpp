@@ -75,6 +75,59 @@ std::vector<E> byte_table(const DeviceDfa &d, const std::vector<uint32_t> &t, ui
     return out;
 }
 
+// Sparse rows: LDS image [256 B byte -> column][(Q+1) rows of 16 B]. Row q:
+// word 0 the columns of four exceptions (one byte each), words 1-2 their
+// entries, word 3 the default entry in its low half; an entry is the next
+// state | final << 15. Unused exception slots repeat a column with its own
+// entry, so a column not among the exceptions always has the default. The
+// default is the row's most frequent next state. False when some row has
+// more than kSparseExc other columns or the image exceeds kSparseLdsMax.
+bool sparse_rows(const DeviceDfa &d, const std::vector<uint32_t> &t, std::vector<uint8_t> &image) {
+    // the invalid column A is reachable only when some byte is outside the alphabet
+    bool invalid_used = false;
+    for (uint32_t x = 0; x < 256; ++x) invalid_used |= d.cls[x] >= d.A;
+    const uint32_t ncol = d.A + (invalid_used ? 1u : 0u);
+    if (ncol > 256 || d.Q + 1 > 0x7fffu) return false;
+    const size_t bytes = 256 + (size_t)(d.Q + 1) * 16;
+    if (bytes > parem::kSparseLdsMax) return false;
+    image.assign(bytes, 0);
+    for (uint32_t x = 0; x < 256; ++x) image[x] = (uint8_t)d.cls[x];
+    std::vector<uint32_t> next(ncol), count(d.Q + 1, 0);
+    for (uint32_t q = 0; q <= d.Q; ++q) {
+        for (uint32_t a = 0; a < ncol; ++a) next[a] = (q < d.Q && a < d.A) ? t[(size_t)q * d.A + a] : d.sent;
+        uint32_t dflt = next[0], best = 0;
+        for (uint32_t a = 0; a < ncol; ++a)
+            if (++count[next[a]] > best) {
+                best = count[next[a]];
+                dflt = next[a];
+            }
+        for (uint32_t a = 0; a < ncol; ++a) count[next[a]] = 0;
+        auto entry = [&](uint32_t nx) { return (uint16_t)(nx | ((uint32_t)d.final_flag[nx] << 15)); };
+        uint8_t col[parem::kSparseExc];
+        uint16_t ent[parem::kSparseExc];
+        uint32_t ne = 0;
+        for (uint32_t a = 0; a < ncol; ++a) {
+            if (next[a] == dflt) continue;
+            if (ne == parem::kSparseExc) return false;
+            col[ne] = (uint8_t)a;
+            ent[ne] = entry(next[a]);
+            ++ne;
+        }
+        for (uint32_t k = ne; k < parem::kSparseExc; ++k) {
+            col[k] = 0;
+            ent[k] = entry(next[0]);
+        }
+        uint8_t *row = image.data() + 256 + (size_t)q * 16;
+        for (uint32_t k = 0; k < parem::kSparseExc; ++k) {
+            row[k] = col[k];
+            std::memcpy(row + 4 + 2 * k, &ent[k], 2);
+        }
+        const uint16_t de = entry(dflt);
+        std::memcpy(row + 12, &de, 2);
+    }
+    return true;
+}
+
 // Hot-row layout. The hot states are the kHotMax states of largest weight
 // under the stationary behaviour of the walk on uniformly random symbols
 // (power iteration, averaged over the later iterates so that periodic chains
@@ -242,7 +295,7 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
         if (o.lookback > parem::kLookMax) return PAREM_EINVAL;
         if (o.chunk_len % 64 || o.chunk_len > parem::kMaxChunk) return PAREM_EINVAL;
         if (o.group && o.group != 2 && o.group != 4 && o.group != 8 && o.group != 16) return PAREM_EINVAL;
-        if (o.layout > PAREM_LAYOUT_CLASS_LDS) return PAREM_EINVAL;
+        if (o.layout > PAREM_LAYOUT_SPARSE_LDS) return PAREM_EINVAL;
         if (o.tile && o.tile != 64 && o.tile != 128) return PAREM_EINVAL;
         if (o.kgram) return PAREM_EINVAL;
         if (o.no_merge > 1) return PAREM_EINVAL;
@@ -329,6 +382,12 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
     if (layout == PAREM_LAYOUT_BYTE_LDS && !lds_ok) layout = class_ok ? PAREM_LAYOUT_CLASS_LDS : big;
     if (layout == PAREM_LAYOUT_CLASS_LDS && !class_ok) layout = big;
     if (layout == PAREM_LAYOUT_HOT_LDS && !hot_ok) layout = PAREM_LAYOUT_BYTE_GLOBAL;
+    // sparse rows: only when asked for and every row has a default and at
+    // most kSparseExc other columns (the invalid column counts unless every
+    // byte is in the alphabet)
+    std::vector<uint8_t> sparse_image;
+    if (layout == PAREM_LAYOUT_SPARSE_LDS && !sparse_rows(d, t, sparse_image))
+        layout = class_ok ? PAREM_LAYOUT_CLASS_LDS : big;
     d.layout = layout;
     if (layout != PAREM_LAYOUT_KGRAM_LDS) {
         d.kgram = 0;
@@ -373,6 +432,14 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
             d.lds_bytes = d.table_bytes;
             uint8_t *p = nullptr;
             st = upload(image, &p);
+            d.d_table = p;
+        } else if (layout == PAREM_LAYOUT_SPARSE_LDS) {
+            d.entry_bytes = 2;
+            d.row_stride = 8;
+            d.table_bytes = (uint32_t)sparse_image.size();
+            d.lds_bytes = d.table_bytes;
+            uint8_t *p = nullptr;
+            st = upload(sparse_image, &p);
             d.d_table = p;
         } else if (layout == PAREM_LAYOUT_HOT_LDS) {
             std::vector<uint8_t> image;

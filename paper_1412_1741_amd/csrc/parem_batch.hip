@@ -558,6 +558,9 @@ parem_status parem_batch_create(const parem_handle *dfas, const uint64_t *lens, 
                                 parem_batch *out) {
     if (!out || (n && (!dfas || !lens))) return PAREM_EINVAL;
     *out = nullptr;
+    // the batch kernels have no sparse-row variant
+    for (uint32_t i = 0; i < n; ++i)
+        if (dfas[i] && dfas[i]->dev.layout == PAREM_LAYOUT_SPARSE_LDS) return PAREM_EUNSUPPORTED;
     parem_batch_s *b = new (std::nothrow) parem_batch_s;
     if (!b) return PAREM_ENOMEM;
     parem_status st = parem::batch_plan(dfas, lens, n, opts, props, m, b);

@@ -50,6 +50,7 @@ struct ByteStep {
     // byte-at-a-time tables serve large speculated sets: many short passes,
     // which share one load of the chunk's first 64 bytes
     static constexpr bool kPrefixPasses = true;
+    static constexpr bool kStage = true;   // text staged through LDS when aligned
     static constexpr uint32_t kAcc = sizeof(E) * 8 - 1;
     static constexpr uint32_t kMask = (1u << kAcc) - 1u;
     const E *__restrict__ T;
@@ -87,6 +88,7 @@ struct ByteStep {
 struct ClassStep {
     static constexpr bool kRedo = false;
     static constexpr bool kPrefixPasses = true;
+    static constexpr bool kStage = true;   // text staged through LDS when aligned
     const uint8_t *__restrict__ col;   // LDS: [256]
     const uint16_t *__restrict__ T;    // LDS: (Q+1) x (A+1)
     uint32_t A1;                       // A + 1
@@ -97,6 +99,50 @@ struct ClassStep {
     __device__ __forceinline__ void one(uint32_t &s, uint32_t &c, uint32_t cl) const {
         const uint32_t v = T[s * A1 + cl];
         c += v >> 15;
+        s = v & 0x7fffu;
+    }
+    template <int G>
+    __device__ __forceinline__ void dword(uint32_t d, uint32_t (&R)[G], uint32_t (&S)[G], uint32_t (&c)[G], int nw,
+                                          uint32_t &bad) const {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t cl = col[(d >> (8 * k)) & 0xffu];
+#pragma unroll
+            for (int j = 0; j < G; ++j)
+                if (j < nw) one(R[j], c[j], cl);
+        }
+    }
+    template <int G>
+    __device__ __forceinline__ void flush(uint32_t (&S)[G], uint32_t (&c)[G], int nw) const {}
+    __device__ __forceinline__ void byte(uint32_t x, uint32_t &R, uint32_t &c, uint32_t &bad) const {
+        one(R, c, col[x]);
+    }
+};
+
+// Sparse rows: per state a default entry and four (column, entry)
+// exceptions in 16 bytes of LDS (entry = next | final << 15; unused slots
+// repeat a column with its own entry). A step is one 16-byte LDS read and
+// four column compares. The table leaves room for two workgroups per CU only
+// without the text staging area, so lanes load their chunks 16 bytes at a
+// time themselves (the lines stay in L2 between a lane's loads).
+struct SparseStep {
+    static constexpr bool kRedo = false;
+    static constexpr bool kPrefixPasses = true;
+    static constexpr bool kStage = false;
+    const uint8_t *__restrict__ col;  // LDS: [256]
+    const uint4 *__restrict__ rows;   // LDS: (Q+1) rows
+
+    __device__ __forceinline__ uint32_t init(uint32_t s) const { return s; }
+    __device__ __forceinline__ uint32_t id(uint32_t r) const { return r; }
+    __device__ __forceinline__ bool same(uint32_t a, uint32_t b) const { return a == b; }
+    __device__ __forceinline__ void one(uint32_t &s, uint32_t &c, uint32_t cl) const {
+        const uint4 r = rows[s];
+        uint32_t v = r.w;
+        v = (r.x & 0xffu) == cl ? r.y : v;
+        v = ((r.x >> 8) & 0xffu) == cl ? (r.y >> 16) : v;
+        v = ((r.x >> 16) & 0xffu) == cl ? r.z : v;
+        v = (r.x >> 24) == cl ? (r.z >> 16) : v;
+        c += (v >> 15) & 1u;
         s = v & 0x7fffu;
     }
     template <int G>
@@ -128,6 +174,7 @@ struct ClassStep {
 struct HotStep {
     static constexpr bool kRedo = true;
     static constexpr bool kPrefixPasses = true;
+    static constexpr bool kStage = true;   // text staged through LDS when aligned
     const uint16_t *__restrict__ hot;   // LDS: H + 1 rows of kHotRow entries
     const uint16_t *__restrict__ ids;   // LDS: state id of each hot slot
     const uint16_t *__restrict__ full;  // global: (Q+1) x 256 entries
@@ -196,6 +243,7 @@ template <int B>
 struct KgStep {
     static constexpr bool kRedo = false;
     static constexpr bool kPrefixPasses = false;  // small alphabets: few passes
+    static constexpr bool kStage = true;
     static constexpr uint32_t K = (B == 3) ? 2 : 4;   // symbols per lookup
     static constexpr uint32_t RS = K * B + 1;         // row bytes = 1 << RS
     static constexpr uint32_t LOW = (1u << RS) - 1u;  // count field
@@ -567,7 +615,7 @@ __device__ __forceinline__ void walk_chunk(const ST &st, const WalkArgs &a, uint
 
     // tiles every chunk of this wave holds in full
     uint32_t ntiles = 0;
-    if constexpr (ALIGNED && MODE != WALK_REDO) {
+    if constexpr (ALIGNED && MODE != WALK_REDO && ST::kStage) {
         uint32_t m = len;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) m = min(m, (uint32_t)__shfl_xor((int)m, o, 64));
@@ -1209,6 +1257,12 @@ __device__ __forceinline__ void compose_segs_seg(uint8_t *smem, const SegOut &in
 // its own translation unit per (layout, mode)
 template <int LAYOUT, int MODE>
 void launch_walk_family(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, hipStream_t stream, bool aligned);
+extern template void launch_walk_family<PAREM_LAYOUT_SPARSE_LDS, WALK_ALL>(const DeviceDfa &, const PlainPlan &,
+                                                     const WalkArgs &, hipStream_t, bool);
+extern template void launch_walk_family<PAREM_LAYOUT_SPARSE_LDS, WALK_SELECTED>(const DeviceDfa &, const PlainPlan &,
+                                                     const WalkArgs &, hipStream_t, bool);
+extern template void launch_walk_family<PAREM_LAYOUT_SPARSE_LDS, WALK_REDO>(const DeviceDfa &, const PlainPlan &,
+                                                     const WalkArgs &, hipStream_t, bool);
 extern template void launch_walk_family<PAREM_LAYOUT_CLASS_LDS, WALK_ALL>(const DeviceDfa &, const PlainPlan &,
                                                      const WalkArgs &, hipStream_t, bool);
 extern template void launch_walk_family<PAREM_LAYOUT_CLASS_LDS, WALK_SELECTED>(const DeviceDfa &, const PlainPlan &,

@@ -589,6 +589,7 @@ static void launch_walk(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &
         case PAREM_LAYOUT_BYTE_LDS: launch_walk_family<PAREM_LAYOUT_BYTE_LDS, MODE>(d, p, a, stream, aligned); break;
         case PAREM_LAYOUT_HOT_LDS: launch_walk_family<PAREM_LAYOUT_HOT_LDS, MODE>(d, p, a, stream, aligned); break;
         case PAREM_LAYOUT_CLASS_LDS: launch_walk_family<PAREM_LAYOUT_CLASS_LDS, MODE>(d, p, a, stream, aligned); break;
+        case PAREM_LAYOUT_SPARSE_LDS: launch_walk_family<PAREM_LAYOUT_SPARSE_LDS, MODE>(d, p, a, stream, aligned); break;
         default: launch_walk_family<PAREM_LAYOUT_BYTE_GLOBAL, MODE>(d, p, a, stream, aligned); break;
     }
 }

@@ -60,6 +60,17 @@ __global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_walk_class(W
     walk_chunk<G, ClassStep, ALIGNED, TILE, MODE>(st, a, smem + table_bytes, (uint64_t)blockIdx.x * kWalkThreads);
 }
 
+// the table limits a CU to two workgroups: registers for two
+template <int G, bool ALIGNED, int MODE>
+__global__ __launch_bounds__(kWalkThreads, 2) void k_walk_sparse(WalkArgs a,
+                                                                                const uint8_t *__restrict__ g_table,
+                                                                                uint32_t table_bytes) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    stage_table(reinterpret_cast<uint4 *>(smem), reinterpret_cast<const uint4 *>(g_table), table_bytes / 16u);
+    SparseStep st{smem, reinterpret_cast<const uint4 *>(smem + 256)};
+    walk_chunk<G, SparseStep, ALIGNED, 64, MODE>(st, a, nullptr, (uint64_t)blockIdx.x * kWalkThreads);
+}
+
 template <int G, int B, bool ALIGNED, uint32_t TILE, int MODE>
 __global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_walk_kgram(WalkArgs a,
                                                                                const uint8_t *__restrict__ g_table,
@@ -118,6 +129,19 @@ inline void launch_walk_class(const DeviceDfa &d, const PlainPlan &p, const Walk
 #undef PAREM_CLS
 }
 
+// no text staging: the LDS holds the table alone
+template <bool ALIGNED, int MODE>
+inline void launch_walk_sparse(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, hipStream_t stream) {
+    const uint32_t grid = (uint32_t)((p.chunks + kWalkThreads - 1) / kWalkThreads);
+    const size_t lds = d.table_bytes;
+    const uint8_t *tab = reinterpret_cast<const uint8_t *>(d.d_table);
+#define PAREM_SPR(GG)                                                                                          \
+    hipLaunchKernelGGL((k_walk_sparse<GG, ALIGNED, MODE>), dim3(grid), dim3(kWalkThreads), lds, stream, a, tab, \
+                       d.table_bytes)
+    PAREM_GROUP_SWITCH(PAREM_SPR)
+#undef PAREM_SPR
+}
+
 template <int LAYOUT, bool ALIGNED, uint32_t TILE, int MODE>
 inline void launch_family_t(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, hipStream_t stream) {
     if constexpr (LAYOUT == PAREM_LAYOUT_KGRAM_LDS) {
@@ -132,6 +156,8 @@ inline void launch_family_t(const DeviceDfa &d, const PlainPlan &p, const WalkAr
         launch_walk_hot<ALIGNED, TILE, MODE>(d, p, a, stream);
     } else if constexpr (LAYOUT == PAREM_LAYOUT_CLASS_LDS) {
         launch_walk_class<ALIGNED, TILE, MODE>(d, p, a, stream);
+    } else if constexpr (LAYOUT == PAREM_LAYOUT_SPARSE_LDS) {
+        launch_walk_sparse<ALIGNED, MODE>(d, p, a, stream);
     } else {
         launch_walk_byte<uint16_t, 256, false, ALIGNED, TILE, MODE>(d, p, a, stream);
     }
@@ -141,6 +167,12 @@ inline void launch_family_t(const DeviceDfa &d, const PlainPlan &p, const WalkAr
 template <int LAYOUT, int MODE>
 void launch_walk_family(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, hipStream_t stream,
                         bool aligned) {
+    if constexpr (LAYOUT == PAREM_LAYOUT_SPARSE_LDS) {
+        // no staged tiles: the tile size does not matter
+        if (aligned) launch_family_t<LAYOUT, true, 64, MODE>(d, p, a, stream);
+        else launch_family_t<LAYOUT, false, 64, MODE>(d, p, a, stream);
+        return;
+    }
     if (!aligned) launch_family_t<LAYOUT, false, 64, MODE>(d, p, a, stream);
     else if (p.tile == 128 || MODE == WALK_REDO) launch_family_t<LAYOUT, true, 128, MODE>(d, p, a, stream);
     else launch_family_t<LAYOUT, true, 64, MODE>(d, p, a, stream);

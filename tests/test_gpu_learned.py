@@ -277,6 +277,19 @@ def test_learned_subchunk_rewalk(n, L):
     assert got.rerun_chunks > 0
 
 
+def test_learned_sparse_rows():
+    """Learned speculation over the sparse-row layout (selected walks,
+    coverage, re-walks)."""
+    rng = np.random.default_rng(31)
+    sym = rng.choice(256, size=16, replace=False).astype(np.uint8)
+    dfa = W.sparse_dfa(rng, 60, bytes(range(256)), 1, 4, rng.choice(np.arange(1, 60), size=5, replace=False),
+                       explicit_cols=sym)
+    text = W.zipf_text(rng, sym, 3_000_017)
+    for mm in (1, 4):
+        learned_case("sparse rows", dfa, text, random_params(dfa.num_states, 41), mm, chunk_len=2048,
+                     layout=P.LAYOUT_SPARSE_LDS)
+
+
 def test_learned_adversarial_proposal():
     """A proposal that always prefers the highest state id (biases only) on a
     non-synchronising automaton: coverage fails along the whole text and the

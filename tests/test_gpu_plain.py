@@ -237,6 +237,56 @@ def test_hot_rows_sparse_and_dense(group):
              group=group, layout=P.LAYOUT_HOT_LDS)
 
 
+@pytest.mark.parametrize("group", [2, 4, 8, 16])
+def test_sparse_rows(group):
+    """Sparse-row layout (a default and at most four exceptions per state):
+    a byte DFA with explicit columns among 64 Zipf symbols, the same table
+    with a default per state other than state 0, a 20-symbol alphabet whose
+    invalid column is one of the exceptions (and a text with a byte outside
+    it), lookback sets, and a table with five exceptions in a row, which
+    falls back to another layout."""
+    rng = np.random.default_rng(900 + group)
+    sym = rng.choice(256, size=64, replace=False).astype(np.uint8)
+    acc = rng.choice(np.arange(1, 3000), size=16, replace=False)
+    sp = W.sparse_dfa(rng, 3000, bytes(range(256)), 1, 4, acc, explicit_cols=sym)
+    m = P.Matcher(sp.table, sp.alphabet, sp.start, sp.accepting, layout=P.LAYOUT_SPARSE_LDS)
+    assert m.describe()["layout"] == P.LAYOUT_SPARSE_LDS
+    m.close()
+    text = W.zipf_text(rng, sym, (1 << 20) + 77)
+    run_case(f"sparse G={group}", sp, text, chunk_len=1024, group=group, layout=P.LAYOUT_SPARSE_LDS)
+    run_case(f"sparse tiny G={group}", sp, text[:1000], chunk_len=64, group=group, offset=3,
+             layout=P.LAYOUT_SPARSE_LDS)
+    run_case(f"sparse lookback G={group}", sp, text, chunk_len=2048, group=group, layout=P.LAYOUT_SPARSE_LDS,
+             lookback=64, check_spec=False)
+    dflt = (np.arange(3000, dtype=np.uint32) % 97 + 1)[:, None]
+    shifted = W.Dfa(np.where(sp.table == 0, dflt, sp.table).astype(np.uint32), sp.alphabet, 5, sp.accepting)
+    m = P.Matcher(shifted.table, shifted.alphabet, shifted.start, shifted.accepting, layout=P.LAYOUT_SPARSE_LDS)
+    assert m.describe()["layout"] == P.LAYOUT_SPARSE_LDS
+    m.close()
+    run_case(f"sparse defaults G={group}", shifted, text, chunk_len=512, group=group, layout=P.LAYOUT_SPARSE_LDS)
+    a20 = bytes(rng.choice(256, size=20, replace=False).astype(np.uint8))
+    small = W.sparse_dfa(rng, 400, a20, 0, 3, rng.choice(np.arange(1, 400), size=9, replace=False))
+    m = P.Matcher(small.table, small.alphabet, small.start, small.accepting, layout=P.LAYOUT_SPARSE_LDS,
+                  chunk_len=1024, group=group)
+    assert m.describe()["layout"] == P.LAYOUT_SPARSE_LDS
+    stext = W.uniform_text(rng, a20, 300_001)
+    want = oracle.walk_dfa(small, stext)
+    got = m.match(torch.from_numpy(stext).cuda())
+    assert (got.final_state, got.accept, got.count) == (want.final_state, want.accept, want.count)
+    bad = stext.copy()
+    bad[123_456] = next(x for x in range(256) if x not in a20)
+    with pytest.raises(P.ParemError) as e:
+        m.match(torch.from_numpy(bad).cuda())
+    assert e.value.status == P.PAREM_ESYMBOL
+    m.close()
+    five = W.sparse_dfa(rng, 300, bytes(range(256)), 5, 5, acc[:3] % 300)
+    m = P.Matcher(five.table, five.alphabet, five.start, five.accepting, layout=P.LAYOUT_SPARSE_LDS)
+    assert m.describe()["layout"] != P.LAYOUT_SPARSE_LDS
+    m.close()
+    run_case(f"sparse fallback G={group}", five, W.uniform_text(rng, five.alphabet, 200_000), chunk_len=1024,
+             group=group, layout=P.LAYOUT_SPARSE_LDS)
+
+
 def test_invalid_bytes():
     rng = np.random.default_rng(5)
     dfa = W.random_dense_dfa(rng, 9, b"ACGT", num_accepting=2)
