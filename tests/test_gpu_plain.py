@@ -336,6 +336,10 @@ def test_compile_errors():
 def test_config3_reduced():
     dfa, text = W.config3(n=64 << 20)
     run_case("config3 64MiB", dfa, text)
+    m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, layout=P.LAYOUT_SPARSE_LDS)
+    assert m.describe()["layout"] == P.LAYOUT_SPARSE_LDS
+    m.close()
+    run_case("config3 64MiB sparse rows", dfa, text, layout=P.LAYOUT_SPARSE_LDS)
 
 
 def test_config5_sample_pairs():
