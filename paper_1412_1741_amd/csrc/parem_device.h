@@ -1063,13 +1063,13 @@ __device__ __forceinline__ uint64_t block_sum(uint64_t v) {
 template <typename CntOf, typename PresentOf>
 __device__ __forceinline__ void uniform_chain(const ComposeArgs &a, const Tree &t, uint32_t np, CntOf cnt_of,
                                               PresentOf present_of, uint64_t &sum, uint32_t &end) {
-    const uint32_t i = threadIdx.x;
     uint64_t contrib = 0;
     int fail = 0;
-    if (i < np && i > 0) {
+    for (uint32_t i = threadIdx.x; i < np; i += kComposeThreads) {
+        if (i == 0) continue;
         const int x = lookup(a, t, t.cls[i], t.sz[i], t.lead[i - 1]);
         if (x < 0 || !present_of(i, (uint32_t)x)) fail = 1;
-        else contrib = cnt_of(i, (uint32_t)x);
+        else contrib += cnt_of(i, (uint32_t)x);
     }
     sum = block_sum(contrib);
     fail = __syncthreads_or(fail);
@@ -1208,7 +1208,7 @@ __device__ __forceinline__ void compose_segs_seg(uint8_t *smem, const SegOut &in
         runs += in_runs[g0 + i];
     }
     const uint64_t runs_total = block_sum(runs);
-    if (!__syncthreads_or(nonuni) && np <= (uint32_t)kComposeThreads) {
+    if (!__syncthreads_or(nonuni)) {
         auto cnt_of = [&](uint32_t i, uint32_t x) { return in_cnt[(g0 + i) * RM + x]; };
         auto present_of = [&](uint32_t i, uint32_t x) { return in_end[(g0 + i) * RM + x] != kAbsent32; };
         auto first_of = [&](uint32_t j, uint64_t &c) {

@@ -119,7 +119,8 @@ struct PlainPlan {
     uint32_t L = 0;          // chunk length
     uint64_t chunks = 0;
     uint32_t RM = 0;         // map width (max_spec)
-    uint32_t P = 0;          // maps composed per workgroup
+    uint32_t P = 0;          // chunk maps composed per workgroup (first level)
+    uint32_t P2 = 0;         // segment maps composed per workgroup (later levels)
     uint32_t G = 0;          // lockstep group
     uint32_t tile = 0;       // staged tile bytes per chunk (64 or 128)
     uint32_t merge = 1;      // 0: speculated runs are never merged
@@ -149,7 +150,8 @@ constexpr uint32_t kLookCap = 64;       // largest lookback set walked as a sele
 constexpr uint32_t kLookStates = 16384; // lookback sets need Q + 1 <= this
 
 // chunking, map width, group, tile and workspace carving of one text under options o
-parem_status plan_chunks(const DeviceDfa &d, uint64_t len, const parem_options &o, bool keep, PlainPlan *p);
+parem_status plan_chunks(const DeviceDfa &d, uint64_t len, const parem_options &o, bool keep, PlainPlan *p,
+                         bool wide_segs = false);
 parem_status plan_plain(const DeviceDfa &d, uint64_t len, PlainPlan *p);
 parem_status launch_plain(const DeviceDfa &d, const PlainPlan &p, const uint8_t *d_text,
                           void *d_ws, hipStream_t stream, parem_result *d_out,

@@ -512,7 +512,8 @@ __global__ void k_set_u32(uint32_t *__restrict__ p, uint32_t v) {
 // host side: plan and launches
 // ---------------------------------------------------------------------------
 
-parem_status plan_chunks(const DeviceDfa &d, uint64_t len, const parem_options &o, bool keep, PlainPlan *p) {
+parem_status plan_chunks(const DeviceDfa &d, uint64_t len, const parem_options &o, bool keep, PlainPlan *p,
+                         bool wide_segs) {
     PlainPlan q;
     q.n = len;
     q.RM = d.max_spec;
@@ -538,6 +539,11 @@ parem_status plan_chunks(const DeviceDfa &d, uint64_t len, const parem_options &
     while (P > 2 && compose_lds(P, q.RM, d.inv_lds) > 64 * 1024) P >>= 1;
     if (compose_lds(P, q.RM, d.inv_lds) > 150 * 1024) return PAREM_EUNSUPPORTED;
     q.P = P;
+    // later levels: with wide_segs up to 512 segment maps a workgroup (LDS
+    // up to 150 KiB), so that 2^17 chunks need two levels, not three
+    uint32_t P2 = P;
+    while (wide_segs && P2 < 512 && compose_lds(2 * P2, q.RM, d.inv_lds) <= 150 * 1024) P2 <<= 1;
+    q.P2 = P2;
     uint64_t off = 0;
     auto take = [&](uint64_t bytes) {
         uint64_t o = off;
@@ -557,7 +563,8 @@ parem_status plan_chunks(const DeviceDfa &d, uint64_t len, const parem_options &
     uint64_t m = q.chunks;
     q.levels.clear();
     do {
-        m = (m + P - 1) / P;
+        const uint32_t fan = q.levels.empty() ? P : P2;
+        m = (m + fan - 1) / fan;
         q.levels.push_back(m);
     } while (m > 1);
     const size_t nbuf = keep ? q.levels.size() : std::min<size_t>(2, q.levels.size());
@@ -578,7 +585,7 @@ parem_status plan_chunks(const DeviceDfa &d, uint64_t len, const parem_options &
 }
 
 parem_status plan_plain(const DeviceDfa &d, uint64_t len, PlainPlan *p) {
-    return plan_chunks(d, len, d.opt, false, p);
+    return plan_chunks(d, len, d.opt, false, p, true);
 }
 
 template <int MODE>
@@ -597,14 +604,16 @@ static void launch_walk(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &
 static parem_status launch_compose(const DeviceDfa &d, const PlainPlan &p, uint8_t *ws, hipStream_t stream,
                                    parem_result *d_out) {
     const ComposeArgs a = compose_args(d, p);
+    ComposeArgs a2 = a;
+    a2.P = p.P2;
     const size_t lds = compose_lds(p.P, p.RM, d.inv_lds);
-    if (lds > 64 * 1024) {
-        if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_compose_chunks),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess ||
-            hipFuncSetAttribute(reinterpret_cast<const void *>(k_compose_segs),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-            return PAREM_EDEVICE;
-    }
+    const size_t lds2 = compose_lds(p.P2, p.RM, d.inv_lds);
+    if (lds > 64 * 1024 && hipFuncSetAttribute(reinterpret_cast<const void *>(k_compose_chunks),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return PAREM_EDEVICE;
+    if (lds2 > 64 * 1024 && hipFuncSetAttribute(reinterpret_cast<const void *>(k_compose_segs),
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2) != hipSuccess)
+        return PAREM_EDEVICE;
     const uint32_t *map = reinterpret_cast<const uint32_t *>(ws + p.off_map);
     const uint16_t *mcl = reinterpret_cast<const uint16_t *>(ws + p.off_mcls);
     const uint16_t *mld = reinterpret_cast<const uint16_t *>(ws + p.off_mlead);
@@ -616,7 +625,7 @@ static parem_status launch_compose(const DeviceDfa &d, const PlainPlan &p, uint8
         const size_t src = p.keep ? l - 1 : (l - 1) % 2, dst = p.keep ? l : l % 2;
         const SegOut in = seg_out(p, ws, src);
         const uint64_t nout = p.levels[l];
-        hipLaunchKernelGGL(k_compose_segs, dim3((uint32_t)nout), dim3(kComposeThreads), lds, stream, in, nin, a,
+        hipLaunchKernelGGL(k_compose_segs, dim3((uint32_t)nout), dim3(kComposeThreads), lds2, stream, in, nin, a2,
                            seg_out(p, ws, dst), nout == 1 ? d_out : nullptr);
         if (hipGetLastError() != hipSuccess) return PAREM_EDEVICE;
         nin = nout;
@@ -694,7 +703,7 @@ parem_status launch_boundary(const DeviceDfa &d, const PlainPlan &p, const uint8
     for (size_t l = top; l-- > 0;) {
         const SegOut s = seg_out(p, ws, l);
         const uint64_t nmaps = p.levels[l];
-        hipLaunchKernelGGL(k_entries<false>, dim3((uint32_t)((nmaps + 255) / 256)), dim3(256), 0, stream, nmaps, p.P,
+        hipLaunchKernelGGL(k_entries<false>, dim3((uint32_t)((nmaps + 255) / 256)), dim3(256), 0, stream, nmaps, p.P2,
                            reinterpret_cast<const uint32_t *>(ws + p.entries[l + 1]), s.end, s.cls, s.lead, nullptr,
                            nullptr, nullptr, d.d_inv, d.Q + 1, p.RM, d.sent,
                            reinterpret_cast<uint32_t *>(ws + p.entries[l]));
