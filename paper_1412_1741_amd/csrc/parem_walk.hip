@@ -725,7 +725,7 @@ parem_status plan_learned(const DeviceDfa &d, const Proposal &pr, uint64_t len, 
                           PlainPlan *p) {
     parem_options o = opt;
     o.lookback = 0;  // the proposal selects within Algorithm 1's sets
-    parem_status st = plan_chunks(d, len, o, false, p);
+    parem_status st = plan_chunks(d, len, o, false, p, true);
     if (st != PAREM_OK) return st;
     uint64_t off = p->bytes;
     const uint64_t ch = std::max<uint64_t>(p->chunks, 1);
