@@ -385,6 +385,12 @@ def test_nonsynchronizing_dfa():
     text = np.frombuffer(b"abcr", dtype=np.uint8)[rng.choice(4, size=300000, p=probs)]
     for lay in all_layouts():
         run_case(f"mixed layout={lay}", dfa2, text, chunk_len=128, layout=lay, group=8)
+    # more than 256 x 256 chunks: the second composition level takes more maps
+    # than a workgroup has threads, all non-uniform (general tree)
+    text = W.uniform_text(rng, alphabet, 64 * 70_001 + 5)
+    run_case("permutation, two wide levels", dfa, text, chunk_len=64, group=4)
+    run_case("mixed, two wide levels", dfa2,
+             np.frombuffer(b"abcr", dtype=np.uint8)[rng.choice(4, size=64 * 90_000, p=probs)], chunk_len=64, group=8)
 
 
 def lookback_runs(dfa, text, L, K, cap=64, kmax=4096):
