@@ -38,8 +38,10 @@ void release(DeviceDfa &d) {
     hipFree(d.d_enc);
     hipFree(d.d_next);
     hipFree(d.d_step);
+    hipFree(d.d_bytes);
     d.d_next = nullptr;
     d.d_step = nullptr;
+    d.d_bytes = nullptr;
     d.d_inv = nullptr;
     d.d_full = nullptr;
     d.d_enc = nullptr;
@@ -382,12 +384,14 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
     if (layout == PAREM_LAYOUT_BYTE_LDS && !lds_ok) layout = class_ok ? PAREM_LAYOUT_CLASS_LDS : big;
     if (layout == PAREM_LAYOUT_CLASS_LDS && !class_ok) layout = big;
     if (layout == PAREM_LAYOUT_HOT_LDS && !hot_ok) layout = PAREM_LAYOUT_BYTE_GLOBAL;
-    // sparse rows: only when asked for and every row has a default and at
-    // most kSparseExc other columns (the invalid column counts unless every
-    // byte is in the alphabet)
+    // sparse rows: asked for, or chosen automatically when no dense table fits
+    // LDS, and only when every row has a default and at most kSparseExc other
+    // columns (the invalid column counts unless every byte is in the alphabet)
     std::vector<uint8_t> sparse_image;
     if (layout == PAREM_LAYOUT_SPARSE_LDS && !sparse_rows(d, t, sparse_image))
         layout = class_ok ? PAREM_LAYOUT_CLASS_LDS : big;
+    if ((o.layout == PAREM_LAYOUT_AUTO) && !kg_ok && !lds_ok && !class_ok && sparse_rows(d, t, sparse_image))
+        layout = PAREM_LAYOUT_SPARSE_LDS;
     d.layout = layout;
     if (layout != PAREM_LAYOUT_KGRAM_LDS) {
         d.kgram = 0;
@@ -441,6 +445,8 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
             uint8_t *p = nullptr;
             st = upload(sparse_image, &p);
             d.d_table = p;
+            // batches walk such a table as the byte table through L2
+            if (st == PAREM_OK) st = upload(byte_table<uint16_t>(d, t, 256), &d.d_bytes);
         } else if (layout == PAREM_LAYOUT_HOT_LDS) {
             std::vector<uint8_t> image;
             std::vector<uint16_t> full, enc;

@@ -392,7 +392,8 @@ static parem_status batch_plan(const parem_handle *dfas, const uint64_t *lens, u
         q.ca = compose_args(d, p);
         if (lens[i] == 0 || b->props[i]) continue;
         q.w = walk_args(d, p, nullptr, pws);
-        q.table = d.d_table;
+        // sparse rows: the batch kernels walk the byte table through L2
+        q.table = d.layout == PAREM_LAYOUT_SPARSE_LDS ? d.d_bytes : d.d_table;
         q.table_bytes = d.table_bytes;
         q.full = d.d_full;
         q.enc = d.d_enc;
@@ -558,9 +559,6 @@ parem_status parem_batch_create(const parem_handle *dfas, const uint64_t *lens, 
                                 parem_batch *out) {
     if (!out || (n && (!dfas || !lens))) return PAREM_EINVAL;
     *out = nullptr;
-    // the batch kernels have no sparse-row variant
-    for (uint32_t i = 0; i < n; ++i)
-        if (dfas[i] && dfas[i]->dev.layout == PAREM_LAYOUT_SPARSE_LDS) return PAREM_EUNSUPPORTED;
     parem_batch_s *b = new (std::nothrow) parem_batch_s;
     if (!b) return PAREM_ENOMEM;
     parem_status st = parem::batch_plan(dfas, lens, n, opts, props, m, b);

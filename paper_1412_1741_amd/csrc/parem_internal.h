@@ -68,6 +68,7 @@ struct DeviceDfa {
     uint16_t *d_next = nullptr;      // [(Q+1) x A] next state by class (lookback sets); row Q: the sentinel
     uint16_t *d_enc = nullptr;       // [Q+1] encoded id of each state (slot when hot, 0x4000 | id else)
     uint16_t *d_step = nullptr;      // [(Q+1) x (A+1)] next state by class | final << 15 (small tables only)
+    uint16_t *d_bytes = nullptr;     // sparse-row layout: the (Q+1) x 256 u16 byte table for batch walks
     uint32_t hot_rows = 0;
 };
 

@@ -130,6 +130,24 @@ def test_batch_graph_replays_new_texts():
         check(cur, b.run(dev, use_graph=False), f"eager {rep}")
 
 
+def test_batch_sparse_row_handles():
+    """Handles compiled with sparse rows (large sparse byte DFAs) in a batch:
+    walked with their byte table through L2, beside other pairs."""
+    rng = np.random.default_rng(77)
+    pairs = []
+    for q in (300, 1200, 4000):
+        sym = rng.choice(256, size=32, replace=False).astype(np.uint8)
+        dfa = W.sparse_dfa(rng, q, bytes(range(256)), 1, 4, rng.choice(np.arange(1, q), size=7, replace=False),
+                           explicit_cols=sym)
+        pairs.append((dfa, W.zipf_text(rng, sym, int(rng.integers(5_000, 400_000)))))
+    pairs += random_pairs(404, 12, max_len=200_000)
+    ms = matchers(pairs)
+    assert [m.describe()["layout"] for m in ms[:3]] == [P.LAYOUT_SPARSE_LDS] * 3
+    say("[case] batch with sparse-row handles")
+    b = P.Batch(ms, [t.size for _, t in pairs])
+    check(pairs, b.run(to_device([t for _, t in pairs])), "sparse rows")
+
+
 def test_batch_per_pair_options():
     pairs = random_pairs(303, 32, max_len=100_000)
     ms = matchers(pairs)

@@ -222,11 +222,12 @@ def test_hot_rows_sparse_and_dense(group):
     acc = rng.choice(np.arange(1, 3000), size=16, replace=False)
     sparse = W.sparse_dfa(rng, 3000, bytes(range(256)), 4, 4, acc, explicit_cols=sym)
     text = W.zipf_text(rng, sym, (1 << 20) + 77)
-    m = P.Matcher(sparse.table, sparse.alphabet, sparse.start, sparse.accepting)
+    m = P.Matcher(sparse.table, sparse.alphabet, sparse.start, sparse.accepting, layout=P.LAYOUT_HOT_LDS)
     assert m.describe()["layout"] == P.LAYOUT_HOT_LDS
     m.close()
-    run_case(f"hot sparse G={group}", sparse, text, chunk_len=1024, group=group)
-    run_case(f"hot sparse tiny G={group}", sparse, text[:1000], chunk_len=64, group=group, offset=3)
+    run_case(f"hot sparse G={group}", sparse, text, chunk_len=1024, group=group, layout=P.LAYOUT_HOT_LDS)
+    run_case(f"hot sparse tiny G={group}", sparse, text[:1000], chunk_len=64, group=group, offset=3,
+             layout=P.LAYOUT_HOT_LDS)
     dense = W.random_dense_dfa(rng, 700, bytes(rng.choice(256, size=4, replace=False).astype(np.uint8)),
                                num_accepting=70)
     run_case(f"hot dense G={group}", dense, W.uniform_text(rng, dense.alphabet, 1 << 18), chunk_len=2048,
@@ -250,6 +251,9 @@ def test_sparse_rows(group):
     acc = rng.choice(np.arange(1, 3000), size=16, replace=False)
     sp = W.sparse_dfa(rng, 3000, bytes(range(256)), 1, 4, acc, explicit_cols=sym)
     m = P.Matcher(sp.table, sp.alphabet, sp.start, sp.accepting, layout=P.LAYOUT_SPARSE_LDS)
+    assert m.describe()["layout"] == P.LAYOUT_SPARSE_LDS
+    m.close()
+    m = P.Matcher(sp.table, sp.alphabet, sp.start, sp.accepting)  # no dense LDS table fits: AUTO takes it
     assert m.describe()["layout"] == P.LAYOUT_SPARSE_LDS
     m.close()
     text = W.zipf_text(rng, sym, (1 << 20) + 77)
@@ -336,10 +340,10 @@ def test_compile_errors():
 def test_config3_reduced():
     dfa, text = W.config3(n=64 << 20)
     run_case("config3 64MiB", dfa, text)
-    m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, layout=P.LAYOUT_SPARSE_LDS)
+    m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting)
     assert m.describe()["layout"] == P.LAYOUT_SPARSE_LDS
     m.close()
-    run_case("config3 64MiB sparse rows", dfa, text, layout=P.LAYOUT_SPARSE_LDS)
+    run_case("config3 64MiB hot rows", dfa, text, layout=P.LAYOUT_HOT_LDS)
 
 
 def test_config5_sample_pairs():
@@ -461,11 +465,12 @@ def test_lookback_invalid_bytes():
 
 def test_config3_full_size():
     """The large sparse byte DFA over its full 4 GiB Zipf text (the
-    benchmark's sparse workload), hot-row layout, against the oracle."""
+    benchmark's sparse workload), sparse-row layout (the automatic choice),
+    against the oracle."""
     dfa, text = W.config3()
     say(f"[case] config3 full: n={text.size}")
     m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting)
-    assert m.describe()["layout"] == P.LAYOUT_HOT_LDS
+    assert m.describe()["layout"] == P.LAYOUT_SPARSE_LDS
     dev = torch.from_numpy(text).cuda()
     got = m.match(dev)
     m.close()
