@@ -738,49 +738,68 @@ __global__ __launch_bounds__(kFuseThreads) void k_mlp_select(const uint8_t *__re
     // top-m within each row's class list (at most 64 positions), in the order
     // (logit descending, position ascending) as k_topm: min(m, sz - m) passes,
     // each taking the best remaining position or dropping the worst kept one
-    // (the last of the order); the kept positions are written ascending.
-    if (tid < kFuseRows) {
-        const uint64_t row = r0 + tid;
+    // (the last of the order). Four lanes per row (one workgroup of 512 holds
+    // the 128 rows): each scans the positions j = q (mod 4), two quad shuffles
+    // pick the pass's winner; the kept positions are written ascending.
+    static_assert(kFuseThreads == 4 * kFuseRows, "four lanes per row");
+    {
+        const uint32_t r = tid >> 2, q = tid & 3;
+        const uint64_t row = r0 + r;
         if (row < chunks) {
-            const uint32_t sz = Cl[2 * tid + 1];
-            const float *z = Key + tid * kFuseKeyRow;
+            const uint32_t sz = Cl[2 * r + 1];
+            const float *z = Key + r * kFuseKeyRow;
             const uint32_t take = sz < m ? sz : m;
             uint64_t keep = sz >= 64 ? ~0ull : (1ull << sz) - 1;
+            // (v, j) of two lanes of the quad: the one first in the pass's order
+            auto pick = [&](float &v, int &j, bool best) {
+#pragma unroll
+                for (int o = 1; o <= 2; o <<= 1) {
+                    const float ov = __shfl_xor(v, o, 64);
+                    const int oj = __shfl_xor(j, o, 64);
+                    const bool take_o = oj >= 0 && (j < 0 || (best ? (ov > v || (ov == v && oj < j))
+                                                                   : (ov < v || (ov == v && oj > j))));
+                    if (take_o) {
+                        v = ov;
+                        j = oj;
+                    }
+                }
+            };
             if (take < sz && take <= sz - take) {
                 keep = 0;
                 for (uint32_t t = 0; t < take; ++t) {
                     float best = 0.0f;
                     int bj = -1;
-#pragma unroll 8
-                    for (uint32_t j = 0; j < sz; ++j) {
+                    for (uint32_t j = q; j < sz; j += 4) {
                         const float v = z[j];
                         if (!((keep >> j) & 1ull) && (bj < 0 || v > best)) {
                             best = v;
                             bj = (int)j;
                         }
                     }
+                    pick(best, bj, true);
                     keep |= 1ull << bj;
                 }
             } else if (take < sz) {
                 for (uint32_t t = 0; t < sz - take; ++t) {
                     float worst = 0.0f;
                     int wj = -1;
-#pragma unroll 8
-                    for (uint32_t j = 0; j < sz; ++j) {
+                    for (uint32_t j = q; j < sz; j += 4) {
                         const float v = z[j];
                         if (((keep >> j) & 1ull) && (wj < 0 || v <= worst)) {
                             worst = v;
                             wj = (int)j;
                         }
                     }
+                    // (a lane's candidates come in ascending j: on a tie the
+                    // later one is the one to drop)
+                    pick(worst, wj, false);
                     keep &= ~(1ull << wj);
                 }
             }
             uint16_t *out = sel + row * RM;
-            uint32_t o = 0;
-            for (uint32_t j = 0; j < sz; ++j)
-                if ((keep >> j) & 1ull) out[o++] = (uint16_t)j;
-            nsel[row] = (uint8_t)take;
+            for (uint32_t j = q; j < sz; j += 4)
+                if ((keep >> j) & 1ull) out[__popcll(keep & ((1ull << j) - 1))] = (uint16_t)j;
+            if (q == 0) nsel[row] = (uint8_t)take;
         }
     }
 }
