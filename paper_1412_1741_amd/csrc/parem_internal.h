@@ -111,8 +111,11 @@ struct Proposal {
 
 void proposal_layout(Proposal &p);
 size_t proposal_infer_bytes(const Proposal &p, uint64_t rows);
+// `zero`: nzero u32 counters the selection also clears (the learned match's
+// coverage counters, which saves a launch); may be null
 parem_status proposal_select(const Proposal &p, const uint8_t *d_text, uint64_t L, uint32_t chunks, uint32_t m,
-                             uint32_t RM, void *scratch, hipStream_t s, uint16_t *sel, uint8_t *nsel);
+                             uint32_t RM, void *scratch, hipStream_t s, uint16_t *sel, uint8_t *nsel,
+                             uint32_t *zero = nullptr, uint32_t nzero = 0);
 
 // Workspace carving for one match.
 struct PlainPlan {

@@ -444,6 +444,10 @@ __global__ __launch_bounds__(256) void k_embed_bwd(const uint16_t *__restrict__ 
         if (acc[i] != 0.0f) atomicAdd(&demb[i], acc[i]);
 }
 
+__global__ void k_zero_u32(uint32_t *__restrict__ p, uint32_t n) {
+    if (threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
 __global__ void k_adamw(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
                         float *__restrict__ v, uint16_t *__restrict__ w16, size_t n, float lr, float b1, float b2,
                         float eps, float wd, float bc1, float bc2) {
@@ -614,8 +618,10 @@ __global__ __launch_bounds__(kFuseThreads) void k_mlp_select(const uint8_t *__re
                                                             size_t o_b3, uint32_t S, const uint32_t *__restrict__ loff,
                                                             const uint32_t *__restrict__ llist, uint32_t m,
                                                             uint32_t RM, uint16_t *__restrict__ sel,
-                                                            uint8_t *__restrict__ nsel) {
+                                                            uint8_t *__restrict__ nsel, uint32_t *__restrict__ zero,
+                                                            uint32_t nzero) {
     extern __shared__ __align__(16) uint8_t smem[];
+    if (blockIdx.x == 0 && threadIdx.x < nzero) zero[threadIdx.x] = 0u;
     uint16_t *Bs = reinterpret_cast<uint16_t *>(smem);
     uint16_t *H = reinterpret_cast<uint16_t *>(smem + FuseLds::kB);
     uint16_t *E = reinterpret_cast<uint16_t *>(smem + FuseLds::kB + FuseLds::kH);
@@ -967,7 +973,8 @@ size_t proposal_infer_bytes(const Proposal &p, uint64_t rows) {
 
 // logits of the chunk boundaries c * L and the top-m selection per chunk
 parem_status proposal_select(const Proposal &p, const uint8_t *d_text, uint64_t L, uint32_t chunks, uint32_t m,
-                             uint32_t RM, void *scratch, hipStream_t s, uint16_t *sel, uint8_t *nsel) {
+                             uint32_t RM, void *scratch, hipStream_t s, uint16_t *sel, uint8_t *nsel, uint32_t *zero,
+                             uint32_t nzero) {
     const DeviceDfa &d = *p.dfa;
     if (p.S <= (uint32_t)kFuseHeadMax && L >= 2 * kMlpWindow) {
         // fused path: no intermediates in memory
@@ -981,7 +988,7 @@ parem_status proposal_select(const Proposal &p, const uint8_t *d_text, uint64_t 
         hipLaunchKernelGGL(k_mlp_select, dim3((chunks + kFuseRows - 1) / kFuseRows), dim3(kFuseThreads),
                            FuseLds::kBytes, s, d_text, L, chunks, d.d_cls, d.A + 1, p.d_params16, p.d_params,
                            p.o_emb, p.o_W1, p.o_b1, p.o_W2, p.o_b2, p.o_W3, p.o_b3, p.S, d.d_loff, d.d_llist, m, RM,
-                           sel, nsel);
+                           sel, nsel, zero, nzero);
         return hipGetLastError() == hipSuccess ? PAREM_OK : PAREM_EDEVICE;
     }
     size_t off = 0;
@@ -997,6 +1004,7 @@ parem_status proposal_select(const Proposal &p, const uint8_t *d_text, uint64_t 
     forward_rows(p, s, win, chunks, X, nullptr, H1, nullptr, H2, Z);
     hipLaunchKernelGGL(k_topm, dim3((chunks + 255) / 256), dim3(256), 0, s, Z, chunks, p.S, wcls, d.d_loff,
                        d.d_llist, m, RM, sel, nsel);
+    if (nzero) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, zero, nzero);
     return hipGetLastError() == hipSuccess ? PAREM_OK : PAREM_EDEVICE;
 }
 

@@ -769,7 +769,10 @@ parem_status launch_learned(const DeviceDfa &d, const Proposal &pr, const PlainP
     const uint32_t g = (C + 255) / 256;
     if (ev_begin && hipEventRecord(ev_begin, stream) != hipSuccess) return PAREM_EDEVICE;
     // 1. proposal: top-m of each chunk's speculated set
-    parem_status st = proposal_select(pr, d_text, p.L, C, p.m, p.m, ws + p.off_mlp, stream, sel, nsel);
+    // the selection also clears the coverage counters of step 3
+    // (flags: 0 chunks marked, 1 escalation, 8 + round: marked in the round)
+    parem_status st = proposal_select(pr, d_text, p.L, C, p.m, p.m, ws + p.off_mlp, stream, sel, nsel, flags,
+                                      8u + kCoverRounds + 1);
     if (st != PAREM_OK) return st;
     // 2. walk the selected states
     WalkArgs a = walk_args(d, p, d_text, ws);
@@ -779,8 +782,6 @@ parem_status launch_learned(const DeviceDfa &d, const Proposal &pr, const PlainP
     launch_walk<WALK_SELECTED>(d, p, a, stream, aligned);
     if (hipGetLastError() != hipSuccess) return PAREM_EDEVICE;
     // 3. verify coverage, walk uncovered chunks again from their whole set
-    //    (flags: 0 chunks marked, 1 escalation, 8 + round: marked in the round)
-    hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(64), 0, stream, flags, 8u + kCoverRounds + 1);
     unsigned long long *part = reinterpret_cast<unsigned long long *>(ws + p.off_part);
     WalkArgs r = walk_args(d, p, d_text, ws);
     r.redo = redo;
