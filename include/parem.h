@@ -204,13 +204,28 @@ parem_status parem_boundary_states(parem_handle h, const uint8_t *d_text, uint64
  *                         d_labels (u32, device) the true states there. Only
  *                         the states of the boundary's speculated set (the
  *                         image of the column of the byte before it) take
- *                         part in the softmax; the label must be one of them.
- *                         lr = 0 and weight_decay = 0 compute the gradient
- *                         without updating. d_loss (device float, may be
- *                         NULL) receives the mean loss.
+ *                         part in the softmax. A row whose label is not one
+ *                         of them (e.g. 0xffffffff, the boundary state after
+ *                         a byte outside the alphabet) or whose position is
+ *                         beyond len takes no part: zero gradient, no loss
+ *                         (the mean still divides by batch). lr = 0 and
+ *                         weight_decay = 0 compute the gradient without
+ *                         updating. d_loss (device float, may be NULL)
+ *                         receives the mean loss.
  * parem_proposal_params   copies the fp32 weights and the last gradient
  *                         (either pointer may be NULL) to the host.
- * parem_proposal_logits   logits [batch][Q] (device fp32) at d_positions.
+ * parem_proposal_logits   logits [batch][Q] (device fp32) at d_positions
+ *                         (u64, device, byte offsets into the len-byte
+ *                         d_text; a position beyond len scores an all-pad
+ *                         window and reads no text).
+ * parem_proposal_apply_grad
+ *                         one AdamW step of the fp32 master weights (and
+ *                         their bf16 copy) with the caller's gradient d_grad
+ *                         (device, nparams floats, the flat parameter order
+ *                         above), e.g. a gradient summed over several
+ *                         devices. Shares the step counter and moments with
+ *                         parem_proposal_train_step. Bias corrections
+ *                         1 - beta^t are formed in double precision.
  */
 parem_status parem_proposal_create(parem_handle h, const float *params, uint64_t nparams, parem_proposal *out);
 void parem_proposal_free(parem_proposal p);
@@ -218,8 +233,10 @@ parem_status parem_proposal_params(parem_proposal p, float *params_out, float *g
 parem_status parem_proposal_train_step(parem_proposal p, const uint8_t *d_text, uint64_t len,
                                        const uint64_t *d_positions, const uint32_t *d_labels, uint32_t batch,
                                        float lr, float weight_decay, void *stream, float *d_loss);
-parem_status parem_proposal_logits(parem_proposal p, const uint8_t *d_text, const uint64_t *d_positions,
-                                   uint32_t batch, float *d_logits, void *stream);
+parem_status parem_proposal_logits(parem_proposal p, const uint8_t *d_text, uint64_t len,
+                                   const uint64_t *d_positions, uint32_t batch, float *d_logits, void *stream);
+parem_status parem_proposal_apply_grad(parem_proposal p, const float *d_grad, uint64_t nparams, float lr,
+                                       float weight_decay, void *stream);
 
 /*
  * The selection learned speculation walks: for each chunk c of chunk_len

@@ -15,6 +15,17 @@ Parameter layout (one flat float vector, in this order): emb [256, 16],
 W1 [256, 512], b1 [256], W2 [256, 256], b2 [256], W3 [S, 256], b3 [S], where
 S is the number of head rows (the DFA's state count). The optimizer is
 AdamW (decoupled weight decay).
+
+Operand precision. The network is specified with bf16 operands and wide
+accumulation. ``forward`` and ``loss_and_grad`` take an optional rounding
+function ``rnd`` applied where a value becomes an operand of a product: the
+hidden activations h1 and h2, and the back-propagated products' left
+operands dz, da2 and da1 (the bias gradients sum the unrounded values). With
+``rnd=None`` every value stays float64: the exact definition, which the
+finite-difference pins check. With ``rnd=bf16_round`` the sums still run in
+float64, so the only difference from the exact definition is where operands
+are rounded, as the specified arithmetic rounds them (the weight matrices and
+the embedding are rounded by the caller, biases stay fp32).
 """
 from __future__ import annotations
 
@@ -67,51 +78,108 @@ def gelu_grad(u):
 PAD = 256  # window index of a byte before the text start: embeds as zeros
 
 
-def forward(flat, states, windows, mask):
+def _identity(a):
+    return a
+
+
+def _rounder(rnd):
+    if rnd is None:
+        return _identity
+    return lambda a: rnd(np.asarray(a, dtype=np.float32)).astype(np.float64)
+
+
+def forward(flat, states, windows, mask, rnd=None):
     """windows: [B, 32] byte values or PAD; mask: [B, S] bool (allowed
     states). Returns logits [B, S] (masked entries -inf) and the cache for
-    backward."""
+    backward. ``rnd`` rounds the hidden activations (see the module notes)."""
+    r = _rounder(rnd)
     p = unpack(np.asarray(flat, dtype=np.float64), states)
     emb = np.vstack([p["emb"], np.zeros((1, EMB))])
     x = emb[np.asarray(windows, dtype=np.int64)].reshape(len(windows), IN)
     a1 = x @ p["W1"].T + p["b1"]
-    h1 = gelu(a1)
+    h1 = r(gelu(a1))
     a2 = h1 @ p["W2"].T + p["b2"]
-    h2 = gelu(a2)
+    h2 = r(gelu(a2))
     z = h2 @ p["W3"].T + p["b3"]
     z = np.where(mask, z, -np.inf)
     return z, (p, x, a1, h1, a2, h2)
 
 
-def loss_and_grad(flat, states, windows, mask, labels):
-    """Mean masked softmax cross-entropy and its gradient (flat, float64)."""
-    z, (p, x, a1, h1, a2, h2) = forward(flat, states, windows, mask)
+def loss_and_grad(flat, states, windows, mask, labels, rnd=None, denom=None):
+    """Mean masked softmax cross-entropy and its gradient (flat, float64).
+    ``rnd`` rounds the products' operands (see the module notes). ``denom``
+    replaces the row count as the mean's divisor (a batch some of whose rows
+    were left out still divides by its full size)."""
+    r = _rounder(rnd)
+    z, (p, x, a1, h1, a2, h2) = forward(flat, states, windows, mask, rnd)
     b = len(labels)
+    nb = b if denom is None else denom
     zmax = np.max(z, axis=1, keepdims=True)
     e = np.where(mask, np.exp(z - zmax), 0.0)
     s = e.sum(axis=1, keepdims=True)
     prob = e / s
     lab = np.asarray(labels, dtype=np.int64)
-    loss = float(np.mean(np.log(s[:, 0]) + zmax[:, 0] - z[np.arange(b), lab]))
+    loss = float(np.sum(np.log(s[:, 0]) + zmax[:, 0] - z[np.arange(b), lab]) / nb)
     dz = prob.copy()
     dz[np.arange(b), lab] -= 1.0
-    dz /= b
+    dz /= nb
     g = {}
-    g["W3"] = dz.T @ h2
+    dzr = r(dz)
+    g["W3"] = dzr.T @ h2
     g["b3"] = dz.sum(axis=0)
-    dh2 = dz @ p["W3"]
+    dh2 = dzr @ p["W3"]
     da2 = dh2 * gelu_grad(a2)
-    g["W2"] = da2.T @ h1
+    da2r = r(da2)
+    g["W2"] = da2r.T @ h1
     g["b2"] = da2.sum(axis=0)
-    dh1 = da2 @ p["W2"]
+    dh1 = da2r @ p["W2"]
     da1 = dh1 * gelu_grad(a1)
-    g["W1"] = da1.T @ x
+    da1r = r(da1)
+    g["W1"] = da1r.T @ x
     g["b1"] = da1.sum(axis=0)
-    dx = (da1 @ p["W1"]).reshape(b, WINDOW, EMB)
+    dx = (da1r @ p["W1"]).reshape(b, WINDOW, EMB)
     demb = np.zeros((257, EMB))
     np.add.at(demb, np.asarray(windows, dtype=np.int64), dx)
     g["emb"] = demb[:256]  # the pad row is constant
     return loss, pack(g)
+
+
+def magnitudes(flat, states, windows, mask, labels, rnd=None, denom=None):
+    """Error-bound scale of every logit and gradient entry: the entry's own
+    last sum taken over absolute values of its terms (sum_k |a_k| |b_k|, plus
+    |bias|), with the operands that sum has under ``rnd``. A floating-point
+    error bound of a sum is proportional to this quantity. Returns (logit
+    scale [B, S], gradient scale, flat like the parameters). For tolerances
+    only."""
+    r = _rounder(rnd)
+    z, (p, x, a1, h1, a2, h2) = forward(flat, states, windows, mask, rnd)
+    b = len(labels)
+    ab = {k: np.abs(v) for k, v in p.items()}
+    zs = np.abs(h2) @ ab["W3"].T + ab["b3"]
+    zmax = np.max(z, axis=1, keepdims=True)
+    e = np.where(mask, np.exp(z - zmax), 0.0)
+    prob = e / e.sum(axis=1, keepdims=True)
+    lab = np.asarray(labels, dtype=np.int64)
+    dz = prob.copy()
+    dz[np.arange(b), lab] -= 1.0
+    dz /= b if denom is None else denom
+    dzr = r(dz)
+    da2 = (dzr @ p["W3"]) * gelu_grad(a2)
+    da2r = r(da2)
+    da1 = (da2r @ p["W2"]) * gelu_grad(a1)
+    da1r = r(da1)
+    g = {}
+    g["W3"] = np.abs(dzr).T @ np.abs(h2)
+    g["b3"] = np.abs(dz).sum(axis=0)
+    g["W2"] = np.abs(da2r).T @ np.abs(h1)
+    g["b2"] = np.abs(da2).sum(axis=0)
+    g["W1"] = np.abs(da1r).T @ np.abs(x)
+    g["b1"] = np.abs(da1).sum(axis=0)
+    dx = (np.abs(da1r) @ ab["W1"]).reshape(b, WINDOW, EMB)
+    demb = np.zeros((257, EMB))
+    np.add.at(demb, np.asarray(windows, dtype=np.int64), dx)
+    g["emb"] = demb[:256]
+    return zs, pack(g)
 
 
 def adamw(flat, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, wd=0.01):

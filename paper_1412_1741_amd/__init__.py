@@ -101,7 +101,9 @@ def _load() -> ctypes.CDLL:
     lib.parem_proposal_train_step.restype = i32
     lib.parem_proposal_train_step.argtypes = [vp, vp, u64, vp, vp, u32, ctypes.c_float, ctypes.c_float, vp, vp]
     lib.parem_proposal_logits.restype = i32
-    lib.parem_proposal_logits.argtypes = [vp, vp, vp, u32, vp, vp]
+    lib.parem_proposal_logits.argtypes = [vp, vp, u64, vp, u32, vp, vp]
+    lib.parem_proposal_apply_grad.restype = i32
+    lib.parem_proposal_apply_grad.argtypes = [vp, vp, u64, ctypes.c_float, ctypes.c_float, vp]
     lib.parem_proposal_select_size.restype = i32
     lib.parem_proposal_select_size.argtypes = [vp, u64, u32, ctypes.POINTER(u64)]
     lib.parem_proposal_select.restype = i32
@@ -131,7 +133,8 @@ _lib = None
 EXPORTED = ["parem_compile", "parem_free", "parem_strerror", "parem_describe", "parem_workspace_size",
             "parem_match_async", "parem_match_async_timed", "parem_match", "parem_boundary_workspace_size",
             "parem_boundary_states", "parem_proposal_create", "parem_proposal_free", "parem_proposal_params",
-            "parem_proposal_train_step", "parem_proposal_logits", "parem_proposal_select_size",
+            "parem_proposal_train_step", "parem_proposal_logits", "parem_proposal_apply_grad",
+            "parem_proposal_select_size",
             "parem_proposal_select", "parem_learned_workspace_size",
             "parem_match_learned_async", "parem_batch_create", "parem_batch_run", "parem_batch_describe",
             "parem_batch_free", "parem_match_batch", "parem_tune"]
@@ -251,10 +254,16 @@ def parem_proposal_train_step(proposal: int, d_text_ptr: int, length: int, d_pos
            "parem_proposal_train_step")
 
 
-def parem_proposal_logits(proposal: int, d_text_ptr: int, d_pos_ptr: int, batch: int, d_logits_ptr: int,
-                          stream_ptr: int) -> None:
-    _check(lib().parem_proposal_logits(proposal, d_text_ptr, d_pos_ptr, int(batch), d_logits_ptr,
+def parem_proposal_logits(proposal: int, d_text_ptr: int, length: int, d_pos_ptr: int, batch: int,
+                          d_logits_ptr: int, stream_ptr: int) -> None:
+    _check(lib().parem_proposal_logits(proposal, d_text_ptr, int(length), d_pos_ptr, int(batch), d_logits_ptr,
                                        stream_ptr or None), "parem_proposal_logits")
+
+
+def parem_proposal_apply_grad(proposal: int, d_grad_ptr: int, nparams: int, lr: float, weight_decay: float,
+                              stream_ptr: int) -> None:
+    _check(lib().parem_proposal_apply_grad(proposal, d_grad_ptr, int(nparams), float(lr), float(weight_decay),
+                                           stream_ptr or None), "parem_proposal_apply_grad")
 
 
 def parem_proposal_select_size(proposal: int, length: int, chunk_len: int) -> int:
@@ -392,7 +401,7 @@ class Matcher:
     def __init__(self, table, alphabet, start, accepting, **opts):
         self.handle = parem_compile(table, alphabet, start, accepting, **opts)
         self.num_states = int(np.asarray(table).shape[0])
-        self._ws = None
+        self._ws = {}
         self._lws = None
 
     def close(self):
@@ -437,22 +446,37 @@ class Matcher:
             raise ParemError(PAREM_ESYMBOL, "parem_match_learned_async")
         return res
 
-    def workspace(self, length: int):
+    def workspace(self, length: int, stream=None):
+        """Workspace for a match of ``length`` bytes on ``stream`` (default:
+        torch's current stream). Each stream has its own, so that matches
+        enqueued on different streams never share one. It is allocated on
+        that stream, so when a larger one replaces it the caching allocator
+        reuses its memory only in that stream's order."""
         import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
         need = parem_workspace_size(self.handle, length)
-        if self._ws is None or self._ws.numel() < need:
-            self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
-        return self._ws
+        ws = self._ws.get(s.cuda_stream)
+        if ws is None or ws.numel() < need:
+            with torch.cuda.stream(s):
+                ws = torch.empty(max(need, 256), dtype=torch.uint8, device="cuda")
+            self._ws[s.cuda_stream] = ws
+        return ws
 
     def match_async(self, text, out=None, stream=None):
         """Enqueue on torch's current stream (or ``stream``); returns the
-        40-byte device result tensor."""
+        40-byte device result tensor (allocated on that stream when not
+        given; a caller's ``out`` is recorded on it)."""
         import torch
         assert text.is_cuda and text.dtype == torch.uint8 and text.is_contiguous()
-        ws = self.workspace(text.numel())
-        if out is None:
-            out = torch.empty(RESULT_BYTES, dtype=torch.uint8, device=text.device)
         s = stream if stream is not None else torch.cuda.current_stream()
+        ws = self.workspace(text.numel(), s)
+        if out is None:
+            with torch.cuda.stream(s):
+                out = torch.empty(RESULT_BYTES, dtype=torch.uint8, device=text.device)
+        elif s != torch.cuda.current_stream():
+            out.record_stream(s)
+        if s != torch.cuda.current_stream():
+            text.record_stream(s)
         parem_match_async(self.handle, text.data_ptr(), text.numel(), ws.data_ptr(), ws.numel(), s.cuda_stream,
                           out.data_ptr())
         return out
@@ -570,9 +594,17 @@ class Proposal:
         import torch
         pos = torch.as_tensor(np.asarray(positions, dtype=np.uint64).view(np.int64), device=text.device)
         out = torch.empty((pos.numel(), self.states), dtype=torch.float32, device=text.device)
-        parem_proposal_logits(self.handle, text.data_ptr(), pos.data_ptr(), pos.numel(), out.data_ptr(),
-                              torch.cuda.current_stream().cuda_stream)
+        parem_proposal_logits(self.handle, text.data_ptr(), text.numel(), pos.data_ptr(), pos.numel(),
+                              out.data_ptr(), torch.cuda.current_stream().cuda_stream)
         return out
+
+    def apply_grad(self, grad, lr: float, weight_decay: float = 0.01):
+        """One AdamW step with ``grad`` (float32 device tensor, nparams)."""
+        import torch
+        assert grad.is_cuda and grad.dtype == torch.float32 and grad.numel() == self.nparams
+        g = grad.contiguous()
+        parem_proposal_apply_grad(self.handle, g.data_ptr(), self.nparams, lr, weight_decay,
+                                  torch.cuda.current_stream().cuda_stream)
 
     def select(self, text, chunk_len: int, m: int):
         """(positions [chunks, m] within each chunk's speculated list, counts)"""
@@ -622,8 +654,12 @@ def train_proposal(matcher: "Matcher", text, params, *, steps: int, batch: int =
     states = boundary_states(matcher, text, label_stride)
     n_lab = states.numel()
     pos_all = torch.arange(n_lab, dtype=torch.int64, device=text.device) * label_stride
-    keep = pos_all > 0  # the first boundary (q0, no window) teaches nothing
+    # the first boundary (q0, no window) teaches nothing; boundaries after a
+    # byte outside the alphabet have no state (0xffffffff) and are dropped
+    keep = (pos_all > 0) & (states != -1)
     pos_all, states = pos_all[keep], states[keep]
+    if pos_all.numel() == 0:
+        raise ValueError("no labelled boundary in the training text")
     g = torch.Generator(device="cpu").manual_seed(seed)
     history = []
     n = pos_all.numel()

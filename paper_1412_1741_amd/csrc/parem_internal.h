@@ -110,6 +110,7 @@ struct Proposal {
 };
 
 void proposal_layout(Proposal &p);
+parem_status proposal_adamw(Proposal &p, const float *d_grad, float lr, float wd, hipStream_t s);
 size_t proposal_infer_bytes(const Proposal &p, uint64_t rows);
 // `zero`: nzero u32 counters the selection also clears (the learned match's
 // coverage counters, which saves a launch); may be null

@@ -326,14 +326,23 @@ static void gemm(hipStream_t s, const uint16_t *A, int lda, const uint16_t *B, i
 // ---------------------------------------------------------------------------
 
 // window of the 32 bytes before each position (256 = pad before the text
-// start) and the class of the byte just before it
-__global__ void k_windows(const uint8_t *__restrict__ text, const uint64_t *__restrict__ pos, uint32_t B,
-                          const uint8_t *__restrict__ cls, uint32_t start_class, uint16_t *__restrict__ win,
-                          uint16_t *__restrict__ wcls) {
+// start) and the class of the byte just before it. A position beyond the
+// text (p > len) reads nothing: its window is all pad and its class
+// kRowInvalid, which the loss kernel skips.
+constexpr uint16_t kRowInvalid = 0xffffu;
+
+__global__ void k_windows(const uint8_t *__restrict__ text, uint64_t len, const uint64_t *__restrict__ pos,
+                          uint32_t B, const uint8_t *__restrict__ cls, uint32_t start_class,
+                          uint16_t *__restrict__ win, uint16_t *__restrict__ wcls) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= B * kMlpWindow) return;
     const uint32_t b = i / kMlpWindow, k = i % kMlpWindow;
     const uint64_t p = pos[b];
+    if (p > len) {
+        win[i] = 256;
+        if (k == 0) wcls[b] = kRowInvalid;
+        return;
+    }
     const int64_t q = (int64_t)p - (int64_t)kMlpWindow + (int64_t)k;
     win[i] = q < 0 ? (uint16_t)256 : (uint16_t)text[q];
     if (k == 0) wcls[b] = p == 0 ? (uint16_t)start_class : (uint16_t)cls[text[p - 1]];
@@ -363,7 +372,11 @@ __global__ void k_embed(const uint16_t *__restrict__ win, uint32_t B, const uint
 
 // one wave per row: masked softmax cross-entropy; writes dZ = (p - onehot) / B
 // (fp32 and bf16) and accumulates the mean loss. A state is allowed when it
-// belongs to the speculated list of the row's class (inverse index hit).
+// belongs to the speculated list of the row's class (inverse index hit). A
+// row whose position lay beyond the text, or whose label is not an allowed
+// state (e.g. 0xffffffff, the boundary state after a byte outside the
+// alphabet), takes no part: its dZ row is zero and it adds no loss (the mean
+// still divides by B).
 __global__ __launch_bounds__(256) void k_softmax_ce(const float *__restrict__ Z, uint32_t B, uint32_t S,
                                                     const uint32_t *__restrict__ label,
                                                     const uint16_t *__restrict__ wcls,
@@ -377,7 +390,16 @@ __global__ __launch_bounds__(256) void k_softmax_ce(const float *__restrict__ Z,
     float part = 0.0f;
     for (uint32_t row = blockIdx.x * 4 + wave; row < B; row += gridDim.x * 4) {
         const float *z = Z + (size_t)row * S;
-        const uint16_t *iv = inv + (size_t)wcls[row] * Q1;
+        const uint32_t lab = label[row];
+        const uint16_t rc = wcls[row];
+        const uint16_t *iv = inv + (size_t)(rc == kRowInvalid ? 0 : rc) * Q1;
+        if (rc == kRowInvalid || lab >= S || iv[lab] == 0xffffu) {
+            for (uint32_t s = lane; s < S; s += 64) {
+                dZ32[(size_t)row * S + s] = 0.0f;
+                dZ16[(size_t)row * S + s] = 0;
+            }
+            continue;
+        }
         float mx = -INFINITY;
         for (uint32_t s = lane; s < S; s += 64)
             if (iv[s] != 0xffffu) mx = fmaxf(mx, z[s]);
@@ -386,7 +408,6 @@ __global__ __launch_bounds__(256) void k_softmax_ce(const float *__restrict__ Z,
         for (uint32_t s = lane; s < S; s += 64)
             if (iv[s] != 0xffffu) sum += expf(z[s] - mx);
         for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
-        const uint32_t lab = label[row];
         for (uint32_t s = lane; s < S; s += 64) {
             float g = 0.0f;
             if (iv[s] != 0xffffu) g = expf(z[s] - mx) / sum;
@@ -912,7 +933,7 @@ parem_status proposal_train_step(Proposal &p, const uint8_t *d_text, uint64_t le
     uint16_t *win = at<uint16_t>(T, p.t_win), *wcls = at<uint16_t>(T, p.t_cls);
     const uint32_t S = p.S;
     const uint32_t nw = (B * kMlpWindow + 255) / 256;
-    hipLaunchKernelGGL(k_windows, dim3(nw), dim3(256), 0, s, d_text, d_pos, B, d.d_cls, d.A + 1, win, wcls);
+    hipLaunchKernelGGL(k_windows, dim3(nw), dim3(256), 0, s, d_text, len, d_pos, B, d.d_cls, d.A + 1, win, wcls);
     float *loss = d_loss_out ? d_loss_out : at<float>(T, p.t_loss);
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(64), 0, s, loss, (size_t)1);
     uint16_t *X = at<uint16_t>(T, p.t_X), *H1 = at<uint16_t>(T, p.t_H1), *H2 = at<uint16_t>(T, p.t_H2);
@@ -951,13 +972,20 @@ parem_status proposal_train_step(Proposal &p, const uint8_t *d_text, uint64_t le
                                 dX, nullptr, kMlpIn);
     hipLaunchKernelGGL(k_embed_bwd, dim3((B + kEmbRowsPerBlock - 1) / kEmbRowsPerBlock), dim3(256), 0, s, win, B, dX,
                        g + p.o_emb);
-    if (lr > 0.0f || wd > 0.0f) {
-        p.step += 1;
-        const float b1 = 0.9f, b2 = 0.999f;
-        const float bc1 = 1.0f - powf(b1, (float)p.step), bc2 = 1.0f - powf(b2, (float)p.step);
-        hipLaunchKernelGGL(k_adamw, dim3((unsigned)((p.nparams + 255) / 256)), dim3(256), 0, s, p.d_params, g, p.d_m,
-                           p.d_v, p.d_params16, p.nparams, lr, b1, b2, 1e-8f, wd, bc1, bc2);
-    }
+    if (lr > 0.0f || wd > 0.0f) return proposal_adamw(p, g, lr, wd, s);
+    return hipGetLastError() == hipSuccess ? PAREM_OK : PAREM_EDEVICE;
+}
+
+// One AdamW step on the master weights with gradient g (device, nparams).
+// The bias corrections 1 - beta^t are formed in double on the host: in fp32,
+// 1 - 0.999^t loses most of its digits for small t.
+parem_status proposal_adamw(Proposal &p, const float *g, float lr, float wd, hipStream_t s) {
+    p.step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float bc1 = (float)(1.0 - std::pow((double)b1, (double)p.step));
+    const float bc2 = (float)(1.0 - std::pow((double)b2, (double)p.step));
+    hipLaunchKernelGGL(k_adamw, dim3((unsigned)((p.nparams + 255) / 256)), dim3(256), 0, s, p.d_params, g, p.d_m,
+                       p.d_v, p.d_params16, p.nparams, lr, b1, b2, 1e-8f, wd, bc1, bc2);
     return hipGetLastError() == hipSuccess ? PAREM_OK : PAREM_EDEVICE;
 }
 
@@ -1008,15 +1036,15 @@ parem_status proposal_select(const Proposal &p, const uint8_t *d_text, uint64_t 
     return hipGetLastError() == hipSuccess ? PAREM_OK : PAREM_EDEVICE;
 }
 
-parem_status proposal_logits(const Proposal &p, const uint8_t *d_text, const uint64_t *d_pos, uint32_t B,
-                             float *d_logits, hipStream_t s) {
+parem_status proposal_logits(const Proposal &p, const uint8_t *d_text, uint64_t len, const uint64_t *d_pos,
+                             uint32_t B, float *d_logits, hipStream_t s) {
     Proposal &q = const_cast<Proposal &>(p);
     parem_status st = ensure_train(q, B);
     if (st != PAREM_OK) return st;
     const DeviceDfa &d = *p.dfa;
     void *T = q.t_buf;
     uint16_t *win = at<uint16_t>(T, q.t_win), *wcls = at<uint16_t>(T, q.t_cls);
-    hipLaunchKernelGGL(k_windows, dim3((B * kMlpWindow + 255) / 256), dim3(256), 0, s, d_text, d_pos, B, d.d_cls,
+    hipLaunchKernelGGL(k_windows, dim3((B * kMlpWindow + 255) / 256), dim3(256), 0, s, d_text, len, d_pos, B, d.d_cls,
                        d.A + 1, win, wcls);
     forward_rows(p, s, win, B, at<uint16_t>(T, q.t_X), at<float>(T, q.t_pre1), at<uint16_t>(T, q.t_H1),
                  at<float>(T, q.t_pre2), at<uint16_t>(T, q.t_H2), d_logits);
@@ -1112,10 +1140,17 @@ parem_status parem_proposal_select(parem_proposal p, const uint8_t *d_text, uint
                                   reinterpret_cast<hipStream_t>(stream), d_sel, d_nsel);
 }
 
-parem_status parem_proposal_logits(parem_proposal p, const uint8_t *d_text, const uint64_t *d_positions,
-                                   uint32_t batch, float *d_logits, void *stream) {
+parem_status parem_proposal_logits(parem_proposal p, const uint8_t *d_text, uint64_t len,
+                                   const uint64_t *d_positions, uint32_t batch, float *d_logits, void *stream) {
     if (!p || !d_text || !d_positions || !d_logits || batch == 0) return PAREM_EINVAL;
-    return parem::proposal_logits(*p, d_text, d_positions, batch, d_logits, reinterpret_cast<hipStream_t>(stream));
+    return parem::proposal_logits(*p, d_text, len, d_positions, batch, d_logits,
+                                  reinterpret_cast<hipStream_t>(stream));
+}
+
+parem_status parem_proposal_apply_grad(parem_proposal p, const float *d_grad, uint64_t nparams, float lr,
+                                       float weight_decay, void *stream) {
+    if (!p || !d_grad || nparams != p->nparams) return PAREM_EINVAL;
+    return parem::proposal_adamw(*p, d_grad, lr, weight_decay, reinterpret_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -476,3 +476,46 @@ def test_config3_full_size():
     m.close()
     want = oracle.walk_dfa(dfa, text)
     assert (got.final_state, got.accept, got.count) == (want.final_state, want.accept, want.count)
+
+
+def perm_final_closed_form(text, start, q=7):
+    """Final state of the permutation automaton delta(s, k-th symbol) =
+    (s + k + 1) mod q: the start plus the sum of (k + 1) over the text, mod q."""
+    total = 0
+    for lo in range(0, text.size, 1 << 28):
+        blk = text[lo:lo + (1 << 28)]
+        total += int(np.count_nonzero(blk == ord("a"))) + 2 * int(np.count_nonzero(blk == ord("b"))) + \
+            3 * int(np.count_nonzero(blk == ord("c")))
+    return (start + total) % q
+
+
+def test_count_beyond_32_bits():
+    """2^32 + 17 bytes with every state final: the count equals the length
+    (arithmetic; the oracle's u64 count is pinned the same way on the CPU)
+    and the final state of the permutation automaton has a closed form. Its
+    chunk maps never merge, so every composition level carries general maps
+    with u64 segment counts above 2^32."""
+    n = (1 << 32) + 17
+    q = 7
+    table = np.stack([(np.arange(q) + k + 1) % q for k in range(3)], axis=1).astype(np.uint8)
+    dfa = W.Dfa(table, b"abc", 2, np.arange(q, dtype=np.uint32))
+    rng = np.random.default_rng(2 ** 32 + 17)
+    text = W.uniform_text(rng, b"abc", n)
+    want_final = perm_final_closed_form(text, 2, q)
+    say(f"[case] count beyond 32 bits: n={n}")
+    d = torch.from_numpy(text).cuda()
+    del text
+    for opts in ({}, {"chunk_len": 32768}):
+        m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, **opts)
+        r = m.match(d)
+        assert (r.final_state, r.accept, r.count) == (want_final, True, n), (opts, r)
+        m.close()
+    # one state, one symbol: k-gram entries carry the final-step counts
+    one = W.Dfa(np.zeros((1, 1), dtype=np.uint8), b"a", 0, np.asarray([0], dtype=np.uint32))
+    d.fill_(ord("a"))
+    m = P.Matcher(one.table, one.alphabet, one.start, one.accepting)
+    r = m.match(d)
+    assert (r.final_state, r.accept, r.count) == (0, True, n), r
+    m.close()
+    del d
+    torch.cuda.empty_cache()

@@ -139,3 +139,45 @@ def test_pad_bytes_embed_as_zero_and_get_no_gradient():
     assert np.allclose(z_pad, z0)
     loss, g = mlp.loss_and_grad(flat, 7, w, mask, labels)
     assert np.all(np.isfinite(g))
+
+
+def test_rounded_operands_stay_near_the_exact_definition():
+    """The bf16-operand variant differs from the exact definition only by
+    operand rounding (each rounding moves a value by at most 2^-8 of itself);
+    its gradient stays within a few percent of the exact one in norm, and
+    every entry's scale bounds the entry (triangle inequality)."""
+    rng = np.random.default_rng(12)
+    flat, windows, mask, labels = tiny_case(rng, states=9, batch=40)
+    zs, gs = mlp.magnitudes(flat, 9, windows, mask, labels, rnd=mlp.bf16_round)
+    l0, g0 = mlp.loss_and_grad(flat, 9, windows, mask, labels)
+    l1, g1 = mlp.loss_and_grad(flat, 9, windows, mask, labels, rnd=mlp.bf16_round)
+    assert np.all(np.abs(g1) <= gs * (1 + 1e-12) + 1e-300)
+    for k in ("emb", "W1", "b1", "W2", "b2", "W3", "b3"):
+        a, b = mlp.unpack(g1, 9)[k], mlp.unpack(g0, 9)[k]
+        assert np.linalg.norm(a - b) <= 0.05 * np.linalg.norm(b), k
+    z0, _ = mlp.forward(flat, 9, windows, mask)
+    z1, _ = mlp.forward(flat, 9, windows, mask, rnd=mlp.bf16_round)
+    ok = np.isfinite(z0)
+    assert np.all(np.abs(z1)[ok] <= zs[ok] * (1 + 1e-12))
+    # the head's operand h2 carries the rounding of two layers
+    assert np.all(np.abs(z1 - z0)[ok] <= 4 * 2.0 ** -8 * zs[ok])
+    assert abs(l1 - l0) <= 0.05 * abs(l0)
+    # without a rounding function the variant is the exact definition
+    l2, g2 = mlp.loss_and_grad(flat, 9, windows, mask, labels, rnd=None)
+    assert l2 == l0 and np.array_equal(g2, g0)
+
+
+def test_scale_exposes_a_dropped_column():
+    """A planted mistake (the last embedding column's gradient dropped, or
+    the bias of one hidden unit) is far outside the comparison bound the GPU
+    gradient is held to (2^-10 of the entry's scale) for nearly every entry:
+    the scale does not hide a wrong element."""
+    rng = np.random.default_rng(13)
+    flat, windows, mask, labels = tiny_case(rng, states=9, batch=40)
+    _, gs = mlp.magnitudes(flat, 9, windows, mask, labels, rnd=mlp.bf16_round)
+    _, g = mlp.loss_and_grad(flat, 9, windows, mask, labels, rnd=mlp.bf16_round)
+    G, GS = mlp.unpack(g, 9), mlp.unpack(gs, 9)
+    used = np.unique(windows)
+    for k, sl in (("emb", (used, -1)), ("W1", (slice(None), 7)), ("W2", (3, slice(None))),
+                  ("b1", (slice(None),)), ("W3", (2, slice(None)))):
+        assert np.mean(np.abs(G[k][sl]) > 2.0 ** -10 * GS[k][sl]) > 0.9, k

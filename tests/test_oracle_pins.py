@@ -320,10 +320,49 @@ def test_edge_cases():
 
 
 def test_count_is_u64_wide():
-    """A 2^32+ count must not wrap: synthesise it from a 1-state automaton on
-    a text longer than 2^32 only where memory allows; otherwise check the
-    dtype path with a 2^20 text and the running-count API."""
+    """A count of 2^32 + 17: a one-state automaton whose state is final makes
+    every step count, so the count equals the text length by arithmetic
+    alone; the oracle must not wrap it at 32 bits."""
+    n = (1 << 32) + 17
     t = np.zeros((1, 1), dtype=np.uint32)
-    text = np.full(1 << 20, ord("a"), dtype=np.uint8)
-    st, cn = oracle.states_at(t, b"a", 0, [0], text, [0, 1 << 19, 1 << 20])
+    text = np.full(n, ord("a"), dtype=np.uint8)
+    r = oracle.walk(t, b"a", 0, [0], text)
+    assert (r.final_state, r.accept, r.count) == (0, True, n)
+    del text
+    short = np.full(1 << 20, ord("a"), dtype=np.uint8)
+    st, cn = oracle.states_at(t, b"a", 0, [0], short, [0, 1 << 19, 1 << 20])
     assert cn.dtype == np.uint64 and cn.tolist() == [0, 1 << 19, 1 << 20]
+
+
+def test_permutation_automaton_closed_form():
+    """delta(s, k-th symbol) = (s + k + 1) mod 7 never synchronises; its
+    final state is the start plus the sum of (k + 1) over the text, mod 7,
+    and with every state final the count is the length."""
+    q = 7
+    table = np.stack([(np.arange(q) + k + 1) % q for k in range(3)], axis=1).astype(np.uint32)
+    rng = np.random.default_rng(5)
+    text = W.uniform_text(rng, b"abc", 1_000_003)
+    k = np.frombuffer(b"abc", dtype=np.uint8)
+    total = sum((j + 1) * int(np.count_nonzero(text == k[j])) for j in range(3))
+    r = oracle.walk(table, b"abc", 2, np.arange(q), text)
+    assert (r.final_state, r.accept, r.count) == ((2 + total) % q, True, text.size)
+    r = oracle.walk(table, b"abc", 2, [4], text)
+    assert r.final_state == (2 + total) % q
+
+
+def test_motif_count_full_size_equals_sliding_compare():
+    """The benchmarked 1 GiB DNA text (default seed, 1e5 planted copies):
+    the oracle's count equals the sliding-window compare at the motif's 12
+    fixed positions over the whole text, taken in 64 MiB blocks that overlap
+    by the motif length minus one."""
+    dfa, text = W.config2()
+    assert text.size == 1 << 30
+    motif, wild = dfa.meta["motif"], dfa.meta["wild"]
+    m = len(motif)
+    block = 1 << 26
+    want = 0
+    for lo in range(0, text.size, block):
+        want += brute_force_motif_count(text[lo:min(text.size, lo + block + m - 1)], motif, wild)
+    assert want >= 100000 - 100
+    r = oracle.walk_dfa(dfa, text)
+    assert r.count == want
