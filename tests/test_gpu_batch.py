@@ -241,39 +241,43 @@ def test_tune_candidates_agree():
 
 
 def test_batch_uneven_4096_full_size():
-    """The 4096-pair uneven workload at full size, planned as the benchmark
-    plans it (autotuner cache, no new measurements), in one graph replay:
-    every pair's result is checked against the oracle for the shorter half of
-    the pairs (sampled) and the longest ones, and every result is valid."""
+    """The 4096-pair uneven workload at full size (25.98 GB), planned as the
+    benchmark plans it (autotuner cache, no new measurements), in one graph
+    replay: every pair's result equals the oracle's. The oracle runs in the
+    generation thread pool (its C walk releases the interpreter lock), each
+    worker keeping only the (final, accept, count) triple."""
     import concurrent.futures as cf
     import os
 
     from paper_1412_1741_amd.autotune import Autotuner
 
     specs = W.config5_specs()
-    order = np.argsort([s.text_len for s in specs])
-    sample = set(int(i) for i in order[: len(order) // 2: 8]) | set(int(i) for i in order[-3:])
-    dfas, devs, host = [], [], {}
-    say(f"[case] uneven batch: generating {len(specs)} pairs")
+
+    def make(spec):
+        dfa, text = W.config5_pair(spec)
+        want = oracle.walk_dfa(dfa, text)
+        return dfa, text, (want.final_state, want.accept, want.count)
+
+    dfas, devs, wants = [], [], []
+    say(f"[case] uneven batch: generating {len(specs)} pairs with their oracle results")
     with cf.ThreadPoolExecutor(16) as ex:
-        for i, (dfa, text) in enumerate(ex.map(W.config5_pair, specs)):
+        for i, (dfa, text, want) in enumerate(ex.map(make, specs)):
             dfas.append(dfa)
             devs.append(torch.from_numpy(text).cuda())
-            if i in sample:
-                host[i] = text
+            wants.append(want)
+            if (i + 1) % 512 == 0:
+                say(f"[case] uneven batch: {i + 1} pairs")
     cache = os.path.join(os.path.dirname(P.__file__), "tuned", "batch_mi355x.json")
     tuner = Autotuner(cache_path=cache, measure=False)
     ms, opts = tuner.plan(dfas, devs)
     b = P.Batch(ms, [d.numel() for d in devs], opts)
     say(f"[info] {b.describe()}")
     got = b.run(devs, use_graph=True)
-    say(f"[case] uneven batch: oracle on {len(host)} pairs")
-    for i, text in host.items():
-        want = oracle.walk_dfa(dfas[i], text)
-        r = got[i]
-        assert (r.final_state, r.accept, r.count) == (want.final_state, want.accept, want.count), i
+    total = sum(d.numel() for d in devs)
+    bad = [i for i, r in enumerate(got) if (r.final_state, r.accept, r.count) != wants[i]]
+    say(f"[case] uneven batch: {len(got) - len(bad)} of {len(got)} pairs ({total} bytes) equal the oracle")
+    assert not bad, bad[:10]
     for i, r in enumerate(got):
-        assert r.final_state < dfas[i].num_states, i
         assert r.chunks == 0 or r.spec_runs >= r.chunks
 
 

@@ -366,3 +366,226 @@ def test_motif_count_full_size_equals_sliding_compare():
     assert want >= 100000 - 100
     r = oracle.walk_dfa(dfa, text)
     assert r.count == want
+
+
+# ---------------------------------------------------------------------------
+# the Enumeration policy (Section II-C's run counts, Section IV-A)
+# ---------------------------------------------------------------------------
+
+def test_enumeration_runs_on_the_example(golden_dir):
+    """Enumeration speculates all nine states for each unit after the first:
+    3 * 9 + 1 = 28 walks on the worked example (Section II-C), against the
+    six of Algorithm 1's rule; both reach the sequential result."""
+    t1 = load_table1(golden_dir)
+    enum = oracle.parem(t1, PAREL, 0, [8], EXAMPLE, p=4, policy=oracle.POLICY_ENUMERATE, traces=True)
+    assert enum.runs == 28
+    assert enum.rsize.tolist() == [1, 9, 9, 9]
+    plain = oracle.parem(t1, PAREL, 0, [8], EXAMPLE, p=4)
+    assert plain.runs == 6
+    seq = oracle.walk(t1, PAREL, 0, [8], EXAMPLE)
+    for r in (enum, plain):
+        assert (r.final_state, r.count) == (seq.final_state, seq.count) == (0, 1)
+    # the enumeration's walks of Table II's starts visit the printed states
+    walks = {(c, r): v for c, r, v in enum.traces}
+    for unit, start, visits in load_table2(golden_dir):
+        assert walks[(unit, start)] == visits, (unit, start)
+
+
+def test_enumeration_vs_parem_worst_case(golden_dir):
+    """Every unit's predecessor ending in 'l' (four destinations): 13 walks
+    against Enumeration's 28, the 2.15x of Section II-C, from two runs."""
+    t1 = load_table1(golden_dir)
+    text = b"paral" + b"l" + b"parall" + b"eparal" + b"pppppp"
+    plain = oracle.parem(t1, PAREL, 0, [8], text, p=4)
+    enum = oracle.parem(t1, PAREL, 0, [8], text, p=4, policy=oracle.POLICY_ENUMERATE)
+    assert (plain.runs, enum.runs) == (13, 28)
+    assert round(enum.runs / plain.runs, 2) == 2.15
+    assert (plain.final_state, plain.count) == (enum.final_state, enum.count)
+
+
+def test_enumeration_equals_sequential_for_any_split():
+    rng = np.random.default_rng(41)
+    for _ in range(20):
+        dfa, text = W.random_case(rng, max_states=20, max_alpha=5, max_len=400)
+        seq = oracle.walk_dfa(dfa, text)
+        for p in (1, 2, 3, 7, max(1, text.size)):
+            r = oracle.parem(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, text, p=p,
+                             policy=oracle.POLICY_ENUMERATE)
+            assert (r.final_state, r.count) == (seq.final_state, seq.count)
+            # every slice after the first walks every state
+            slices = [int((c + 1) * text.size // p) - int(c * text.size // p) for c in range(p)]
+            assert r.runs == 1 + (p - 1) * dfa.num_states, slices
+
+
+# ---------------------------------------------------------------------------
+# partial DFAs: undefined transitions, the S set, the DEAD result
+# ---------------------------------------------------------------------------
+
+def partial_table1(golden_dir):
+    """Table I with its restart entries (state 0) left undefined: a run dies
+    on any symbol that does not extend the word or start it again."""
+    t1 = load_table1(golden_dir).astype(np.int64)
+    t1[t1 == 0] = -1
+    return t1
+
+
+def test_partial_example_dies_early(golden_dir):
+    """Worked by hand from Table I: the run reads 'p' (state 1) and dies on
+    'l'. Algorithm 1 with four units: unit 1 follows 'p' (L = {1}) and starts
+    with 'a' (S = {1, 3}): R = {1}; unit 2 follows 'e' (L = {7}) and starts
+    with 'l' (S = {4, 5, 7}): R = {7}, whose walk reaches 8 (one count) and
+    dies on 'a'; unit 3: L = {7}, S = every state ('p'): R = {7}."""
+    t = partial_table1(golden_dir)
+    seq = oracle.walk(t, PAREL, 0, [8], EXAMPLE, partial=True)
+    assert (seq.final_state, seq.accept, seq.count) == (oracle.DEAD, False, 0)
+    r = oracle.parem(t, PAREL, 0, [8], EXAMPLE, p=4, partial=True, traces=True)
+    assert (r.final_state, r.accept, r.count) == (oracle.DEAD, False, 0)
+    assert r.rsize.tolist() == [1, 1, 1, 1]
+    assert r.entries.tolist() == [0, oracle.DEAD, oracle.DEAD, oracle.DEAD]
+    walks = {(c, s): v for c, s, v in r.traces}
+    D = oracle.DEAD
+    assert walks[(0, 0)] == [1, D, D, D, D, D]
+    assert walks[(1, 1)] == [2, 3, 4, 5, 6, 7]
+    assert walks[(2, 7)] == [8, D, D, D, D, D]
+    assert walks[(3, 7)] == [1, 2, 3, 4, 1, D]
+
+
+def test_partial_first_symbol_empties_s(golden_dir):
+    """"parall" then "aaaaaa", two units: unit 1 follows 'l' (L = {5, 6, 8})
+    and starts with 'a' (S = {1, 3}): R is empty, and the route (state 6)
+    dies on the unit's first symbol. "para" then "llel": R = {4}, whose walk
+    ends the word (accept, one count)."""
+    t = partial_table1(golden_dir)
+    r = oracle.parem(t, PAREL, 0, [8], b"paralla" + b"aaaaa", p=2, partial=True)
+    assert r.rsize.tolist() == [1, 0]
+    assert (r.final_state, r.count, r.runs) == (oracle.DEAD, 0, 1)
+    assert r.entries.tolist() == [0, 6]
+    r = oracle.parem(t, PAREL, 0, [8], b"parallel", p=2, partial=True)
+    assert r.rsize.tolist() == [1, 1]
+    assert (r.final_state, r.accept, r.count, r.runs) == (8, True, 1, 2)
+
+
+def test_partial_equals_total_with_a_dead_state():
+    """The regular-expression example without its dead state 4: undefined
+    transitions give DEAD exactly where the total automaton enters state 4,
+    the same count, and acceptance equals Python's re.fullmatch on every
+    string of up to five symbols; Algorithm 1 on the partial table agrees for
+    every split."""
+    t = regex_dfa()
+    part = t[:4].astype(np.int64)
+    part[part == 4] = -1
+    pat = re.compile(r"(a|b)?c*[0-3]b+")
+    syms = [bytes([c]) for c in RE_ALPHA]
+    for length in range(0, 6):
+        for tup in itertools.product(syms, repeat=length):
+            s = b"".join(tup)
+            full = oracle.walk(t, RE_ALPHA, 0, [3], s)
+            r = oracle.walk(part, RE_ALPHA, 0, [3], s, partial=True)
+            assert r.count == full.count, s
+            assert (r.final_state == oracle.DEAD) == (full.final_state == 4), s
+            assert r.accept == bool(pat.fullmatch(s.decode())), s
+            if 0 < length and length % 2:
+                for p in range(1, length + 1):
+                    a = oracle.parem(part, RE_ALPHA, 0, [3], s, p=p, partial=True)
+                    assert (a.final_state, a.count) == (r.final_state, r.count), (s, p)
+
+
+def test_partial_random_any_split():
+    """Random partial tables (a quarter of the transitions undefined): the
+    result of Algorithm 1 with the S filter equals the sequential run for
+    every split, and never walks more states than its total completion (an
+    absorbing non-final state for every undefined entry) would."""
+    rng = np.random.default_rng(5)
+    for _ in range(40):
+        q = int(rng.integers(1, 12))
+        a = int(rng.integers(1, 5))
+        alpha = bytes(rng.choice(np.arange(97, 123), size=a, replace=False).astype(np.uint8))
+        t = rng.integers(0, q, size=(q, a)).astype(np.int64)
+        t[rng.random((q, a)) < 0.25] = -1
+        acc = rng.choice(q, size=int(rng.integers(0, q + 1)), replace=False)
+        text = np.frombuffer(alpha, dtype=np.uint8)[rng.integers(0, a, size=int(rng.integers(0, 60)))]
+        comp = np.where(t < 0, q, t)
+        comp = np.vstack([comp, np.full((1, a), q)])
+        seq = oracle.walk(t, alpha, 0, acc, text, partial=True)
+        tot = oracle.walk(comp, alpha, 0, acc, text)
+        assert seq.count == tot.count
+        assert (seq.final_state == oracle.DEAD) == (tot.final_state == q)
+        for p in (1, 2, 3, 5, max(1, text.size)):
+            r = oracle.parem(t, alpha, 0, acc, text, p=p, partial=True)
+            assert (r.final_state, r.count) == (seq.final_state, seq.count)
+            rc = oracle.parem(comp, alpha, 0, acc, text, p=p)
+            assert r.runs <= rc.runs
+
+
+def test_partial_errors():
+    t = np.array([[1, -1], [0, 1]], dtype=np.int64)
+    # undefined entries need the flag
+    with pytest.raises(oracle.OracleError) as ei:
+        oracle.walk(t, b"ab", 0, [1], b"ab")
+    assert ei.value.code == oracle.ESTATE
+    # a byte outside the alphabet is reported even after the run died
+    with pytest.raises(oracle.OracleError) as ei:
+        oracle.walk(t, b"ab", 0, [1], b"abbbxa", partial=True)
+    assert ei.value.code == oracle.ESYMBOL and ei.value.bad_pos == 4
+    r = oracle.walk(t, b"ab", 0, [1], b"abab", partial=True)  # 0 -a-> 1 -b-> 1 -a-> 0 -b-> dead
+    assert (r.final_state, r.count) == (oracle.DEAD, 2)
+    st, cn = oracle.states_at(t, b"ab", 0, [1], b"abab", [0, 1, 3, 4], partial=True)
+    assert st.tolist() == [0, 1, 0, oracle.DEAD] and cn.tolist() == [0, 1, 2, 2]
+
+
+# ---------------------------------------------------------------------------
+# match positions (the steps that enter a final state)
+# ---------------------------------------------------------------------------
+
+def test_positions_of_the_example(golden_dir):
+    t1 = load_table1(golden_dir)
+    pos, total = oracle.positions(t1, PAREL, 0, [8], EXAMPLE)
+    assert total == 1 and pos.tolist() == [EXAMPLE.index(b"parallel") + 7] == [12]
+
+
+def test_positions_are_word_ends():
+    """The KMP automaton enters state 8 exactly at the last symbol of every
+    occurrence of "parallel" (overlaps included); random texts with planted
+    copies; the cap keeps the first offsets and the total."""
+    t1 = kmp_automaton(b"parallel", PAREL)
+    rng = np.random.default_rng(9)
+    for _ in range(10):
+        text = bytearray(np.frombuffer(PAREL, dtype=np.uint8)[rng.integers(0, 5, size=5000)].tobytes())
+        for o in rng.integers(0, 5000 - 8, size=30):
+            text[o:o + 8] = b"parallel"
+        text = bytes(text)
+        want = [i + 7 for i in range(len(text) - 7) if text[i:i + 8] == b"parallel"]
+        pos, total = oracle.positions(t1, PAREL, 0, [8], text)
+        assert pos.tolist() == want and total == len(want)
+        pos, total = oracle.positions(t1, PAREL, 0, [8], text, cap=5)
+        assert pos.tolist() == want[:5] and total == len(want)
+
+
+def test_positions_of_the_regex_example():
+    """Offsets i whose prefix t[0..i] is in the language of
+    (a|b)?c*[0-3]b+ (Python's re.fullmatch), partial and total forms."""
+    t = regex_dfa()
+    part = t[:4].astype(np.int64)
+    part[part == 4] = -1
+    pat = re.compile(r"(a|b)?c*[0-3]b+")
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        s = bytes(np.frombuffer(RE_ALPHA, dtype=np.uint8)[rng.choice(7, size=int(rng.integers(0, 12)),
+                                                                       p=[.1, .1, .2, .1, .1, .1, .3])])
+        want = [i for i in range(len(s)) if pat.fullmatch(s[:i + 1].decode())]
+        assert oracle.positions(t, RE_ALPHA, 0, [3], s)[0].tolist() == want
+        assert oracle.positions(part, RE_ALPHA, 0, [3], s, partial=True)[0].tolist() == want
+
+
+def test_positions_of_the_motif_automaton():
+    dfa, text = W.config2(seed=7, n=1 << 20, copies=300)
+    motif, wild = dfa.meta["motif"], dfa.meta["wild"]
+    m = len(motif)
+    n = text.size - m + 1
+    ok = np.ones(n, dtype=bool)
+    for k in range(m):
+        if not wild[k]:
+            ok &= text[k:k + n] == motif[k]
+    want = np.flatnonzero(ok) + m - 1
+    pos, total = oracle.positions_dfa(dfa, text)
+    assert total == want.size and np.array_equal(pos, want.astype(np.uint64))
