@@ -65,11 +65,27 @@ enum {
                                     such a handle's byte table through L2. */
 };
 
+/* Speculation policy (parem_options.policy). */
+enum {
+    PAREM_POLICY_PAREM = 0,     /* chunk c is walked from R_c = S intersect L
+                                   (Algorithm 1, Section II-B)                 */
+    PAREM_POLICY_ENUMERATE = 1  /* every state for every chunk after the first:
+                                   the Enumeration approach the paper compares
+                                   against (Section II-C counts its runs,
+                                   Section IV-A measures it). Total tables
+                                   only; not with lookback.                   */
+};
+
+/* Final state of a run that met an undefined transition of a partial table
+ * (parem_options.partial), and of a text with a byte outside the alphabet. */
+#define PAREM_DEAD_STATE 0xFFFFFFFEu
+#define PAREM_INVALID_STATE 0xFFFFFFFFu
+
 typedef struct {
     uint32_t chunk_len;   /* bytes per chunk, multiple of 64; 0 = automatic     */
     uint32_t layout;      /* PAREM_LAYOUT_*; AUTO lets the compile step choose  */
     uint32_t group;       /* speculated states walked in lockstep per lane; 0 = auto */
-    uint32_t kgram;       /* reserved for the k-gram step width; must be 0       */
+    uint32_t policy;      /* PAREM_POLICY_*                                      */
     uint32_t tile;        /* bytes of each chunk staged per load round: 64 or 128; 0 = auto */
     uint32_t no_merge;    /* 1: every speculated run walks its whole chunk, as the
                              paper's Algorithm 1 does; 0 (default): runs that
@@ -81,12 +97,27 @@ typedef struct {
                              offset), a subset of R_c that still holds the true
                              entry state, so results are identical; chunks
                              whose image has more than 64 states use R_c. At
-                             most 4096; ignored when Q >= 16384.              */
-    uint32_t reserved;    /* must be zero                                        */
+                             most 4096; ignored when Q >= 16384. Not with
+                             partial tables or the Enumeration policy.       */
+    uint32_t partial;     /* 1: the table is a partial DFA (Section II-B): an
+                             entry equal to the all-ones value of its width
+                             (0xFF, 0xFFFF, 0xFFFFFFFF) is an undefined
+                             transition. A run that meets one dies: the match
+                             reports final_state PAREM_DEAD_STATE, accept 0,
+                             and the count of final destinations before it.
+                             Chunk c is then walked only from S intersect L:
+                             the states of L (destinations on the byte before
+                             the chunk) that have a transition on the chunk's
+                             first byte. Needs num_states <= 16381; not with
+                             lookback, the Enumeration policy, proposals or
+                             batches. 0: every entry must be a state.        */
 } parem_options;
 
 typedef struct {
-    uint32_t final_state;  /* state after the last byte (start state if len == 0) */
+    uint32_t final_state;  /* state after the last byte (start state if len == 0);
+                              PAREM_DEAD_STATE after an undefined transition,
+                              PAREM_INVALID_STATE after a byte outside the
+                              alphabet (async calls)                           */
     uint32_t accept;       /* 1 iff final_state is final                           */
     uint64_t count;        /* number of steps whose destination state is final    */
     uint64_t chunks;       /* chunks the text was split into                       */
@@ -100,7 +131,8 @@ typedef struct {
  *  table        host, row-major [num_states][alphabet_size]; entry (q, j) is
  *               delta(q, alphabet[j]); entry_bytes is 1, 2 or 4 (unsigned).
  *               Every entry must be < num_states (else PAREM_ESTATE): the
- *               table must be total (the S set of Algorithm 1 is then Q).
+ *               table is total (the S set of Algorithm 1 is then Q), unless
+ *               opt->partial allows undefined entries (all-ones values).
  *  alphabet     host, alphabet_size distinct byte values (1..256); column j
  *               of the table is the byte alphabet[j]. Bytes not listed are
  *               invalid in texts (PAREM_ESYMBOL at match time).
@@ -183,6 +215,34 @@ parem_status parem_boundary_workspace_size(parem_handle h, uint64_t len, uint32_
 parem_status parem_boundary_states(parem_handle h, const uint8_t *d_text, uint64_t len, uint32_t chunk_len,
                                    uint32_t *d_states, void *d_workspace, uint64_t workspace_bytes,
                                    void *stream);
+
+/*
+ * Match positions: the offset (0-based) of every byte whose step enters a
+ * final state, ascending - the steps the count counts (Algorithm 1's `found`
+ * tally along the connected route; for a search automaton such as Sigma*.P,
+ * the last byte of every occurrence). After the walk and composition of a
+ * plain match, a down-sweep hands every chunk its true entry state (chunk c
+ * is entered in chunk c-1's exit, Section II-B); the chunk's count on that
+ * route comes from its map, an exclusive scan of the counts gives each
+ * chunk's first output slot, and each chunk with matches is walked once more
+ * from its entry state alone, writing its offsets.
+ *  d_positions  device, cap u64 slots; the first min(cap, count) offsets are
+ *               written (cap may be 0: count only; d_positions may then be
+ *               NULL).
+ *  d_out        device parem_result of the match (count = number of
+ *               positions). After a byte outside the alphabet the result is
+ *               invalid (final_state PAREM_INVALID_STATE) and the positions
+ *               are unspecified; a partial table's run that died has no
+ *               positions after its death.
+ *  d_workspace  device, parem_positions_workspace_size bytes; owned by the
+ *               call until the stream reaches its end.
+ * Chunks of the handle's chunk_len, or (0) about len / 2^19 bytes (256 to
+ * 4096), so that the second walk, one lane per chunk, stays short.
+ */
+parem_status parem_positions_workspace_size(parem_handle h, uint64_t len, uint64_t *bytes);
+parem_status parem_match_positions_async(parem_handle h, const uint8_t *d_text, uint64_t len, uint64_t *d_positions,
+                                         uint64_t cap, void *d_workspace, uint64_t workspace_bytes, void *stream,
+                                         parem_result *d_out);
 
 /*
  * Learned speculation proposal (not in the paper). A small network scores

@@ -35,8 +35,12 @@ LAYOUT_HOT_LDS = 4
 LAYOUT_CLASS_LDS = 5
 LAYOUT_SPARSE_LDS = 6
 
+POLICY_PAREM = 0
+POLICY_ENUMERATE = 1
+
 RESULT_BYTES = 40
 INVALID_STATE = 0xFFFFFFFF
+DEAD_STATE = 0xFFFFFFFE
 
 
 class ParemError(RuntimeError):
@@ -47,8 +51,8 @@ class ParemError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("chunk_len", ctypes.c_uint32), ("layout", ctypes.c_uint32), ("group", ctypes.c_uint32),
-                ("kgram", ctypes.c_uint32), ("tile", ctypes.c_uint32), ("no_merge", ctypes.c_uint32),
-                ("lookback", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("policy", ctypes.c_uint32), ("tile", ctypes.c_uint32), ("no_merge", ctypes.c_uint32),
+                ("lookback", ctypes.c_uint32), ("partial", ctypes.c_uint32)]
 
 
 class Result(ctypes.Structure):
@@ -92,6 +96,10 @@ def _load() -> ctypes.CDLL:
     lib.parem_boundary_workspace_size.argtypes = [vp, u64, u32, ctypes.POINTER(u64)]
     lib.parem_boundary_states.restype = i32
     lib.parem_boundary_states.argtypes = [vp, vp, u64, u32, vp, vp, u64, vp]
+    lib.parem_positions_workspace_size.restype = i32
+    lib.parem_positions_workspace_size.argtypes = [vp, u64, ctypes.POINTER(u64)]
+    lib.parem_match_positions_async.restype = i32
+    lib.parem_match_positions_async.argtypes = [vp, vp, u64, vp, u64, vp, u64, vp, vp]
     lib.parem_proposal_create.restype = i32
     lib.parem_proposal_create.argtypes = [vp, vp, u64, ctypes.POINTER(vp)]
     lib.parem_proposal_free.restype = None
@@ -132,7 +140,8 @@ _lib = None
 # every symbol the header declares, for the export check
 EXPORTED = ["parem_compile", "parem_free", "parem_strerror", "parem_describe", "parem_workspace_size",
             "parem_match_async", "parem_match_async_timed", "parem_match", "parem_boundary_workspace_size",
-            "parem_boundary_states", "parem_proposal_create", "parem_proposal_free", "parem_proposal_params",
+            "parem_boundary_states", "parem_positions_workspace_size", "parem_match_positions_async",
+            "parem_proposal_create", "parem_proposal_free", "parem_proposal_params",
             "parem_proposal_train_step", "parem_proposal_logits", "parem_proposal_apply_grad",
             "parem_proposal_select_size",
             "parem_proposal_select", "parem_learned_workspace_size",
@@ -162,16 +171,21 @@ def _check(status: int, where: str):
 
 
 def parem_compile(table, alphabet, start: int, accepting, *, chunk_len: int = 0, layout: int = 0,
-                  group: int = 0, tile: int = 0, no_merge: bool = False, lookback: int = 0) -> int:
-    """Compile a total DFA; returns the handle (an integer address)."""
+                  group: int = 0, tile: int = 0, no_merge: bool = False, lookback: int = 0,
+                  policy: int = POLICY_PAREM, partial: bool = False) -> int:
+    """Compile a DFA; returns the handle (an integer address). With
+    ``partial`` the all-ones value of the table's unsigned type marks an
+    undefined transition (a signed table's -1 is converted to it)."""
     t = np.ascontiguousarray(table)
     if t.ndim != 2:
         raise ValueError("table must be 2-D [num_states, alphabet_size]")
     if t.dtype not in (np.uint8, np.uint16, np.uint32):
+        if partial and t.dtype.kind == "i":
+            t = np.where(t < 0, 0xFFFFFFFF, t)
         t = np.ascontiguousarray(t, dtype=np.uint32)
     alpha = np.frombuffer(bytes(alphabet), dtype=np.uint8).copy()
     acc = np.ascontiguousarray(np.asarray(accepting, dtype=np.uint32).reshape(-1))
-    opt = Options(chunk_len, layout, group, 0, tile, 1 if no_merge else 0, lookback)
+    opt = Options(chunk_len, layout, group, policy, tile, 1 if no_merge else 0, lookback, 1 if partial else 0)
     h = ctypes.c_void_p()
     st = lib().parem_compile(t.ctypes.data, t.dtype.itemsize, t.shape[0], alpha.ctypes.data, alpha.size,
                             int(start), acc.ctypes.data if acc.size else None, acc.size, ctypes.byref(opt),
@@ -225,6 +239,20 @@ def parem_boundary_states(handle: int, d_text_ptr: int, length: int, chunk_len: 
     _check(lib().parem_boundary_states(handle, d_text_ptr or None, int(length), int(chunk_len), d_states_ptr or None,
                                        d_workspace_ptr or None, int(workspace_bytes), stream_ptr or None),
            "parem_boundary_states")
+
+
+def parem_positions_workspace_size(handle: int, length: int) -> int:
+    n = ctypes.c_uint64()
+    _check(lib().parem_positions_workspace_size(handle, int(length), ctypes.byref(n)),
+           "parem_positions_workspace_size")
+    return n.value
+
+
+def parem_match_positions_async(handle: int, d_text_ptr: int, length: int, d_pos_ptr: int, cap: int,
+                                d_workspace_ptr: int, workspace_bytes: int, stream_ptr: int, d_out_ptr: int) -> None:
+    _check(lib().parem_match_positions_async(handle, d_text_ptr or None, int(length), d_pos_ptr or None, int(cap),
+                                             d_workspace_ptr or None, int(workspace_bytes), stream_ptr or None,
+                                             d_out_ptr), "parem_match_positions_async")
 
 
 def parem_proposal_create(handle: int, params: np.ndarray) -> int:
@@ -480,6 +508,26 @@ class Matcher:
         parem_match_async(self.handle, text.data_ptr(), text.numel(), ws.data_ptr(), ws.numel(), s.cuda_stream,
                           out.data_ptr())
         return out
+
+    def positions(self, text, cap: int | None = None):
+        """Offsets of the bytes whose step enters a final state (uint64
+        device tensor, ascending) and the match result. With cap None a plain
+        match first sizes the output to the count."""
+        import torch
+        assert text.is_cuda and text.dtype == torch.uint8 and text.is_contiguous()
+        if cap is None:
+            cap = self.match(text).count
+        s = torch.cuda.current_stream()
+        ws = torch.empty(max(parem_positions_workspace_size(self.handle, text.numel()), 256), dtype=torch.uint8,
+                         device=text.device)
+        pos = torch.empty(max(int(cap), 1), dtype=torch.int64, device=text.device)
+        out = torch.empty(RESULT_BYTES, dtype=torch.uint8, device=text.device)
+        parem_match_positions_async(self.handle, text.data_ptr(), text.numel(), pos.data_ptr(), int(cap),
+                                    ws.data_ptr(), ws.numel(), s.cuda_stream, out.data_ptr())
+        res = MatchResult.from_bytes(out.cpu().numpy().tobytes())
+        if res.final_state == INVALID_STATE:
+            raise ParemError(PAREM_ESYMBOL, "parem_match_positions_async")
+        return pos[:min(int(cap), res.count)], res
 
     def match(self, text) -> MatchResult:
         try:

@@ -37,6 +37,7 @@ SOURCES = [
     "parem_walk_sparse_sel.hip",
     "parem_walk_sparse_redo.hip",
     "parem_mlp.hip",
+    "parem_positions.hip",
     "parem_batch.hip",
     "parem_batch_t64.hip",
     "parem_batch_t128.hip",

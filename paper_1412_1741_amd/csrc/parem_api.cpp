@@ -39,6 +39,8 @@ void release(DeviceDfa &d) {
     hipFree(d.d_next);
     hipFree(d.d_step);
     hipFree(d.d_bytes);
+    hipFree(d.d_coltab);
+    d.d_coltab = nullptr;
     d.d_next = nullptr;
     d.d_step = nullptr;
     d.d_bytes = nullptr;
@@ -293,23 +295,32 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
     parem_options o{};
     if (opt) {
         o = *opt;
-        if (o.reserved) return PAREM_EINVAL;
+        if (o.partial > 1) return PAREM_EINVAL;
         if (o.lookback > parem::kLookMax) return PAREM_EINVAL;
         if (o.chunk_len % 64 || o.chunk_len > parem::kMaxChunk) return PAREM_EINVAL;
         if (o.group && o.group != 2 && o.group != 4 && o.group != 8 && o.group != 16) return PAREM_EINVAL;
         if (o.layout > PAREM_LAYOUT_SPARSE_LDS) return PAREM_EINVAL;
         if (o.tile && o.tile != 64 && o.tile != 128) return PAREM_EINVAL;
-        if (o.kgram) return PAREM_EINVAL;
+        if (o.policy > PAREM_POLICY_ENUMERATE) return PAREM_EINVAL;
         if (o.no_merge > 1) return PAREM_EINVAL;
+        // lookback sets shrink the speculated sets by another rule; the
+        // Enumeration policy walks every state of total tables only
+        if ((o.partial || o.policy == PAREM_POLICY_ENUMERATE) && o.lookback) return PAREM_EINVAL;
+        if (o.partial && o.policy == PAREM_POLICY_ENUMERATE) return PAREM_EINVAL;
     }
+    // a partial table gains one state (dead); the S filter reads the
+    // next-state table, which holds Q + 1 <= kLookStates states
+    if (o.partial && num_states + 2 > parem::kLookStates) return PAREM_EUNSUPPORTED;
 
     parem_dfa *h = new (std::nothrow) parem_dfa();
     if (!h) return PAREM_ENOMEM;
     DeviceDfa &d = h->dev;
-    d.Q = num_states;
+    d.user_Q = num_states;
+    d.Q = o.partial ? num_states + 1 : num_states;
+    d.dead = o.partial ? num_states : 0xffffffffu;
     d.A = alphabet_size;
     d.start = start;
-    d.sent = num_states;
+    d.sent = d.Q;
     d.opt = o;
     d.num_classes = d.A + 2;
 
@@ -326,33 +337,46 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
     for (uint32_t x = 0; x < 256; ++x) d.cls[x] = (uint8_t)std::min<uint32_t>(d.A, 255);
     for (uint32_t j = 0; j < d.A; ++j) d.cls[alphabet[j]] = (uint8_t)j;
 
+    // the table (for a partial one: undefined entries -> dead, and the dead
+    // row, which stays dead)
+    const uint32_t undef = entry_bytes == 1 ? 0xffu : (entry_bytes == 2 ? 0xffffu : 0xffffffffu);
     std::vector<uint32_t> t((size_t)d.Q * d.A);
-    for (uint64_t k = 0; k < (uint64_t)d.Q * d.A; ++k) {
+    for (uint64_t k = 0; k < (uint64_t)d.user_Q * d.A; ++k) {
         t[k] = read_entry(table, entry_bytes, k);
-        if (t[k] >= d.Q) {
+        if (o.partial && t[k] == undef) t[k] = d.dead;
+        else if (t[k] >= d.user_Q) {
             delete h;
             return PAREM_ESTATE;
         }
     }
+    if (o.partial)
+        for (uint32_t a = 0; a < d.A; ++a) t[(size_t)d.dead * d.A + a] = d.dead;
     d.final_flag.assign(d.Q + 1, 0);
     for (uint32_t i = 0; i < num_accepting; ++i) {
-        if (accepting[i] >= d.Q) {
+        if (accepting[i] >= d.user_Q) {
             delete h;
             return PAREM_ESTATE;
         }
         d.final_flag[accepting[i]] = 1;
     }
 
-    // speculated set per class: image of the column (L of Algorithm 1), the
-    // sentinel after an invalid byte, and {q0} for the first chunk
+    // speculated set per class: image of the column (L of Algorithm 1; for a
+    // partial table completed with dead, which the S filter leaves out of the
+    // walks), every state under the Enumeration
+    // policy, the sentinel after an invalid byte, and {q0} for the first chunk
     d.loff.assign(d.num_classes + 1, 0);
     d.llist.clear();
     std::vector<uint8_t> mark(d.Q + 1);
     for (uint32_t c = 0; c < d.num_classes; ++c) {
         d.loff[c] = (uint32_t)d.llist.size();
-        if (c < d.A) {
+        if (c < d.A && o.policy == PAREM_POLICY_ENUMERATE) {
+            for (uint32_t q = 0; q < d.Q; ++q) d.llist.push_back(q);
+        } else if (c < d.A) {
             std::fill(mark.begin(), mark.end(), 0);
             for (uint32_t q = 0; q < d.Q; ++q) mark[t[(size_t)q * d.A + c]] = 1;
+            // the run may have died anywhere before: dead is a possible entry
+            // of every chunk (its map entry is known, it is never walked)
+            if (o.partial) mark[d.dead] = 1;
             for (uint32_t q = 0; q <= d.Q; ++q)
                 if (mark[q]) d.llist.push_back(q);
         } else if (c == d.A) {
@@ -492,16 +516,18 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
                 nx[(size_t)q * d.A + a] = (uint16_t)(q < d.Q ? t[(size_t)q * d.A + a] : d.sent);
         st = upload(nx, &d.d_next);
     }
-    if (st == PAREM_OK && (uint64_t)(d.Q + 1) * (d.A + 1) <= parem::kSplitTable) {
-        // next state by class with the invalid class A, final flag in bit 15
-        // (the sub-chunk re-walk of learned speculation stages it in LDS)
+    if (st == PAREM_OK) {
+        // next state by class with the invalid class A, final flag in bit 15:
+        // match positions walk it; the sub-chunk re-walk of learned
+        // speculation stages it in LDS when it is small
         std::vector<uint16_t> sx((size_t)(d.Q + 1) * (d.A + 1));
         for (uint32_t q = 0; q <= d.Q; ++q)
             for (uint32_t a = 0; a <= d.A; ++a) {
                 const uint32_t e = (q < d.Q && a < d.A) ? t[(size_t)q * d.A + a] : d.sent;
                 sx[(size_t)q * (d.A + 1) + a] = (uint16_t)(e | (e < d.Q && d.final_flag[e] ? 0x8000u : 0u));
             }
-        st = upload(sx, &d.d_step);
+        st = upload(sx, &d.d_coltab);
+        if (st == PAREM_OK && sx.size() <= parem::kSplitTable) st = upload(sx, &d.d_step);
     }
     // inverse index of the class lists (composition looks up the position of
     // an end state in the next chunk's list); skipped when it would be huge

@@ -217,7 +217,11 @@ static parem_status batch_plan(const parem_handle *dfas, const uint64_t *lens, u
         if (d.device != b->device) return PAREM_EINVAL;
         b->dfas[i] = &d;
         parem_options o = opts ? opts[i] : d.opt;
-        if (o.kgram != 0 || o.reserved || o.lookback > kLookMax) return PAREM_EINVAL;
+        if (o.lookback > kLookMax) return PAREM_EINVAL;
+        // the speculated sets (policy, partial table) are the handle's; per-pair
+        // options may only repeat them
+        if ((o.policy && o.policy != d.opt.policy) || (o.partial && o.partial != d.opt.partial)) return PAREM_EINVAL;
+        if (d.dead != 0xffffffffu) return PAREM_EUNSUPPORTED;  // partial tables: single-text matches only
         if (o.chunk_len == 0) o.chunk_len = batch_chunk_len(lens[i]);
         PlainPlan &p = b->plans[i];
         const Proposal *pr = props ? props[i] : nullptr;

@@ -579,6 +579,9 @@ struct WalkArgs {
     const uint8_t *nsel;  // [nchunks] number of selected positions (0: the whole set)
     uint32_t sel_stride;
     const uint8_t *redo;  // re-walk mode: only chunks with redo[c] != 0, from the whole set
+    uint32_t absent_fill; // selection: map entry of a state not walked (kAbsent16, or for
+                          // the S filter of a partial table dead | 0 << 16: such a
+                          // state has no transition on the chunk's first byte)
 };
 
 enum WalkMode : int { WALK_ALL = 0, WALK_SELECTED = 1, WALK_REDO = 2 };
@@ -635,9 +638,9 @@ __device__ __forceinline__ void walk_chunk(const ST &st, const WalkArgs &a, uint
     const uint8_t *p = a.text + b;
     uint32_t *out = a.map + c;
     if constexpr (MODE == WALK_SELECTED) {
-        // entries not walked are marked absent
+        // entries not walked are marked absent (or given their known end)
         if (pos.sel)
-            for (uint32_t j = 0; j < nlist; ++j) out[(uint64_t)j * a.nchunks] = kAbsent16;
+            for (uint32_t j = 0; j < nlist; ++j) out[(uint64_t)j * a.nchunks] = a.absent_fill;
     }
     walk_direct<G, ST, ALIGNED>(st, w, p, ntiles * TILE, len, true, bad);
     bool nonuni = store_pass<G>(st, w, pos, 1, nwalk, true, lead_end, lead_cnt, out, a.nchunks);
@@ -666,6 +669,11 @@ __device__ __forceinline__ void walk_chunk(const ST &st, const WalkArgs &a, uint
             walk_direct<G, ST, ALIGNED>(st, w, p, at, len, false, bad);
             nonuni |= store_pass<G>(st, w, pos, first, nwalk, false, lead_end, lead_cnt, out, a.nchunks);
         }
+    }
+    if constexpr (MODE == WALK_SELECTED) {
+        // entries filled with a known end other than the leader's make the
+        // map non-uniform (the S filter of a partial table)
+        if (pos.sel && nwalk < nlist && a.absent_fill != kAbsent16 && a.absent_fill != lead_end) nonuni = true;
     }
     if (bad) {
         // a byte outside the alphabet: every walk of this chunk ends in the sentinel
@@ -1324,6 +1332,7 @@ inline WalkArgs walk_args(const DeviceDfa &d, const PlainPlan &p, const uint8_t 
     a.map = reinterpret_cast<uint32_t *>(ws + p.off_map);
     a.map_cls = reinterpret_cast<uint16_t *>(ws + p.off_mcls);
     a.map_lead = reinterpret_cast<uint16_t *>(ws + p.off_mlead);
+    a.absent_fill = kAbsent16;
     return a;
 }
 

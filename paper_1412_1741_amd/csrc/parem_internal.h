@@ -32,6 +32,11 @@ struct KgParams {
 struct DeviceDfa {
     uint32_t Q = 0, A = 0, start = 0;
     uint32_t sent = 0;           // absorbing sentinel state (= Q) entered on an invalid byte
+    // partial tables: the caller's Q states plus one absorbing, non-final
+    // state `dead` (= the caller's Q) standing for every undefined transition;
+    // Q counts it. 0xffffffff for total tables.
+    uint32_t dead = 0xffffffffu;
+    uint32_t user_Q = 0;         // states of the caller's table
     uint32_t num_classes = 0;    // A + 2
     uint32_t max_spec = 0;       // largest list size over all classes
     uint32_t total_list = 0;     // sum of list sizes
@@ -69,6 +74,7 @@ struct DeviceDfa {
     uint16_t *d_enc = nullptr;       // [Q+1] encoded id of each state (slot when hot, 0x4000 | id else)
     uint16_t *d_step = nullptr;      // [(Q+1) x (A+1)] next state by class | final << 15 (small tables only)
     uint16_t *d_bytes = nullptr;     // sparse-row layout: the (Q+1) x 256 u16 byte table for batch walks
+    uint16_t *d_coltab = nullptr;    // [(Q+1) x (A+1)] next state by column | final << 15 (match positions)
     uint32_t hot_rows = 0;
 };
 
@@ -131,6 +137,7 @@ struct PlainPlan {
     uint32_t merge = 1;      // 0: speculated runs are never merged
     uint32_t m = 0;          // learned: states walked per chunk
     uint32_t look = 0;       // lookback bytes (0: the speculated sets of Algorithm 1)
+    bool sfilter = false;    // partial table: walk only S intersect L (selection per chunk)
     bool keep = false;       // keep every composition level (down-sweep)
     std::vector<uint64_t> levels;  // maps after each composition level
     struct Seg {
@@ -164,6 +171,8 @@ parem_status launch_plain(const DeviceDfa &d, const PlainPlan &p, const uint8_t 
 parem_status plan_boundary(const DeviceDfa &d, uint64_t len, uint32_t L, PlainPlan *p);
 parem_status launch_boundary(const DeviceDfa &d, const PlainPlan &p, const uint8_t *d_text, uint32_t *d_states,
                              void *d_ws, hipStream_t stream);
+parem_status launch_boundary_into(const DeviceDfa &d, const PlainPlan &p, const uint8_t *d_text, uint32_t *d_states,
+                                  uint8_t *ws, hipStream_t stream, parem_result *d_out);
 parem_status plan_learned(const DeviceDfa &d, const Proposal &pr, uint64_t len, uint32_t m, const parem_options &o,
                           PlainPlan *p);
 parem_status launch_learned(const DeviceDfa &d, const Proposal &pr, const PlainPlan &p, const uint8_t *d_text,

@@ -1060,6 +1060,7 @@ extern "C" {
 parem_status parem_proposal_create(parem_handle h, const float *params, uint64_t nparams, parem_proposal *out) {
     if (!h || !out || !params) return PAREM_EINVAL;
     *out = nullptr;
+    if (h->dev.dead != 0xffffffffu) return PAREM_EUNSUPPORTED;  // no proposals for partial tables
     parem_proposal_s *p = new (std::nothrow) parem_proposal_s();
     if (!p) return PAREM_ENOMEM;
     p->dfa = &h->dev;

@@ -422,6 +422,68 @@ __global__ void k_look_stats(const uint8_t *__restrict__ nsel, const uint16_t *_
     if (threadIdx.x == 0) atomicAdd(&acc[0], part[0] + part[1] + part[2] + part[3]);
 }
 
+// S filter of a partial table (Algorithm 1's R = S intersect L): for chunk
+// c >= 1 the positions, in the list of the class of the byte before it (L,
+// completed with `dead`), of the states other than dead that have a
+// transition on the chunk's first byte. At most kLookCap are selected (more: nsel 0, the whole list is
+// walked, states outside S die on the first byte); none: position 0 is
+// walked (it dies at once, or is dead), so the map still has a leader. The
+// walks of S intersect L (1 for chunk 0) are tallied in acc[0].
+__global__ void k_sfilter(const uint8_t *__restrict__ text, uint64_t n, uint32_t L, uint64_t C,
+                          const uint8_t *__restrict__ cls, uint32_t A, const uint32_t *__restrict__ loff,
+                          const uint32_t *__restrict__ llist, const uint16_t *__restrict__ next, uint32_t dead,
+                          uint16_t *__restrict__ sel, uint8_t *__restrict__ nsel,
+                          unsigned long long *__restrict__ acc) {
+    const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long runs = 0;
+    if (c < C) {
+        if (c == 0) {
+            nsel[0] = 0;
+            runs = 1;
+        } else {
+            const uint64_t b = c * (uint64_t)L;
+            const uint32_t pc = cls[text[b - 1]], x = cls[text[b]];
+            if (pc >= A || x >= A) {
+                nsel[c] = 0;  // a byte outside the alphabet: the walk reports it
+            } else {
+                const uint32_t lo = loff[pc], sz = loff[pc + 1] - lo;
+                uint16_t *s = sel + c * kLookCap;
+                uint32_t k = 0;
+                for (uint32_t j = 0; j < sz; ++j) {
+                    const uint32_t r = llist[lo + j];
+                    if (r != dead && next[r * A + x] != dead) {
+                        if (k < kLookCap) s[k] = (uint16_t)j;
+                        ++k;
+                    }
+                }
+                runs = k;
+                if (k == 0) s[0] = 0;
+                nsel[c] = k > kLookCap ? 0 : (uint8_t)max(k, 1u);
+            }
+        }
+    }
+    (void)n;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) runs += (unsigned long long)__shfl_xor((long long)runs, o, 64);
+    __shared__ unsigned long long part[4];
+    if ((threadIdx.x & 63u) == 0) part[threadIdx.x >> 6] = runs;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(&acc[0], part[0] + part[1] + part[2] + part[3]);
+}
+
+// the internal dead state of a partial table reads PAREM_DEAD_STATE outside
+__global__ void k_dead_result(parem_result *__restrict__ r, uint32_t dead) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && r->final_state == dead) {
+        r->final_state = PAREM_DEAD_STATE;
+        r->accept = 0;
+    }
+}
+
+__global__ void k_dead_states(uint32_t *__restrict__ states, uint64_t C, uint32_t dead) {
+    const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < C && states[c] == dead) states[c] = PAREM_DEAD_STATE;
+}
+
 __global__ __launch_bounds__(256) void k_lookback(LookArgs a, uint32_t start, uint32_t wave_bytes) {
     extern __shared__ __align__(16) uint8_t smem[];
     const uint64_t c = (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6);
@@ -529,6 +591,7 @@ parem_status plan_chunks(const DeviceDfa &d, uint64_t len, const parem_options &
     q.L = L;
     q.chunks = (len + L - 1) / L;
     q.look = (o.lookback && d.d_next && d.d_inv) ? o.lookback : 0u;
+    q.sfilter = d.dead != 0xffffffffu;
     q.tile = o.tile ? o.tile : 128;
     q.merge = o.no_merge ? 0u : 1u;
     if (q.tile != 64 && q.tile != 128) return PAREM_EINVAL;
@@ -554,8 +617,8 @@ parem_status plan_chunks(const DeviceDfa &d, uint64_t len, const parem_options &
     q.off_map = take(ch * q.RM * 4);  // packed chunk maps
     q.off_mcls = take(ch * 2);
     q.off_mlead = take(ch * 2);
-    if (q.look) {
-        q.off_sel = take(ch * kLookCap * 2);  // lookback selection (positions in R_c)
+    if (q.look || q.sfilter) {
+        q.off_sel = take(ch * kLookCap * 2);  // lookback / S-filter selection (positions in R_c)
         q.off_nsel = take(ch);
         q.off_flags = take(64);               // speculated-walk tally
     }
@@ -633,6 +696,11 @@ static parem_status launch_compose(const DeviceDfa &d, const PlainPlan &p, uint8
     return PAREM_OK;
 }
 
+void launch_walk_phase(const DeviceDfa &d, const PlainPlan &p, WalkArgs &a, const uint8_t *d_text, uint8_t *ws,
+                       hipStream_t stream, bool aligned);
+parem_status finish_result(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, uint8_t *ws,
+                           hipStream_t stream, parem_result *d_out);
+
 parem_status launch_plain(const DeviceDfa &d, const PlainPlan &p, const uint8_t *d_text, void *d_ws,
                           hipStream_t stream, parem_result *d_out, hipEvent_t ev_begin, hipEvent_t ev_end) {
     if (p.n == 0) {
@@ -643,6 +711,20 @@ parem_status launch_plain(const DeviceDfa &d, const PlainPlan &p, const uint8_t 
     const bool aligned = (reinterpret_cast<uintptr_t>(d_text) & 15u) == 0;
     if (ev_begin && hipEventRecord(ev_begin, stream) != hipSuccess) return PAREM_EDEVICE;
     WalkArgs a = walk_args(d, p, d_text, ws);
+    launch_walk_phase(d, p, a, d_text, ws, stream, aligned);
+    if (hipGetLastError() != hipSuccess) return PAREM_EDEVICE;
+    if (ev_end && hipEventRecord(ev_end, stream) != hipSuccess) return PAREM_EDEVICE;
+    parem_status st = launch_compose(d, p, ws, stream, d_out);
+    if (st != PAREM_OK) return st;
+    return finish_result(d, p, a, ws, stream, d_out);
+}
+
+// The walk of a plain match: Algorithm 1's sets, lookback sets, or for a
+// partial table the S filter's selection. `a` receives the selection.
+void launch_walk_phase(const DeviceDfa &d, const PlainPlan &p, WalkArgs &a, const uint8_t *d_text, uint8_t *ws,
+                       hipStream_t stream, bool aligned) {
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(ws + p.off_flags);
+    const uint32_t g = (uint32_t)((p.chunks + 255) / 256);
     if (p.look) {
         const LookArgs la = look_args(d, p, d_text, ws);
         const uint32_t wb = look_wave_bytes(la.words);
@@ -651,17 +733,35 @@ parem_status launch_plain(const DeviceDfa &d, const PlainPlan &p, const uint8_t 
         a.nsel = la.nsel;
         a.sel_stride = kLookCap;
         launch_walk<WALK_SELECTED>(d, p, a, stream, aligned);
+    } else if (p.sfilter) {
+        a.sel = reinterpret_cast<uint16_t *>(ws + p.off_sel);
+        a.nsel = ws + p.off_nsel;
+        a.sel_stride = kLookCap;
+        a.absent_fill = d.dead;  // count 0
+        hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(64), 0, stream, reinterpret_cast<uint32_t *>(acc), 4u);
+        hipLaunchKernelGGL(k_sfilter, dim3(g), dim3(256), 0, stream, d_text, p.n, p.L, p.chunks, d.d_cls, d.A,
+                           d.d_loff, d.d_llist, d.d_next, d.dead, const_cast<uint16_t *>(a.sel),
+                           const_cast<uint8_t *>(a.nsel), acc);
+        launch_walk<WALK_SELECTED>(d, p, a, stream, aligned);
     } else {
         launch_walk<WALK_ALL>(d, p, a, stream, aligned);
     }
-    if (hipGetLastError() != hipSuccess) return PAREM_EDEVICE;
-    if (ev_end && hipEventRecord(ev_end, stream) != hipSuccess) return PAREM_EDEVICE;
-    parem_status st = launch_compose(d, p, ws, stream, d_out);
-    if (st != PAREM_OK || !p.look) return st;
+}
+
+// After the composition wrote *d_out: the walk tally of a selection and the
+// outside name of the dead state.
+parem_status finish_result(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, uint8_t *ws,
+                           hipStream_t stream, parem_result *d_out) {
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(ws + p.off_flags);
+    const uint32_t g = (uint32_t)((p.chunks + 255) / 256);
+    if (p.sfilter) {
+        hipLaunchKernelGGL(k_learned_total, dim3(1), dim3(64), 0, stream, acc, d_out);
+        hipLaunchKernelGGL(k_dead_result, dim3(1), dim3(64), 0, stream, d_out, d.dead);
+        return hipGetLastError() == hipSuccess ? PAREM_OK : PAREM_EDEVICE;
+    }
+    if (!p.look) return PAREM_OK;
     hipLaunchKernelGGL(k_clear_u32, dim3(1), dim3(64), 0, stream, reinterpret_cast<uint32_t *>(acc), 4u);
-    hipLaunchKernelGGL(k_look_stats, dim3((uint32_t)((p.chunks + 255) / 256)), dim3(256), 0, stream, a.nsel,
-                       a.map_cls, d.d_loff, p.chunks, acc);
+    hipLaunchKernelGGL(k_look_stats, dim3(g), dim3(256), 0, stream, a.nsel, a.map_cls, d.d_loff, p.chunks, acc);
     hipLaunchKernelGGL(k_learned_total, dim3(1), dim3(64), 0, stream, acc, d_out);
     return hipGetLastError() == hipSuccess ? PAREM_OK : PAREM_EDEVICE;
 }
@@ -688,18 +788,32 @@ parem_status plan_boundary(const DeviceDfa &d, uint64_t len, uint32_t L, PlainPl
 
 parem_status launch_boundary(const DeviceDfa &d, const PlainPlan &p, const uint8_t *d_text, uint32_t *d_states,
                              void *d_ws, hipStream_t stream) {
+    uint8_t *ws = reinterpret_cast<uint8_t *>(d_ws);
+    parem_status st =
+        launch_boundary_into(d, p, d_text, d_states, ws, stream, reinterpret_cast<parem_result *>(ws + p.off_dummy));
+    if (st != PAREM_OK || p.n == 0 || d.dead == 0xffffffffu) return st;
+    hipLaunchKernelGGL(k_dead_states, dim3((uint32_t)((p.chunks + 255) / 256)), dim3(256), 0, stream, d_states,
+                       p.chunks, d.dead);
+    return hipGetLastError() == hipSuccess ? PAREM_OK : PAREM_EDEVICE;
+}
+
+// Walk, composition (the match result into d_out) and down-sweep (the entry
+// state of every chunk into d_states).
+parem_status launch_boundary_into(const DeviceDfa &d, const PlainPlan &p, const uint8_t *d_text, uint32_t *d_states,
+                                  uint8_t *ws, hipStream_t stream, parem_result *d_out) {
     if (p.n == 0) return PAREM_OK;
     if (!d.d_inv) return PAREM_EUNSUPPORTED;
-    uint8_t *ws = reinterpret_cast<uint8_t *>(d_ws);
     const bool aligned = (reinterpret_cast<uintptr_t>(d_text) & 15u) == 0;
-    const WalkArgs a = walk_args(d, p, d_text, ws);
-    launch_walk<WALK_ALL>(d, p, a, stream, aligned);
-    parem_status st = launch_compose(d, p, ws, stream, reinterpret_cast<parem_result *>(ws + p.off_dummy));
+    WalkArgs a = walk_args(d, p, d_text, ws);
+    launch_walk_phase(d, p, a, d_text, ws, stream, aligned);
+    parem_status st = launch_compose(d, p, ws, stream, d_out);
+    if (st != PAREM_OK) return st;
+    st = finish_result(d, p, a, ws, stream, d_out);
     if (st != PAREM_OK) return st;
     // down-sweep: the top map is entered in q0
     const size_t top = p.levels.size() - 1;
     uint32_t *top_entry = reinterpret_cast<uint32_t *>(ws + p.entries[top]);
-    if (hipMemcpyAsync(top_entry, &d.start, 4, hipMemcpyHostToDevice, stream) != hipSuccess) return PAREM_EDEVICE;
+    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(64), 0, stream, top_entry, d.start);
     for (size_t l = top; l-- > 0;) {
         const SegOut s = seg_out(p, ws, l);
         const uint64_t nmaps = p.levels[l];

@@ -59,8 +59,8 @@ def test_struct_layouts_match_the_header(tmp_path):
 #define F(T, f) printf(#T "." #f " %zu\n", offsetof(T, f))
 int main(void) {
     printf("parem_options %zu\n", sizeof(parem_options));
-    F(parem_options, chunk_len); F(parem_options, layout); F(parem_options, group); F(parem_options, kgram);
-    F(parem_options, tile); F(parem_options, no_merge); F(parem_options, lookback); F(parem_options, reserved);
+    F(parem_options, chunk_len); F(parem_options, layout); F(parem_options, group); F(parem_options, policy);
+    F(parem_options, tile); F(parem_options, no_merge); F(parem_options, lookback); F(parem_options, partial);
     printf("parem_result %zu\n", sizeof(parem_result));
     F(parem_result, final_state); F(parem_result, accept); F(parem_result, count); F(parem_result, chunks);
     F(parem_result, spec_runs); F(parem_result, rerun_chunks);
