@@ -194,6 +194,25 @@ parem_status parem_match_async_timed(parem_handle h, const uint8_t *d_text, uint
                                      parem_result *d_out, void *ev_walk_begin, void *ev_walk_end);
 
 /*
+ * parem_match_async without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). The workspace is a file-scope device
+ * array of parem_noalloc_scratch_bytes() bytes (64 MiB) that every GPU the
+ * library runs on holds until the process ends; the call allocates no
+ * device memory. Texts whose workspace (parem_workspace_size) exceeds it get
+ * PAREM_EUNSUPPORTED (e.g. the 35-state DNA automaton needs about 10 MiB for
+ * 1 GiB of text at the default chunk length). Nothing in the array needs to
+ * start at zero. All calls on one GPU share its array: calls that overlap
+ * on one GPU (other streams, or other host threads) race and give undefined
+ * results; serialise them. The current device must be the handle's device
+ * (PAREM_EINVAL otherwise). Same text, result and error conventions as
+ * parem_match_async.
+ */
+parem_status parem_match_async_noalloc(parem_handle h, const uint8_t *d_text, uint64_t len, void *stream,
+                                       parem_result *d_out);
+uint64_t parem_noalloc_scratch_bytes(void);
+
+/*
  * Synchronous match. `text` may be host or device memory (detected with
  * hipPointerGetAttributes); host text is staged through pinned memory. The
  * workspace is allocated and freed inside the call. Returns PAREM_ESYMBOL if

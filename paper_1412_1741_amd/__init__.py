@@ -90,6 +90,10 @@ def _load() -> ctypes.CDLL:
     lib.parem_match_async.argtypes = [vp, vp, u64, vp, u64, vp, vp]
     lib.parem_match_async_timed.restype = i32
     lib.parem_match_async_timed.argtypes = [vp, vp, u64, vp, u64, vp, vp, vp, vp]
+    lib.parem_match_async_noalloc.restype = i32
+    lib.parem_match_async_noalloc.argtypes = [vp, vp, u64, vp, vp]
+    lib.parem_noalloc_scratch_bytes.restype = u64
+    lib.parem_noalloc_scratch_bytes.argtypes = []
     lib.parem_match.restype = i32
     lib.parem_match.argtypes = [vp, vp, u64, ctypes.POINTER(Result)]
     lib.parem_boundary_workspace_size.restype = i32
@@ -139,7 +143,8 @@ _lib = None
 
 # every symbol the header declares, for the export check
 EXPORTED = ["parem_compile", "parem_free", "parem_strerror", "parem_describe", "parem_workspace_size",
-            "parem_match_async", "parem_match_async_timed", "parem_match", "parem_boundary_workspace_size",
+            "parem_match_async", "parem_match_async_timed", "parem_match_async_noalloc",
+            "parem_noalloc_scratch_bytes", "parem_match", "parem_boundary_workspace_size",
             "parem_boundary_states", "parem_positions_workspace_size", "parem_match_positions_async",
             "parem_proposal_create", "parem_proposal_free", "parem_proposal_params",
             "parem_proposal_train_step", "parem_proposal_logits", "parem_proposal_apply_grad",
@@ -225,6 +230,17 @@ def parem_match_async_timed(handle: int, d_text_ptr: int, length: int, d_workspa
     _check(lib().parem_match_async_timed(handle, d_text_ptr or None, int(length), d_workspace_ptr or None,
                                         int(workspace_bytes), stream_ptr or None, d_out_ptr, ev_begin or None,
                                         ev_end or None), "parem_match_async_timed")
+
+
+def parem_match_async_noalloc(handle: int, d_text_ptr: int, length: int, stream_ptr: int, d_out_ptr: int) -> None:
+    """parem_match_async with the library's own device scratch array (no
+    workspace; allocates no device memory)."""
+    _check(lib().parem_match_async_noalloc(handle, d_text_ptr or None, int(length), stream_ptr or None, d_out_ptr),
+           "parem_match_async_noalloc")
+
+
+def parem_noalloc_scratch_bytes() -> int:
+    return int(lib().parem_noalloc_scratch_bytes())
 
 
 def parem_boundary_workspace_size(handle: int, length: int, chunk_len: int) -> int:

@@ -38,6 +38,7 @@ SOURCES = [
     "parem_walk_sparse_redo.hip",
     "parem_mlp.hip",
     "parem_positions.hip",
+    "parem_noalloc.hip",
     "parem_batch.hip",
     "parem_batch_t64.hip",
     "parem_batch_t128.hip",
