@@ -94,6 +94,8 @@ def _load() -> ctypes.CDLL:
     lib.parem_match_async_noalloc.argtypes = [vp, vp, u64, vp, vp]
     lib.parem_noalloc_scratch_bytes.restype = u64
     lib.parem_noalloc_scratch_bytes.argtypes = []
+    lib.parem_read_sweep.restype = i32
+    lib.parem_read_sweep.argtypes = [vp, u64, vp, vp]
     lib.parem_match.restype = i32
     lib.parem_match.argtypes = [vp, vp, u64, ctypes.POINTER(Result)]
     lib.parem_boundary_workspace_size.restype = i32
@@ -144,7 +146,7 @@ _lib = None
 # every symbol the header declares, for the export check
 EXPORTED = ["parem_compile", "parem_free", "parem_strerror", "parem_describe", "parem_workspace_size",
             "parem_match_async", "parem_match_async_timed", "parem_match_async_noalloc",
-            "parem_noalloc_scratch_bytes", "parem_match", "parem_boundary_workspace_size",
+            "parem_noalloc_scratch_bytes", "parem_read_sweep", "parem_match", "parem_boundary_workspace_size",
             "parem_boundary_states", "parem_positions_workspace_size", "parem_match_positions_async",
             "parem_proposal_create", "parem_proposal_free", "parem_proposal_params",
             "parem_proposal_train_step", "parem_proposal_logits", "parem_proposal_apply_grad",
@@ -237,6 +239,12 @@ def parem_match_async_noalloc(handle: int, d_text_ptr: int, length: int, stream_
     workspace; allocates no device memory)."""
     _check(lib().parem_match_async_noalloc(handle, d_text_ptr or None, int(length), stream_ptr or None, d_out_ptr),
            "parem_match_async_noalloc")
+
+
+def parem_read_sweep(d_buf_ptr: int, length: int, stream_ptr: int, d_sink_ptr: int) -> None:
+    """One coalesced 16-byte-load read of a device buffer (the HBM read
+    ceiling the walk is compared against; measurement helper)."""
+    _check(lib().parem_read_sweep(d_buf_ptr, int(length), stream_ptr or None, d_sink_ptr), "parem_read_sweep")
 
 
 def parem_noalloc_scratch_bytes() -> int:

@@ -39,6 +39,7 @@ SOURCES = [
     "parem_mlp.hip",
     "parem_positions.hip",
     "parem_noalloc.hip",
+    "parem_measure.hip",
     "parem_batch.hip",
     "parem_batch_t64.hip",
     "parem_batch_t128.hip",

@@ -1,0 +1,39 @@
+// HBM read ceiling: one coalesced 16-byte-load pass over a buffer.
+#include "parem_internal.h"
+
+#include "../../include/parem_measure.h"
+
+namespace parem {
+
+__global__ __launch_bounds__(256) void k_read_sweep(const uint4 *__restrict__ p, uint64_t n16,
+                                                    uint32_t *__restrict__ sink) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t acc = 0;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        const uint4 a = p[i], b = p[i + stride], c = p[i + 2 * stride], d = p[i + 3 * stride];
+        acc ^= a.x ^ a.y ^ a.z ^ a.w ^ b.x ^ b.y ^ b.z ^ b.w ^ c.x ^ c.y ^ c.z ^ c.w ^ d.x ^ d.y ^ d.z ^ d.w;
+    }
+    for (; i < n16; i += stride) {
+        const uint4 a = p[i];
+        acc ^= a.x ^ a.y ^ a.z ^ a.w;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc ^= (uint32_t)__shfl_xor((int)acc, o, 64);
+    if ((threadIdx.x & 63u) == 0 && acc == 0x9e3779b9u) *sink = acc;  // practically never stores
+}
+
+}  // namespace parem
+
+extern "C" parem_status parem_read_sweep(const uint8_t *d_buf, uint64_t len, void *stream, uint32_t *d_sink) {
+    if (!d_buf || !d_sink || len == 0 || (len & 15u) || (reinterpret_cast<uintptr_t>(d_buf) & 15u))
+        return PAREM_EINVAL;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return PAREM_EDEVICE;
+    hipLaunchKernelGGL(parem::k_read_sweep, dim3((unsigned)(8 * cus)), dim3(256), 0,
+                       reinterpret_cast<hipStream_t>(stream), reinterpret_cast<const uint4 *>(d_buf), len / 16,
+                       d_sink);
+    return hipGetLastError() == hipSuccess ? PAREM_OK : PAREM_EDEVICE;
+}

@@ -8,13 +8,15 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "parem.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("parem.h", "parem_measure.h")]
 
 
 def declared_functions():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(parem_[a-z_0-9]+)\s*\(", src)))
+    names = set()
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(parem_[a-z_0-9]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_header_declares_entry_points():

@@ -278,6 +278,29 @@ def config1(seed: int = CFG1_SEED, n: int = 1 << 20):
     return dfa, text, 1024
 
 
+# Table I of the paper (Section II-C): the 9-state automaton that finds the
+# word "parallel" over the symbols p, a, r, e, l (columns in that order).
+PAREL = b"parel"
+TABLE1 = np.asarray([[1, 0, 0, 0, 0], [1, 2, 0, 0, 0], [1, 0, 3, 0, 0], [1, 4, 0, 0, 0], [1, 0, 0, 0, 5],
+                     [1, 0, 0, 0, 6], [1, 0, 0, 7, 0], [1, 0, 0, 0, 8], [1, 0, 0, 0, 0]], dtype=np.uint8)
+# input lengths of the paper's measurements (Section IV-A)
+PAPER_LENGTHS = (66_900_000, 134_000_000, 268_000_000, 536_000_000, 1_070_000_000)
+
+
+def paper_parallel(n: int, seed: int = 1412, copies_per_mib: int = 64):
+    """Table I's automaton (F = {8}) and n i.i.d. uniform symbols over
+    p,a,r,e,l with the word "parallel" planted at random offsets (the paper
+    does not give its input strings)."""
+    rng = np.random.default_rng([seed, n])
+    dfa = Dfa(TABLE1.copy(), PAREL, 0, np.asarray([8], dtype=np.uint32), "table1")
+    text = uniform_text(rng, PAREL, n)
+    k = max(1, n * copies_per_mib >> 20)
+    word = np.frombuffer(b"parallel", dtype=np.uint8)
+    for o in rng.integers(0, max(1, n - 8), size=k):
+        text[o:o + 8] = word[: max(0, min(8, n - int(o)))]
+    return dfa, text
+
+
 def motif_spec(seed: int):
     rng = np.random.default_rng([seed, 0xD7A])
     alpha = np.frombuffer(ACGT, dtype=np.uint8)
