@@ -615,6 +615,17 @@ __device__ __forceinline__ void walk_chunk(const ST &st, const WalkArgs &a, uint
             nwalk = 1;
         }
     }
+    if constexpr (MODE == WALK_REDO) {
+        // a walk again from a lookback set (it holds the true entry state);
+        // the entries it does not walk keep what the first walk stored
+        if (a.sel) {
+            const uint32_t ns = a.nsel[c];
+            if (ns) {
+                pos.sel = a.sel + c * a.sel_stride;
+                nwalk = ns;
+            }
+        }
+    }
 
     // tiles every chunk of this wave holds in full
     uint32_t ntiles = 0;

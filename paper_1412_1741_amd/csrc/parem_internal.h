@@ -138,6 +138,8 @@ struct PlainPlan {
     uint32_t m = 0;          // learned: states walked per chunk
     uint32_t look = 0;       // lookback bytes (0: the speculated sets of Algorithm 1)
     bool sfilter = false;    // partial table: walk only S intersect L (selection per chunk)
+    uint32_t relook = 0;     // learned: chunks walked again use lookback sets of this window
+    uint64_t off_lsel = 0, off_lnsel = 0;  // learned: their selections
     bool keep = false;       // keep every composition level (down-sweep)
     std::vector<uint64_t> levels;  // maps after each composition level
     struct Seg {

@@ -136,7 +136,7 @@ __global__ void k_escalate(uint64_t C, uint8_t *__restrict__ redo, uint8_t *__re
                            uint32_t *__restrict__ flags, uint32_t *__restrict__ round_count,
                            uint32_t *__restrict__ rlist, const uint8_t *__restrict__ nsel,
                            const uint16_t *__restrict__ map_cls, const uint32_t *__restrict__ loff,
-                           unsigned long long *__restrict__ part_out) {
+                           const uint8_t *__restrict__ lnsel, unsigned long long *__restrict__ part_out) {
     const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long runs = 0, again = 0;
     if (c < C) {
@@ -151,8 +151,11 @@ __global__ void k_escalate(uint64_t C, uint8_t *__restrict__ redo, uint8_t *__re
         }
         runs = nsel[c];
         if (dn) {
+            // walked again from its lookback set (lnsel, when that is not the
+            // whole set) or from its whole speculated set
             const uint32_t cl = map_cls[c] & 0x7fffu;
-            runs += loff[cl + 1] - loff[cl];
+            const uint32_t ln = lnsel ? lnsel[c] : 0u;
+            runs += ln ? ln : loff[cl + 1] - loff[cl];
             again = 1;
         }
     }
@@ -484,10 +487,13 @@ __global__ void k_dead_states(uint32_t *__restrict__ states, uint64_t C, uint32_
     if (c < C && states[c] == dead) states[c] = PAREM_DEAD_STATE;
 }
 
-__global__ __launch_bounds__(256) void k_lookback(LookArgs a, uint32_t start, uint32_t wave_bytes) {
+// `only` (may be null): chunks with only[c] == 0 are skipped
+__global__ __launch_bounds__(256) void k_lookback(LookArgs a, uint32_t start, uint32_t wave_bytes,
+                                                  const uint8_t *__restrict__ only) {
     extern __shared__ __align__(16) uint8_t smem[];
     const uint64_t c = (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6);
     if (c >= a.nchunks) return;  // whole waves leave; no workgroup barrier follows
+    if (only && only[c] == 0) return;
     lookback_chunk(a, start, c, smem + (threadIdx.x >> 6) * wave_bytes);
 }
 
@@ -728,7 +734,8 @@ void launch_walk_phase(const DeviceDfa &d, const PlainPlan &p, WalkArgs &a, cons
     if (p.look) {
         const LookArgs la = look_args(d, p, d_text, ws);
         const uint32_t wb = look_wave_bytes(la.words);
-        hipLaunchKernelGGL(k_lookback, dim3((uint32_t)((p.chunks + 3) / 4)), dim3(256), 4 * wb, stream, la, d.start, wb);
+        hipLaunchKernelGGL(k_lookback, dim3((uint32_t)((p.chunks + 3) / 4)), dim3(256), 4 * wb, stream, la, d.start, wb,
+                           nullptr);
         a.sel = la.sel;
         a.nsel = la.nsel;
         a.sel_stride = kLookCap;
@@ -859,6 +866,17 @@ parem_status plan_learned(const DeviceDfa &d, const Proposal &pr, uint64_t len, 
     off = align256(off + (ch + 255) / 256 * 16);
     p->off_mlp = off;
     off = align256(off + proposal_infer_bytes(pr, ch));
+    // a handle that walks lookback sets in plain matches walks them again
+    // here for chunks whose selection missed (the sub-chunk path serves
+    // small sets instead)
+    const bool split = d.d_step && d.max_spec <= 64;
+    p->relook = (opt.lookback && d.d_next && d.d_inv && !split) ? opt.lookback : 0u;
+    if (p->relook) {
+        p->off_lsel = off;
+        off = align256(off + ch * kLookCap * 2);
+        p->off_lnsel = off;
+        off = align256(off + ch);
+    }
     p->bytes = off;
     p->m = m;
     return PAREM_OK;
@@ -917,6 +935,22 @@ parem_status launch_learned(const DeviceDfa &d, const Proposal &pr, const PlainP
         });
         if (lds_err != hipSuccess) return PAREM_EDEVICE;
     }
+    // marked chunks of handles with lookback sets are walked again from them
+    LookArgs la{};
+    uint32_t lwb = 0;
+    uint8_t *lnsel = nullptr;
+    if (p.relook) {
+        PlainPlan lp = p;
+        lp.look = p.relook;
+        la = look_args(d, lp, d_text, ws);
+        la.sel = reinterpret_cast<uint16_t *>(ws + p.off_lsel);
+        lnsel = ws + p.off_lnsel;
+        la.nsel = lnsel;
+        lwb = look_wave_bytes(la.words);
+        r.sel = la.sel;
+        r.nsel = lnsel;
+        r.sel_stride = kLookCap;
+    }
     // (the sub-chunk walk settles what later coverage rounds would find: one
     // round before the escalation is enough then)
     const int rounds = split ? 1 : kCoverRounds;
@@ -928,11 +962,13 @@ parem_status launch_learned(const DeviceDfa &d, const Proposal &pr, const PlainP
                            it == 0 ? 1u : 0u);
         if (escalate)
             hipLaunchKernelGGL(k_escalate, dim3(g), dim3(256), 0, stream, (uint64_t)C, redo, done, flags, round_count,
-                               rlist, nsel, a.map_cls, d.d_loff, part);
+                               rlist, nsel, a.map_cls, d.d_loff, lnsel, part);
         if (split) {
             sa.count = round_count;
             hipLaunchKernelGGL(k_redo_split, dim3(512), dim3(kSplitThreads), sl.bytes, stream, sa);
         }
+        if (p.relook)
+            hipLaunchKernelGGL(k_lookback, dim3((C + 3) / 4), dim3(256), 4 * lwb, stream, la, d.start, lwb, redo);
         launch_walk<WALK_REDO>(d, p, r, stream, aligned);
     }
     if (ev_end && hipEventRecord(ev_end, stream) != hipSuccess) return PAREM_EDEVICE;

@@ -563,3 +563,27 @@ def test_learned_exact_wide_heads(kind, mm, L):
     dfa, text = head_case(kind)
     got = learned_case(f"wide head {kind}", dfa, text, random_params(dfa.num_states, 5), mm, chunk_len=L)
     say(f"[wide head] {kind} m={mm}: re-walked {got.rerun_chunks} of {got.chunks}")
+
+
+def test_learned_rewalk_from_lookback_sets():
+    """A handle compiled with lookback sets (as the tuner picks for dense
+    4-symbol DFAs with thousands of states, whose speculated sets hold most
+    states) walks chunks whose selection missed again from their lookback
+    sets, not from the whole set: exact, and far fewer walks."""
+    rng = np.random.default_rng(2048)
+    dfa = W.random_dense_dfa(rng, 2000, b"ACGT", num_accepting=31)
+    text = W.uniform_text(rng, b"ACGT", 2_000_003)
+    params = random_params(dfa.num_states, 13)
+    got = {}
+    for look in (0, 64):
+        m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, chunk_len=4096, lookback=look)
+        prop = P.Proposal(m, params)
+        r = m.match_learned(prop, dev(text), 2)
+        want = oracle.walk_dfa(dfa, text)
+        assert (r.final_state, r.accept, r.count) == (want.final_state, want.accept, want.count), look
+        say(f"[relook] lookback={look}: walks {r.spec_runs}, re-walked {r.rerun_chunks} of {r.chunks}")
+        got[look] = r
+        prop.close()
+        m.close()
+    assert got[64].rerun_chunks > 0
+    assert got[64].spec_runs * 5 < got[0].spec_runs
