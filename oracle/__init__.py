@@ -65,6 +65,9 @@ def _load():
         lib.oracle_parem.restype = ctypes.c_int
         lib.oracle_parem.argtypes = [u32p, u32, u8p, u32, u32, u32, u32, u8p, u8p, ctypes.c_uint64,
                                      ctypes.c_uint64, u32p, u64p, u64p, u32p, u32p, u32p, ctypes.c_uint64, u64p]
+        lib.oracle_nfa_walk.restype = ctypes.c_int
+        lib.oracle_nfa_walk.argtypes = [u32, u32, u8p, u32p, u32, u32p, u32, u8p, u32, u8p, ctypes.c_uint64, u8p,
+                                        u64p, u8p, u64p]
         lib.oracle_positions.restype = ctypes.c_int
         lib.oracle_positions.argtypes = [u32p, u32, u8p, u32, u32, u32, u8p, u8p, ctypes.c_uint64, u64p,
                                          ctypes.c_uint64, u64p, u64p]

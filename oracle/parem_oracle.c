@@ -374,3 +374,97 @@ int oracle_parem(const uint32_t *table, uint32_t Q, const uint8_t *alphabet, uin
         *trace_len = tl;
     return ORC_OK;
 }
+
+/*
+ * Run of a nondeterministic automaton with empty moves (the McNaughton-
+ * Yamada-Thompson construction of Section III), simulated on sets of states:
+ * the current set starts as the empty-move closure of `start`; each byte
+ * moves every state of the set along its edges whose byte range holds the
+ * byte, and the closure of the result is the next set. Nothing is
+ * determinised. A step counts when the new set holds an accepting state;
+ * *out_accept is whether the final set does, *out_empty whether the set
+ * became empty (no continuation can match any more).
+ *  edges: n_edges records (from, lo, hi, to): a move on bytes lo..hi;
+ *  eps:   n_eps records (from, to): an empty move.
+ * Bytes outside the alphabet give -4 (offset in *bad_pos).
+ */
+int oracle_nfa_walk(uint32_t n_states, uint32_t start, const uint8_t *accepting,
+                    const uint32_t *edges, uint32_t n_edges, const uint32_t *eps, uint32_t n_eps,
+                    const uint8_t *alphabet, uint32_t A, const uint8_t *text, uint64_t len,
+                    uint8_t *out_accept, uint64_t *out_count, uint8_t *out_empty, uint64_t *bad_pos)
+{
+    int col[256];
+    if (!accepting || n_states == 0 || start >= n_states || (n_edges && !edges) || (n_eps && !eps) ||
+        !out_accept || !out_count || (!text && len) || !alphabet || A == 0 || A > 256)
+        return ORC_EINVAL;
+    if (build_columns(alphabet, A, col))
+        return ORC_EINVAL;
+    for (uint32_t k = 0; k < n_edges; ++k)
+        if (edges[4 * k] >= n_states || edges[4 * k + 3] >= n_states || edges[4 * k + 1] > edges[4 * k + 2] ||
+            edges[4 * k + 2] > 255)
+            return ORC_EINVAL;
+    for (uint32_t k = 0; k < n_eps; ++k)
+        if (eps[2 * k] >= n_states || eps[2 * k + 1] >= n_states)
+            return ORC_EINVAL;
+    uint8_t *cur = (uint8_t *)calloc(n_states, 1);
+    uint8_t *nxt = (uint8_t *)calloc(n_states, 1);
+    uint32_t *stack = (uint32_t *)malloc((size_t)n_states * sizeof(uint32_t));
+    if (!cur || !nxt || !stack) {
+        free(cur); free(nxt); free(stack);
+        return ORC_EINVAL;
+    }
+    /* closure of the marked set `s` in place (depth-first over empty moves) */
+#define CLOSE(s)                                                              \
+    do {                                                                      \
+        uint32_t sp = 0;                                                      \
+        for (uint32_t q = 0; q < n_states; ++q)                               \
+            if (s[q])                                                         \
+                stack[sp++] = q;                                              \
+        while (sp) {                                                          \
+            uint32_t q = stack[--sp];                                         \
+            for (uint32_t k = 0; k < n_eps; ++k)                              \
+                if (eps[2 * k] == q && !s[eps[2 * k + 1]]) {                  \
+                    s[eps[2 * k + 1]] = 1;                                    \
+                    stack[sp++] = eps[2 * k + 1];                             \
+                }                                                             \
+        }                                                                     \
+    } while (0)
+    cur[start] = 1;
+    CLOSE(cur);
+    uint64_t count = 0;
+    int rc = ORC_OK;
+    for (uint64_t i = 0; i < len; ++i) {
+        if (col[text[i]] < 0) {
+            if (bad_pos)
+                *bad_pos = i;
+            rc = ORC_ESYMBOL;
+            break;
+        }
+        memset(nxt, 0, n_states);
+        for (uint32_t k = 0; k < n_edges; ++k)
+            if (cur[edges[4 * k]] && text[i] >= edges[4 * k + 1] && text[i] <= edges[4 * k + 2])
+                nxt[edges[4 * k + 3]] = 1;
+        CLOSE(nxt);
+        uint8_t *t = cur;
+        cur = nxt;
+        nxt = t;
+        int acc = 0;
+        for (uint32_t q = 0; q < n_states && !acc; ++q)
+            acc = cur[q] && accepting[q];
+        count += (uint64_t)acc;
+    }
+#undef CLOSE
+    if (rc == ORC_OK) {
+        int acc = 0, any = 0;
+        for (uint32_t q = 0; q < n_states; ++q) {
+            acc |= cur[q] && accepting[q];
+            any |= cur[q];
+        }
+        *out_accept = (uint8_t)acc;
+        *out_count = count;
+        if (out_empty)
+            *out_empty = (uint8_t)!any;
+    }
+    free(cur); free(nxt); free(stack);
+    return rc;
+}
