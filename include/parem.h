@@ -43,7 +43,8 @@ typedef enum {
     PAREM_EDEVICE = -3,     /* a HIP runtime call failed                  */
     PAREM_ESYMBOL = -4,     /* a text byte is not in the alphabet         */
     PAREM_ESTATE = -5,      /* a table entry / start / final id >= Q      */
-    PAREM_EUNSUPPORTED = -6 /* sizes beyond what this build handles       */
+    PAREM_EUNSUPPORTED = -6,/* sizes beyond what this build handles       */
+    PAREM_ESYNTAX = -7      /* a regular expression does not parse        */
 } parem_status;
 
 /* Table layouts the compile step may choose (parem_options.layout). */
@@ -150,6 +151,46 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
                            const uint8_t *alphabet, uint32_t alphabet_size, uint32_t start,
                            const uint32_t *accepting, uint32_t num_accepting,
                            const parem_options *opt, parem_handle *out);
+
+/*
+ * Regular-expression front-end (Section III). A pattern of the operators of
+ * Table III - concatenation ab, Kleene star a*, union a|b, positive closure
+ * a+, range [x..y] (bytes x to y in code order; x-y and several items per
+ * bracket are accepted too), optionality a?, groups (...) - is parsed into a
+ * syntax tree, turned into an automaton with empty moves by the
+ * McNaughton-Yamada-Thompson construction, freed of its empty moves, and
+ * determinised by the subset construction over the given alphabet (states
+ * numbered in breadth-first order of discovery; the start state is 0).
+ * Outside brackets ( ) [ ] | * + ? \ are operators and \x is the byte x;
+ * every other byte stands for itself; an empty branch is the empty word.
+ *  mode PAREM_RE_ANCHORED: the automaton of the expression itself; a step
+ *       counts when the text read so far is in its language, and the match
+ *       accepts when the whole text is.
+ *  mode PAREM_RE_SEARCH: the automaton of Sigma* followed by the expression
+ *       (Sigma = the alphabet); a step counts when some match of the
+ *       expression ends at that byte - e.g. "parallel" over p,a,r,e,l gives
+ *       the automaton of Table I.
+ *  partial  1: no dead state; transitions into the empty set are undefined
+ *       (a partial table, see parem_options.partial).
+ * parem_regex_dfa writes the number of states to *num_states and, when the
+ * pointers are not NULL, the table [states][alphabet_size] (u32; 0xFFFFFFFF
+ * for undefined transitions; table_cap entries available) and one final
+ * flag per state (final_cap bytes available). Host code only: no device is
+ * used. PAREM_ESYNTAX for a malformed pattern, PAREM_EUNSUPPORTED beyond
+ * 32767 states (16381 for partial tables), PAREM_EINVAL for too small
+ * buffers or a repeated alphabet byte.
+ * parem_compile_regex builds that automaton and compiles it with
+ * parem_compile (opt->partial selects the partial form); bytes of the
+ * pattern outside the alphabet can never match.
+ */
+#define PAREM_RE_ANCHORED 0u
+#define PAREM_RE_SEARCH 1u
+parem_status parem_regex_dfa(const char *pattern, uint64_t pattern_len, const uint8_t *alphabet,
+                             uint32_t alphabet_size, uint32_t mode, uint32_t partial, uint32_t *num_states,
+                             uint32_t *table, uint64_t table_cap, uint8_t *final_flags, uint64_t final_cap);
+parem_status parem_compile_regex(const char *pattern, uint64_t pattern_len, const uint8_t *alphabet,
+                                 uint32_t alphabet_size, uint32_t mode, const parem_options *opt,
+                                 parem_handle *out);
 
 /* Release a handle and its device memory. NULL is accepted. */
 void parem_free(parem_handle h);

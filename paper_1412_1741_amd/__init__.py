@@ -26,6 +26,10 @@ PAREM_EDEVICE = -3
 PAREM_ESYMBOL = -4
 PAREM_ESTATE = -5
 PAREM_EUNSUPPORTED = -6
+PAREM_ESYNTAX = -7
+
+RE_ANCHORED = 0
+RE_SEARCH = 1
 
 LAYOUT_AUTO = 0
 LAYOUT_BYTE_LDS = 1
@@ -77,6 +81,11 @@ def _load() -> ctypes.CDLL:
     lib.parem_compile.restype = i32
     lib.parem_compile.argtypes = [vp, i32, u32, vp, u32, u32, vp, u32, ctypes.POINTER(Options),
                                   ctypes.POINTER(vp)]
+    lib.parem_regex_dfa.restype = i32
+    lib.parem_regex_dfa.argtypes = [ctypes.c_char_p, u64, vp, u32, u32, u32, ctypes.POINTER(u32), vp, u64, vp, u64]
+    lib.parem_compile_regex.restype = i32
+    lib.parem_compile_regex.argtypes = [ctypes.c_char_p, u64, vp, u32, u32, ctypes.POINTER(Options),
+                                        ctypes.POINTER(vp)]
     lib.parem_free.restype = None
     lib.parem_free.argtypes = [vp]
     lib.parem_strerror.restype = ctypes.c_char_p
@@ -144,7 +153,7 @@ def _load() -> ctypes.CDLL:
 _lib = None
 
 # every symbol the header declares, for the export check
-EXPORTED = ["parem_compile", "parem_free", "parem_strerror", "parem_describe", "parem_workspace_size",
+EXPORTED = ["parem_compile", "parem_regex_dfa", "parem_compile_regex", "parem_free", "parem_strerror", "parem_describe", "parem_workspace_size",
             "parem_match_async", "parem_match_async_timed", "parem_match_async_noalloc",
             "parem_noalloc_scratch_bytes", "parem_read_sweep", "parem_match", "parem_boundary_workspace_size",
             "parem_boundary_states", "parem_positions_workspace_size", "parem_match_positions_async",
@@ -198,6 +207,34 @@ def parem_compile(table, alphabet, start: int, accepting, *, chunk_len: int = 0,
                             int(start), acc.ctypes.data if acc.size else None, acc.size, ctypes.byref(opt),
                             ctypes.byref(h))
     _check(st, "parem_compile")
+    return h.value
+
+
+def parem_regex_dfa(pattern: bytes, alphabet, mode: int = RE_ANCHORED, partial: bool = False):
+    """Host-side front-end: (table [Q, A] uint32 with 0xFFFFFFFF for undefined
+    transitions, final flags [Q] uint8); start state 0."""
+    pat = bytes(pattern)
+    alpha = np.frombuffer(bytes(alphabet), dtype=np.uint8).copy()
+    q = ctypes.c_uint32()
+    _check(lib().parem_regex_dfa(pat, len(pat), alpha.ctypes.data, alpha.size, int(mode), 1 if partial else 0,
+                                 ctypes.byref(q), None, 0, None, 0), "parem_regex_dfa")
+    table = np.zeros((q.value, alpha.size), dtype=np.uint32)
+    fin = np.zeros(q.value, dtype=np.uint8)
+    _check(lib().parem_regex_dfa(pat, len(pat), alpha.ctypes.data, alpha.size, int(mode), 1 if partial else 0,
+                                 ctypes.byref(q), table.ctypes.data, table.size, fin.ctypes.data, fin.size),
+           "parem_regex_dfa")
+    return table, fin
+
+
+def parem_compile_regex(pattern: bytes, alphabet, mode: int = RE_ANCHORED, *, chunk_len: int = 0,
+                        layout: int = 0, group: int = 0, tile: int = 0, no_merge: bool = False, lookback: int = 0,
+                        policy: int = POLICY_PAREM, partial: bool = False) -> int:
+    pat = bytes(pattern)
+    alpha = np.frombuffer(bytes(alphabet), dtype=np.uint8).copy()
+    opt = Options(chunk_len, layout, group, policy, tile, 1 if no_merge else 0, lookback, 1 if partial else 0)
+    h = ctypes.c_void_p()
+    _check(lib().parem_compile_regex(pat, len(pat), alpha.ctypes.data, alpha.size, int(mode), ctypes.byref(opt),
+                                     ctypes.byref(h)), "parem_compile_regex")
     return h.value
 
 
@@ -455,6 +492,17 @@ class Matcher:
         self.num_states = int(np.asarray(table).shape[0])
         self._ws = {}
         self._lws = None
+
+    @classmethod
+    def from_regex(cls, pattern: bytes, alphabet, mode: int = RE_ANCHORED, **opts) -> "Matcher":
+        """A matcher of a regular expression (Section III front-end)."""
+        self = cls.__new__(cls)
+        self.handle = parem_compile_regex(pattern, alphabet, mode, **opts)
+        table, _ = parem_regex_dfa(pattern, alphabet, mode, opts.get("partial", False))
+        self.num_states = int(table.shape[0])
+        self._ws = {}
+        self._lws = None
+        return self
 
     def close(self):
         if self.handle:

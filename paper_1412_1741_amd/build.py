@@ -17,6 +17,7 @@ LIB = os.path.join(HERE, "libparem.so")
 
 SOURCES = [
     "parem_api.cpp",
+    "parem_regex.cpp",
     "parem_walk.hip",
     "parem_walk_kgram_all.hip",
     "parem_walk_kgram_sel.hip",

@@ -278,6 +278,7 @@ const char *parem_strerror(parem_status s) {
         case PAREM_ESYMBOL: return "text byte outside the alphabet";
         case PAREM_ESTATE: return "state id out of range";
         case PAREM_EUNSUPPORTED: return "unsupported size";
+        case PAREM_ESYNTAX: return "regular expression syntax error";
         default: return "unknown status";
     }
 }
