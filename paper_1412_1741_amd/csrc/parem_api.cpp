@@ -96,6 +96,12 @@ bool sparse_rows(const DeviceDfa &d, const std::vector<uint32_t> &t, std::vector
     if (bytes > parem::kSparseLdsMax) return false;
     image.assign(bytes, 0);
     for (uint32_t x = 0; x < 256; ++x) image[x] = (uint8_t)d.cls[x];
+    // every byte valid: exceptions name the byte itself (the walk then needs
+    // no byte -> column read); else the column
+    uint8_t key[256];
+    for (uint32_t a = 0; a < 256; ++a) key[a] = (uint8_t)a;
+    if (!invalid_used)
+        for (uint32_t x = 0; x < 256; ++x) key[d.cls[x]] = (uint8_t)x;
     std::vector<uint32_t> next(ncol), count(d.Q + 1, 0);
     for (uint32_t q = 0; q <= d.Q; ++q) {
         for (uint32_t a = 0; a < ncol; ++a) next[a] = (q < d.Q && a < d.A) ? t[(size_t)q * d.A + a] : d.sent;
@@ -113,12 +119,12 @@ bool sparse_rows(const DeviceDfa &d, const std::vector<uint32_t> &t, std::vector
         for (uint32_t a = 0; a < ncol; ++a) {
             if (next[a] == dflt) continue;
             if (ne == parem::kSparseExc) return false;
-            col[ne] = (uint8_t)a;
+            col[ne] = key[a];
             ent[ne] = entry(next[a]);
             ++ne;
         }
         for (uint32_t k = ne; k < parem::kSparseExc; ++k) {
-            col[k] = 0;
+            col[k] = key[0];
             ent[k] = entry(next[0]);
         }
         uint8_t *row = image.data() + 256 + (size_t)q * 16;
@@ -418,6 +424,11 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
     if ((o.layout == PAREM_LAYOUT_AUTO) && !kg_ok && !lds_ok && !class_ok && sparse_rows(d, t, sparse_image))
         layout = PAREM_LAYOUT_SPARSE_LDS;
     d.layout = layout;
+    if (layout == PAREM_LAYOUT_SPARSE_LDS) {
+        bool all_valid = true;
+        for (uint32_t x = 0; x < 256; ++x) all_valid &= d.cls[x] < d.A;
+        d.sparse_raw = all_valid;
+    }
     if (layout != PAREM_LAYOUT_KGRAM_LDS) {
         d.kgram = 0;
         d.kg = parem::KgParams{};

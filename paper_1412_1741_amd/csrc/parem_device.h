@@ -125,16 +125,21 @@ struct ClassStep {
 // four column compares. The table leaves room for two workgroups per CU only
 // without the text staging area, so lanes load their chunks 16 bytes at a
 // time themselves (the lines stay in L2 between a lane's loads).
+// Sparse rows: per state a default entry and four (key, entry) exceptions in
+// one 16-byte LDS row. A key is the byte itself when every byte is valid
+// (RAW: no byte -> column read per step), else the byte's column.
+template <bool RAW>
 struct SparseStep {
     static constexpr bool kRedo = false;
     static constexpr bool kPrefixPasses = true;
     static constexpr bool kStage = false;
-    const uint8_t *__restrict__ col;  // LDS: [256]
+    const uint8_t *__restrict__ col;  // LDS: [256] byte -> column (unused when RAW)
     const uint4 *__restrict__ rows;   // LDS: (Q+1) rows
 
     __device__ __forceinline__ uint32_t init(uint32_t s) const { return s; }
     __device__ __forceinline__ uint32_t id(uint32_t r) const { return r; }
     __device__ __forceinline__ bool same(uint32_t a, uint32_t b) const { return a == b; }
+    __device__ __forceinline__ uint32_t key(uint32_t byte) const { return RAW ? byte : (uint32_t)col[byte]; }
     __device__ __forceinline__ void one(uint32_t &s, uint32_t &c, uint32_t cl) const {
         const uint4 r = rows[s];
         uint32_t v = r.w;
@@ -150,7 +155,7 @@ struct SparseStep {
                                           uint32_t &bad) const {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const uint32_t cl = col[(d >> (8 * k)) & 0xffu];
+            const uint32_t cl = key((d >> (8 * k)) & 0xffu);
 #pragma unroll
             for (int j = 0; j < G; ++j)
                 if (j < nw) one(R[j], c[j], cl);
@@ -159,7 +164,7 @@ struct SparseStep {
     template <int G>
     __device__ __forceinline__ void flush(uint32_t (&S)[G], uint32_t (&c)[G], int nw) const {}
     __device__ __forceinline__ void byte(uint32_t x, uint32_t &R, uint32_t &c, uint32_t &bad) const {
-        one(R, c, col[x]);
+        one(R, c, key(x));
     }
 };
 

@@ -76,6 +76,7 @@ struct DeviceDfa {
     uint16_t *d_bytes = nullptr;     // sparse-row layout: the (Q+1) x 256 u16 byte table for batch walks
     uint16_t *d_coltab = nullptr;    // [(Q+1) x (A+1)] next state by column | final << 15 (match positions)
     uint32_t hot_rows = 0;
+    bool sparse_raw = false;         // sparse rows name exception bytes, not columns (every byte valid)
 };
 
 // hot-row layout: at most kHotMax rows of kHotRow u16 entries (256 bytes plus

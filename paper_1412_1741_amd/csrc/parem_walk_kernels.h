@@ -61,14 +61,14 @@ __global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_walk_class(W
 }
 
 // the table limits a CU to two workgroups: registers for two
-template <int G, bool ALIGNED, int MODE>
+template <int G, bool ALIGNED, int MODE, bool RAW>
 __global__ __launch_bounds__(kWalkThreads, 2) void k_walk_sparse(WalkArgs a,
                                                                                 const uint8_t *__restrict__ g_table,
                                                                                 uint32_t table_bytes) {
     extern __shared__ __align__(16) uint8_t smem[];
     stage_table(reinterpret_cast<uint4 *>(smem), reinterpret_cast<const uint4 *>(g_table), table_bytes / 16u);
-    SparseStep st{smem, reinterpret_cast<const uint4 *>(smem + 256)};
-    walk_chunk<G, SparseStep, ALIGNED, 64, MODE>(st, a, nullptr, (uint64_t)blockIdx.x * kWalkThreads);
+    SparseStep<RAW> st{smem, reinterpret_cast<const uint4 *>(smem + 256)};
+    walk_chunk<G, SparseStep<RAW>, ALIGNED, 64, MODE>(st, a, nullptr, (uint64_t)blockIdx.x * kWalkThreads);
 }
 
 template <int G, int B, bool ALIGNED, uint32_t TILE, int MODE>
@@ -130,16 +130,22 @@ inline void launch_walk_class(const DeviceDfa &d, const PlainPlan &p, const Walk
 }
 
 // no text staging: the LDS holds the table alone
-template <bool ALIGNED, int MODE>
-inline void launch_walk_sparse(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, hipStream_t stream) {
+template <bool ALIGNED, int MODE, bool RAW>
+inline void launch_walk_sparse_t(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, hipStream_t stream) {
     const uint32_t grid = (uint32_t)((p.chunks + kWalkThreads - 1) / kWalkThreads);
     const size_t lds = d.table_bytes;
     const uint8_t *tab = reinterpret_cast<const uint8_t *>(d.d_table);
-#define PAREM_SPR(GG)                                                                                          \
-    hipLaunchKernelGGL((k_walk_sparse<GG, ALIGNED, MODE>), dim3(grid), dim3(kWalkThreads), lds, stream, a, tab, \
+#define PAREM_SPR(GG)                                                                                               \
+    hipLaunchKernelGGL((k_walk_sparse<GG, ALIGNED, MODE, RAW>), dim3(grid), dim3(kWalkThreads), lds, stream, a, tab, \
                        d.table_bytes)
     PAREM_GROUP_SWITCH(PAREM_SPR)
 #undef PAREM_SPR
+}
+
+template <bool ALIGNED, int MODE>
+inline void launch_walk_sparse(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, hipStream_t stream) {
+    if (d.sparse_raw) launch_walk_sparse_t<ALIGNED, MODE, true>(d, p, a, stream);
+    else launch_walk_sparse_t<ALIGNED, MODE, false>(d, p, a, stream);
 }
 
 template <int LAYOUT, bool ALIGNED, uint32_t TILE, int MODE>
