@@ -148,13 +148,28 @@ bool sparse_rows(const DeviceDfa &d, const std::vector<uint32_t> &t, std::vector
 // in LDS rows); fills `order` with the states by decreasing weight.
 double hot_share(const DeviceDfa &d, const std::vector<uint32_t> &t, std::vector<uint32_t> &order) {
     const uint32_t Q = d.Q, A = d.A;
+    // each row as (target, share of its columns): rows of large sparse tables
+    // have few distinct targets, so the iterations touch far fewer entries
+    std::vector<uint32_t> roff(Q + 1, 0), tgt;
+    std::vector<double> wt;
+    std::vector<uint32_t> row(A);
+    for (uint32_t q = 0; q < Q; ++q) {
+        std::copy(t.begin() + (size_t)q * A, t.begin() + (size_t)(q + 1) * A, row.begin());
+        std::sort(row.begin(), row.end());
+        for (uint32_t a = 0; a < A;) {
+            uint32_t b = a;
+            while (b < A && row[b] == row[a]) ++b;
+            tgt.push_back(row[a]);
+            wt.push_back((double)(b - a) / A);
+            a = b;
+        }
+        roff[q + 1] = (uint32_t)tgt.size();
+    }
     std::vector<double> pi(Q, 1.0 / Q), nx(Q), acc(Q, 0.0);
     for (int it = 0; it < 48; ++it) {
         std::fill(nx.begin(), nx.end(), 0.0);
-        for (uint32_t q = 0; q < Q; ++q) {
-            const double w = pi[q] / A;
-            for (uint32_t a = 0; a < A; ++a) nx[t[(size_t)q * A + a]] += w;
-        }
+        for (uint32_t q = 0; q < Q; ++q)
+            for (uint32_t k = roff[q]; k < roff[q + 1]; ++k) nx[tgt[k]] += pi[q] * wt[k];
         pi.swap(nx);
         if (it >= 16)
             for (uint32_t q = 0; q < Q; ++q) acc[q] += pi[q];
@@ -405,9 +420,14 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
     const bool hot_ok = d.Q + 1 <= 0x3fffu;  // kHotFlag | id stays below kHotLost
     const bool class_ok = 256 + (uint64_t)(d.Q + 1) * (d.A + 1) * 2 <= parem::kClassLdsMax;
     std::vector<uint32_t> hot_order;
-    // automatic choice: k-gram, LDS byte table, column-indexed LDS table, hot
-    // rows only when they hold most of the walk's weight, else through L2
-    const bool hot_auto = hot_ok && !kg_ok && !lds_ok && !class_ok && hot_share(d, t, hot_order) >= 0.9;
+    // automatic choice: k-gram, LDS byte table, column-indexed LDS table, then
+    // sparse rows when every row qualifies (checked once), hot rows only when
+    // they hold most of the walk's weight, else the byte table through L2
+    std::vector<uint8_t> sparse_image;
+    const bool big_auto = layout == PAREM_LAYOUT_AUTO && !kg_ok && !lds_ok && !class_ok;
+    const bool sparse_ok = (big_auto || layout == PAREM_LAYOUT_SPARSE_LDS) && sparse_rows(d, t, sparse_image);
+    const bool hot_auto = hot_ok && !kg_ok && !lds_ok && !class_ok && !(big_auto && sparse_ok) &&
+                          hot_share(d, t, hot_order) >= 0.9;
     const uint32_t big = hot_auto ? PAREM_LAYOUT_HOT_LDS : PAREM_LAYOUT_BYTE_GLOBAL;
     if (layout == PAREM_LAYOUT_AUTO || (layout == PAREM_LAYOUT_KGRAM_LDS && !kg_ok))
         layout = kg_ok ? PAREM_LAYOUT_KGRAM_LDS
@@ -418,11 +438,8 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
     // sparse rows: asked for, or chosen automatically when no dense table fits
     // LDS, and only when every row has a default and at most kSparseExc other
     // columns (the invalid column counts unless every byte is in the alphabet)
-    std::vector<uint8_t> sparse_image;
-    if (layout == PAREM_LAYOUT_SPARSE_LDS && !sparse_rows(d, t, sparse_image))
-        layout = class_ok ? PAREM_LAYOUT_CLASS_LDS : big;
-    if ((o.layout == PAREM_LAYOUT_AUTO) && !kg_ok && !lds_ok && !class_ok && sparse_rows(d, t, sparse_image))
-        layout = PAREM_LAYOUT_SPARSE_LDS;
+    if (layout == PAREM_LAYOUT_SPARSE_LDS && !sparse_ok) layout = class_ok ? PAREM_LAYOUT_CLASS_LDS : big;
+    if (big_auto && sparse_ok) layout = PAREM_LAYOUT_SPARSE_LDS;
     d.layout = layout;
     if (layout == PAREM_LAYOUT_SPARSE_LDS) {
         bool all_valid = true;
