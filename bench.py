@@ -221,10 +221,10 @@ def bench_sparse(args):
     for name, kw in (("hot_rows", {"layout": P.LAYOUT_HOT_LDS}), ("byte_l2", {"layout": P.LAYOUT_BYTE_GLOBAL}),
                      ("hot_rows_lookback64", {"layout": P.LAYOUT_HOT_LDS, "lookback": 64}),
                      ("sparse_rows", {"layout": S}),
-                     ("sparse_rows_g4", {"layout": S, "group": 4}),
-                     ("sparse_rows_g16", {"layout": S, "group": 16}),
+                     ("sparse_rows_g2", {"layout": S, "group": 2}),
+                     ("sparse_rows_g8", {"layout": S, "group": 8}),
                      ("sparse_rows_lookback4", {"layout": S, "lookback": 4}),
-                     ("sparse_rows_L16k", {"layout": S, "chunk_len": 16384})):
+                     ("sparse_rows_L32k", {"layout": S, "chunk_len": 32768})):
         m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, **kw)
         res_t = torch.empty(P.RESULT_BYTES, dtype=torch.uint8, device="cuda")
         ms = event_times(lambda: m.match_async(dev, res_t), max(3, args.steps // 4), stream)

@@ -79,20 +79,25 @@ std::vector<E> byte_table(const DeviceDfa &d, const std::vector<uint32_t> &t, ui
     return out;
 }
 
-// Sparse rows: LDS image [256 B byte -> column][(Q+1) rows of 16 B]. Row q:
-// word 0 the columns of four exceptions (one byte each), words 1-2 their
-// entries, word 3 the default entry in its low half; an entry is the next
-// state | final << 15. Unused exception slots repeat a column with its own
-// entry, so a column not among the exceptions always has the default. The
+// Sparse rows: LDS image [256 B byte -> column][rows of kSparseRow = 16 B].
+// Row q: word 0 the keys of four exceptions (one byte each), words 1-2 their
+// entries (u16 each), word 3 the default entry in its low half and the final
+// flag of q in its high half. An entry is the next state's row offset
+// (16 * id), so every reachable row must start below 64 KiB: Q + 1 <= 4096
+// rows, or Q = 4096 when every byte is valid (the sentinel row is then
+// unreachable and left out). Unused exception slots repeat a key with its
+// own entry, so a key not among the exceptions always has the default. The
 // default is the row's most frequent next state. False when some row has
-// more than kSparseExc other columns or the image exceeds kSparseLdsMax.
+// more than kSparseExc other columns or the rows do not fit.
 bool sparse_rows(const DeviceDfa &d, const std::vector<uint32_t> &t, std::vector<uint8_t> &image) {
     // the invalid column A is reachable only when some byte is outside the alphabet
     bool invalid_used = false;
     for (uint32_t x = 0; x < 256; ++x) invalid_used |= d.cls[x] >= d.A;
     const uint32_t ncol = d.A + (invalid_used ? 1u : 0u);
-    if (ncol > 256 || d.Q + 1 > 0x7fffu) return false;
-    const size_t bytes = 256 + (size_t)(d.Q + 1) * 16;
+    if (ncol > 256) return false;
+    const uint32_t nrows = std::min<uint32_t>(d.Q + 1, 65536 / parem::kSparseRow);
+    if (d.Q + 1 > nrows && (invalid_used || d.Q > nrows)) return false;
+    const size_t bytes = 256 + (size_t)nrows * parem::kSparseRow;
     if (bytes > parem::kSparseLdsMax) return false;
     image.assign(bytes, 0);
     for (uint32_t x = 0; x < 256; ++x) image[x] = (uint8_t)d.cls[x];
@@ -103,7 +108,7 @@ bool sparse_rows(const DeviceDfa &d, const std::vector<uint32_t> &t, std::vector
     if (!invalid_used)
         for (uint32_t x = 0; x < 256; ++x) key[d.cls[x]] = (uint8_t)x;
     std::vector<uint32_t> next(ncol), count(d.Q + 1, 0);
-    for (uint32_t q = 0; q <= d.Q; ++q) {
+    for (uint32_t q = 0; q < nrows; ++q) {
         for (uint32_t a = 0; a < ncol; ++a) next[a] = (q < d.Q && a < d.A) ? t[(size_t)q * d.A + a] : d.sent;
         uint32_t dflt = next[0], best = 0;
         for (uint32_t a = 0; a < ncol; ++a)
@@ -112,9 +117,9 @@ bool sparse_rows(const DeviceDfa &d, const std::vector<uint32_t> &t, std::vector
                 dflt = next[a];
             }
         for (uint32_t a = 0; a < ncol; ++a) count[next[a]] = 0;
-        auto entry = [&](uint32_t nx) { return (uint16_t)(nx | ((uint32_t)d.final_flag[nx] << 15)); };
+        auto entry = [&](uint32_t nx) { return nx * parem::kSparseRow; };
         uint8_t col[parem::kSparseExc];
-        uint16_t ent[parem::kSparseExc];
+        uint32_t ent[parem::kSparseExc];
         uint32_t ne = 0;
         for (uint32_t a = 0; a < ncol; ++a) {
             if (next[a] == dflt) continue;
@@ -127,13 +132,12 @@ bool sparse_rows(const DeviceDfa &d, const std::vector<uint32_t> &t, std::vector
             col[k] = key[0];
             ent[k] = entry(next[0]);
         }
-        uint8_t *row = image.data() + 256 + (size_t)q * 16;
-        for (uint32_t k = 0; k < parem::kSparseExc; ++k) {
-            row[k] = col[k];
-            std::memcpy(row + 4 + 2 * k, &ent[k], 2);
-        }
-        const uint16_t de = entry(dflt);
-        std::memcpy(row + 12, &de, 2);
+        uint8_t *row = image.data() + 256 + (size_t)q * parem::kSparseRow;
+        const uint32_t w[4] = {(uint32_t)col[0] | (uint32_t)col[1] << 8 | (uint32_t)col[2] << 16 |
+                                   (uint32_t)col[3] << 24,
+                               ent[0] | ent[1] << 16, ent[2] | ent[3] << 16,
+                               entry(dflt) | (uint32_t)d.final_flag[q] << 16};
+        std::memcpy(row, w, sizeof(w));
     }
     return true;
 }

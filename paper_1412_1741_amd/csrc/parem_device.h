@@ -7,12 +7,17 @@
 #include "parem_internal.h"
 
 #include <algorithm>
+#include <type_traits>
 #include <utility>
 
 namespace parem {
 
 
 constexpr int kWalkThreads = 256;
+// the sparse-row walk: one 1024-thread workgroup per CU, four waves per SIMD
+// (measured: a second workgroup per CU does not become resident, and a
+// register cap for more waves spills)
+constexpr int kSparseThreads = 1024;
 constexpr int kComposeThreads = 256;
 // A staged tile holds TILE bytes of each of a wave's 64 chunks; LDS rows are
 // TILE + 16 bytes apart so that 8 consecutive lanes' 16-byte reads hit
@@ -31,6 +36,14 @@ struct Stage {
 // offset is an LDS address: the read needs no base addition.
 __device__ __forceinline__ uint32_t lds_u16_abs(uint32_t addr) {
     return *reinterpret_cast<const __attribute__((address_space(3))) uint16_t *>(static_cast<uintptr_t>(addr));
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// T (a scalar or ext_vector_type) at LDS byte address `addr`
+template <typename T>
+__device__ __forceinline__ T lds_abs(uint32_t addr) {
+    return *reinterpret_cast<const __attribute__((address_space(3))) T *>(static_cast<uintptr_t>(addr));
 }
 
 __device__ __forceinline__ uint32_t lds_u16(const uint8_t *base, uint32_t byte_off) {
@@ -125,48 +138,101 @@ struct ClassStep {
 // four column compares. The table leaves room for two workgroups per CU only
 // without the text staging area, so lanes load their chunks 16 bytes at a
 // time themselves (the lines stay in L2 between a lane's loads).
-// Sparse rows: per state a default entry and four (key, entry) exceptions in
-// one 16-byte LDS row. A key is the byte itself when every byte is valid
-// (RAW: no byte -> column read per step), else the byte's column.
+// Sparse rows: per state one 16-byte LDS row: the keys of four exceptions
+// (one byte each), their entries (u16 each), the default entry (u16) and
+// the final flag of the row's own state (u16). A key is the byte itself when
+// every byte is valid (RAW), else the byte's column. An entry is the next
+// state's row offset (16 * id), which is also the walk's state, so a step is
+// one 16-byte LDS read, four compares and four selects, and one add for the
+// count: the compares take the byte straight out of the text dword and the
+// selects take the 16-bit entries straight out of the row (SDWA operand
+// selects, written out below because the compiler extracts them with extra
+// instructions), and the row offset is the next read's address. The count
+// takes the flag of the state a step leaves, so it is shifted by one step:
+// it starts at minus the start state's flag and the end state's flag is
+// added when the walk is stored (kDeferredCount).
+//
+// One step: v = default; then v = entry i where key i equals the byte (keys
+// in row byte order, i = 0..3); c += own final flag. KSEL selects the byte
+// of `key` compared (BYTE_k of a text dword, or DWORD for a column). A
+// VALU write of VCC needs two wait states before v_cndmask reads it.
+#define PAREM_SPARSE_STEP(KSEL)                                                                                  \
+    asm("v_cmp_eq_u32_sdwa vcc, %1, %5 src0_sel:BYTE_0 src1_sel:" KSEL "\n\t"                                   \
+        "s_nop 1\n\t"                                                                                            \
+        "v_cndmask_b32_sdwa %0, %4, %2, vcc dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_0 src1_sel:WORD_0\n\t" \
+        "v_cmp_eq_u32_sdwa vcc, %1, %5 src0_sel:BYTE_1 src1_sel:" KSEL "\n\t"                                   \
+        "s_nop 1\n\t"                                                                                            \
+        "v_cndmask_b32_sdwa %0, %0, %2, vcc dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_1\n\t" \
+        "v_cmp_eq_u32_sdwa vcc, %1, %5 src0_sel:BYTE_2 src1_sel:" KSEL "\n\t"                                   \
+        "s_nop 1\n\t"                                                                                            \
+        "v_cndmask_b32_sdwa %0, %0, %3, vcc dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_0\n\t" \
+        "v_cmp_eq_u32_sdwa vcc, %1, %5 src0_sel:BYTE_3 src1_sel:" KSEL "\n\t"                                   \
+        "s_nop 1\n\t"                                                                                            \
+        "v_cndmask_b32_sdwa %0, %0, %3, vcc dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_1"    \
+        : "=&v"(v)                                                                                               \
+        : "v"(r.x), "v"(r.y), "v"(r.z), "v"(r.w), "v"(key)                                                       \
+        : "vcc")
+
 template <bool RAW>
 struct SparseStep {
     static constexpr bool kRedo = false;
     static constexpr bool kPrefixPasses = true;
-    static constexpr bool kStage = false;
-    const uint8_t *__restrict__ col;  // LDS: [256] byte -> column (unused when RAW)
-    const uint4 *__restrict__ rows;   // LDS: (Q+1) rows
+    static constexpr bool kStage = true;   // text staged through LDS when aligned (64-byte tiles)
+    static constexpr bool kDeferredCount = true;
+    // The kernel declares no static LDS: its dynamic LDS (the byte -> column
+    // map, then the rows) starts at LDS address 0, so row offset + kRows is
+    // the row's LDS address.
+    static constexpr uint32_t kRows = 256;
+    const uint8_t *__restrict__ col;   // LDS: [256] byte -> column (unused when RAW)
 
-    __device__ __forceinline__ uint32_t init(uint32_t s) const { return s; }
-    __device__ __forceinline__ uint32_t id(uint32_t r) const { return r; }
+    __device__ __forceinline__ uint32_t init(uint32_t s) const { return s * kSparseRow; }
+    __device__ __forceinline__ uint32_t id(uint32_t r) const { return r / kSparseRow; }
     __device__ __forceinline__ bool same(uint32_t a, uint32_t b) const { return a == b; }
-    __device__ __forceinline__ uint32_t key(uint32_t byte) const { return RAW ? byte : (uint32_t)col[byte]; }
-    __device__ __forceinline__ void one(uint32_t &s, uint32_t &c, uint32_t cl) const {
-        const uint4 r = rows[s];
-        uint32_t v = r.w;
-        v = (r.x & 0xffu) == cl ? r.y : v;
-        v = ((r.x >> 8) & 0xffu) == cl ? (r.y >> 16) : v;
-        v = ((r.x >> 16) & 0xffu) == cl ? r.z : v;
-        v = (r.x >> 24) == cl ? (r.z >> 16) : v;
-        c += (v >> 15) & 1u;
-        s = v & 0x7fffu;
+    __device__ __forceinline__ uint32_t fin(uint32_t r) const { return lds_abs<uint32_t>(kRows + r + 12) >> 16; }
+    // K = 0..3: compare byte K of `key` (a text dword); K = 4: `key` is a column
+    template <int K>
+    __device__ __forceinline__ void one(uint32_t &s, uint32_t &c, uint32_t key) const {
+        const u32x4 r = lds_abs<u32x4>(kRows + s);
+        uint32_t v;
+        if constexpr (K == 0) PAREM_SPARSE_STEP("BYTE_0");
+        else if constexpr (K == 1) PAREM_SPARSE_STEP("BYTE_1");
+        else if constexpr (K == 2) PAREM_SPARSE_STEP("BYTE_2");
+        else if constexpr (K == 3) PAREM_SPARSE_STEP("BYTE_3");
+        else PAREM_SPARSE_STEP("DWORD");
+        asm("v_add_u32_sdwa %0, %0, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_1"
+            : "+v"(c)
+            : "v"(r.w));
+        s = v;
+    }
+    template <int K, int G>
+    __device__ __forceinline__ void byte_of(uint32_t d, uint32_t (&R)[G], uint32_t (&c)[G], int nw) const {
+        if constexpr (RAW) {
+#pragma unroll
+            for (int j = 0; j < G; ++j)
+                if (j < nw) one<K>(R[j], c[j], d);
+        } else {
+            const uint32_t cl = col[(d >> (8 * K)) & 0xffu];
+#pragma unroll
+            for (int j = 0; j < G; ++j)
+                if (j < nw) one<4>(R[j], c[j], cl);
+        }
     }
     template <int G>
     __device__ __forceinline__ void dword(uint32_t d, uint32_t (&R)[G], uint32_t (&S)[G], uint32_t (&c)[G], int nw,
                                           uint32_t &bad) const {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t cl = key((d >> (8 * k)) & 0xffu);
-#pragma unroll
-            for (int j = 0; j < G; ++j)
-                if (j < nw) one(R[j], c[j], cl);
-        }
+        byte_of<0, G>(d, R, c, nw);
+        byte_of<1, G>(d, R, c, nw);
+        byte_of<2, G>(d, R, c, nw);
+        byte_of<3, G>(d, R, c, nw);
     }
     template <int G>
     __device__ __forceinline__ void flush(uint32_t (&S)[G], uint32_t (&c)[G], int nw) const {}
     __device__ __forceinline__ void byte(uint32_t x, uint32_t &R, uint32_t &c, uint32_t &bad) const {
-        one(R, c, key(x));
+        if constexpr (RAW) one<0>(R, c, x);
+        else one<4>(R, c, (uint32_t)col[x]);
     }
 };
+#undef PAREM_SPARSE_STEP
 
 // Hot-row layout: the byte-table rows of the H most visited states sit in
 // LDS, the other rows are read through L2. A walk carries its state encoded:
@@ -386,6 +452,26 @@ struct Positions {
     __device__ __forceinline__ uint32_t operator()(uint32_t idx) const { return sel ? (uint32_t)sel[idx] : idx; }
 };
 
+// Steppers with kDeferredCount count the final flag of the state a step
+// leaves: a walk's count starts at minus its start state's flag and gets its
+// end state's flag when stored. Others count the state a step enters.
+template <typename ST, typename = void>
+struct Deferred : std::false_type {};
+template <typename ST>
+struct Deferred<ST, std::void_t<decltype(ST::kDeferredCount)>> : std::bool_constant<ST::kDeferredCount> {};
+
+template <typename ST>
+__device__ __forceinline__ uint32_t count_start(const ST &st, uint32_t r) {
+    if constexpr (Deferred<ST>::value) return 0u - st.fin(r);
+    else return 0u;
+}
+
+template <typename ST>
+__device__ __forceinline__ uint32_t count_end(const ST &st, uint32_t r) {
+    if constexpr (Deferred<ST>::value) return st.fin(r);
+    else return 0u;
+}
+
 template <int G, typename ST>
 __device__ __forceinline__ void walks_init(const ST &st, Walks<G> &w, const uint32_t *__restrict__ list,
                                            const Positions &pos, uint32_t nwalk, uint32_t first) {
@@ -397,7 +483,7 @@ __device__ __forceinline__ void walks_init(const ST &st, Walks<G> &w, const uint
         const bool real = j > 0 && idx < nwalk;
         w.R[j] = real ? st.init(list[pos(idx)]) : lead;
         w.S[j] = 0;
-        w.c[j] = 0;
+        w.c[j] = count_start(st, w.R[j]);
         w.off[j] = 0;
         if (real && !st.same(w.R[j], lead)) w.pending |= 1u << j;
     }
@@ -543,7 +629,7 @@ __device__ __forceinline__ bool store_pass(const ST &st, const Walks<G> &w, cons
     bool differs = false;
     if (full) {
         lead_end = st.id(w.R[0]);
-        lead_cnt = w.c[0];
+        lead_cnt = w.c[0] + count_end(st, w.R[0]);
         out[(uint64_t)pos(0) * stride] = lead_end | (lead_cnt << 16);
     }
 #pragma unroll
@@ -553,7 +639,7 @@ __device__ __forceinline__ bool store_pass(const ST &st, const Walks<G> &w, cons
             uint32_t e, cn;
             if ((w.pending >> j) & 1u) {
                 e = st.id(w.R[j]);
-                cn = w.c[j];
+                cn = w.c[j] + count_end(st, w.R[j]);
                 differs |= e != lead_end;
             } else {
                 e = lead_end;
@@ -870,16 +956,18 @@ __device__ __forceinline__ void lookback_chunk(const LookArgs &a, uint32_t start
 }
 
 // copy the table into LDS with four 16-byte loads in flight per thread
+// (NT threads in the workgroup)
+template <uint32_t NT = kWalkThreads>
 __device__ __forceinline__ void stage_table(uint4 *dst, const uint4 *__restrict__ src, uint32_t n16) {
     // loads are unconditional (index clamped) so that they stay in registers
     // and are all in flight before the first store
-    for (uint32_t i0 = threadIdx.x; i0 < n16; i0 += 4 * kWalkThreads) {
+    for (uint32_t i0 = threadIdx.x; i0 < n16; i0 += 4 * NT) {
         uint4 v[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = src[min(i0 + (uint32_t)u * kWalkThreads, n16 - 1)];
+        for (int u = 0; u < 4; ++u) v[u] = src[min(i0 + (uint32_t)u * NT, n16 - 1)];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const uint32_t i = i0 + (uint32_t)u * kWalkThreads;
+            const uint32_t i = i0 + (uint32_t)u * NT;
             if (i < n16) dst[i] = v[u];
         }
     }

@@ -83,7 +83,8 @@ struct DeviceDfa {
 // padding that shifts successive rows by one LDS bank)
 constexpr uint32_t kHotMax = 32;
 constexpr uint32_t kClassLdsMax = 48 * 1024;  // largest column-indexed LDS table
-constexpr uint32_t kSparseLdsMax = 80 * 1024; // largest sparse-row LDS table (two workgroups per CU)
+constexpr uint32_t kSparseRow = 16;             // bytes per sparse row
+constexpr uint32_t kSparseLdsMax = 256 + 65536; // largest sparse-row LDS image (row offsets are u16)
 constexpr uint32_t kSparseExc = 4;            // exceptions per sparse row
 constexpr uint32_t kHotRow = 258;
 constexpr uint32_t kHotFlag = 0x4000u;  // cold state: kHotFlag | id; hot state: its slot

@@ -588,8 +588,9 @@ parem_status plan_chunks(const DeviceDfa &d, uint64_t len, const parem_options &
     uint32_t L = o.chunk_len;
     if (L == 0) {
         // about 2^17 chunks for large texts (two 256-lane workgroups per CU
-        // on a 1 GiB text), at least 256 bytes each
-        uint64_t want = len >> 17;
+        // on a 1 GiB text), 2^18 for sparse rows (one 1024-lane workgroup
+        // per CU), at least 256 bytes each
+        uint64_t want = len >> (d.layout == PAREM_LAYOUT_SPARSE_LDS ? 18 : 17);
         L = 256;
         while ((uint64_t)L < want && L < kMaxChunk) L <<= 1;
     }
@@ -601,7 +602,9 @@ parem_status plan_chunks(const DeviceDfa &d, uint64_t len, const parem_options &
     q.tile = o.tile ? o.tile : 128;
     q.merge = o.no_merge ? 0u : 1u;
     if (q.tile != 64 && q.tile != 128) return PAREM_EINVAL;
-    uint32_t G = o.group ? o.group : 8;
+    // sparse rows: four runs a pass keep the walk within 128 registers (four
+    // waves per SIMD); their followers merge within a few bytes
+    uint32_t G = o.group ? o.group : (d.layout == PAREM_LAYOUT_SPARSE_LDS ? 4 : 8);
     if (G != 2 && G != 4 && G != 8 && G != 16) return PAREM_EINVAL;
     q.G = G;
     uint32_t P = 256;

@@ -60,15 +60,15 @@ __global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_walk_class(W
     walk_chunk<G, ClassStep, ALIGNED, TILE, MODE>(st, a, smem + table_bytes, (uint64_t)blockIdx.x * kWalkThreads);
 }
 
-// the table limits a CU to two workgroups: registers for two
+// one workgroup of kSparseThreads per CU: four waves per SIMD
 template <int G, bool ALIGNED, int MODE, bool RAW>
-__global__ __launch_bounds__(kWalkThreads, 2) void k_walk_sparse(WalkArgs a,
-                                                                                const uint8_t *__restrict__ g_table,
-                                                                                uint32_t table_bytes) {
+__global__ __launch_bounds__(kSparseThreads) void k_walk_sparse(WalkArgs a, const uint8_t *__restrict__ g_table,
+                                                                uint32_t table_bytes) {
     extern __shared__ __align__(16) uint8_t smem[];
-    stage_table(reinterpret_cast<uint4 *>(smem), reinterpret_cast<const uint4 *>(g_table), table_bytes / 16u);
-    SparseStep<RAW> st{smem, reinterpret_cast<const uint4 *>(smem + 256)};
-    walk_chunk<G, SparseStep<RAW>, ALIGNED, 64, MODE>(st, a, nullptr, (uint64_t)blockIdx.x * kWalkThreads);
+    stage_table<kSparseThreads>(reinterpret_cast<uint4 *>(smem), reinterpret_cast<const uint4 *>(g_table),
+                                table_bytes / 16u);
+    SparseStep<RAW> st{smem};
+    walk_chunk<G, SparseStep<RAW>, ALIGNED, 64, MODE>(st, a, smem + table_bytes, (uint64_t)blockIdx.x * kSparseThreads);
 }
 
 template <int G, int B, bool ALIGNED, uint32_t TILE, int MODE>
@@ -129,15 +129,15 @@ inline void launch_walk_class(const DeviceDfa &d, const PlainPlan &p, const Walk
 #undef PAREM_CLS
 }
 
-// no text staging: the LDS holds the table alone
+// the table, then (aligned texts) a 64-byte text tile per wave
 template <bool ALIGNED, int MODE, bool RAW>
 inline void launch_walk_sparse_t(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, hipStream_t stream) {
-    const uint32_t grid = (uint32_t)((p.chunks + kWalkThreads - 1) / kWalkThreads);
-    const size_t lds = d.table_bytes;
+    const uint32_t grid = (uint32_t)((p.chunks + kSparseThreads - 1) / kSparseThreads);
+    const size_t lds = d.table_bytes + ((ALIGNED && MODE != WALK_REDO) ? (kSparseThreads / 64) * Stage<64>::kWave : 0);
     const uint8_t *tab = reinterpret_cast<const uint8_t *>(d.d_table);
-#define PAREM_SPR(GG)                                                                                               \
-    hipLaunchKernelGGL((k_walk_sparse<GG, ALIGNED, MODE, RAW>), dim3(grid), dim3(kWalkThreads), lds, stream, a, tab, \
-                       d.table_bytes)
+#define PAREM_SPR(GG)                                                                                           \
+    hipLaunchKernelGGL((k_walk_sparse<GG, ALIGNED, MODE, RAW>), dim3(grid), dim3(kSparseThreads), lds, stream, a, \
+                       tab, d.table_bytes)
     PAREM_GROUP_SWITCH(PAREM_SPR)
 #undef PAREM_SPR
 }
