@@ -7,6 +7,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# test_sanitizers.py runs the oracle's pins again on a sanitized build of the oracle
+if os.environ.get("PAREM_ORACLE_LIB"):
+    import oracle
+
+    oracle._LIB = os.environ["PAREM_ORACLE_LIB"]
+
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
