@@ -127,7 +127,7 @@ def bench_small(args):
     import oracle
     import paper_1412_1741_amd as P
     import workloads as W
-    dfa, text, chunks = W.config1()
+    dfa, text, chunks = W.random8()
     L = text.size // chunks
     dev = torch.from_numpy(text).cuda()
     m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, chunk_len=L)
@@ -210,7 +210,7 @@ def bench_sparse(args):
     import workloads as W
 
     log(f"sparse: generating {args.sparse_size} bytes")
-    dfa, text = W.config3(n=args.sparse_size)
+    dfa, text = W.sparse4096(n=args.sparse_size)
     dev = torch.from_numpy(text).cuda()
     del text
     stream = torch.cuda.current_stream()
@@ -256,14 +256,14 @@ def bench_batch(args):
     import workloads as W
     from paper_1412_1741_amd.autotune import Autotuner
 
-    specs = W.config5_specs()[: args.batch_pairs]
+    specs = W.batch_specs()[: args.batch_pairs]
     log(f"batch: generating {len(specs)} pairs")
     t0 = time.perf_counter()
     order = np.argsort([s.text_len for s in specs])
     sample = set(int(i) for i in order[: len(order) // 2: 16]) | set(int(i) for i in order[-4:])
     dfas, devs, host = [], [], {}
     with cf.ThreadPoolExecutor(16) as ex:
-        for i, (dfa, text) in enumerate(ex.map(W.config5_pair, specs)):
+        for i, (dfa, text) in enumerate(ex.map(W.batch_pair, specs)):
             dfas.append(dfa)
             devs.append(torch.from_numpy(text).cuda())
             if i in sample:
@@ -340,7 +340,7 @@ def bench_learned(args, m, dfa, dev, stream, steps):
     import paper_1412_1741_amd as P
     import workloads as W
     log("training the proposal")
-    _, train_text = W.config4_train_text()
+    _, train_text = W.motif_train_text()
     tdev = torch.from_numpy(train_text).cuda()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -436,7 +436,7 @@ def main():
     import workloads as W
 
     log(f"generating workload n={args.size}")
-    dfa, text = W.config2(n=args.size)
+    dfa, text = W.dna_motif(n=args.size)
     dev = torch.from_numpy(text).cuda()
     torch.cuda.synchronize()
     m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, chunk_len=args.chunk_len,

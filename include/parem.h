@@ -43,7 +43,7 @@ typedef enum {
     PAREM_EDEVICE = -3,     /* a HIP runtime call failed                  */
     PAREM_ESYMBOL = -4,     /* a text byte is not in the alphabet         */
     PAREM_ESTATE = -5,      /* a table entry / start / final id >= Q      */
-    PAREM_EUNSUPPORTED = -6,/* sizes beyond what this build handles       */
+    PAREM_EUNSUPPORTED = -6,/* sizes or options the library does not take */
     PAREM_ESYNTAX = -7      /* a regular expression does not parse        */
 } parem_status;
 

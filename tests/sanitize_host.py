@@ -40,14 +40,14 @@ def expect(status, allowed, what):
 rng = np.random.default_rng(12)
 cases = [
     ("table I", W.TABLE1.astype(np.uint32), W.PAREL, 0, [5]),
-    ("dna motif", W.config2_dfa().table, b"ACGT", 0, W.config2_dfa().accepting),
-    ("sparse 4096", W.config3_dfa().table, bytes(range(256)), 0, W.config3_dfa().accepting),
+    ("dna motif", W.dna_motif_dfa().table, b"ACGT", 0, W.dna_motif_dfa().accepting),
+    ("sparse 4096", W.sparse4096_dfa().table, bytes(range(256)), 0, W.sparse4096_dfa().accepting),
 ]
 for q, a in ((3, 1), (40, 4), (300, 20), (1200, 4), (2500, 4), (70, 256)):
     d = W.random_dense_dfa(rng, q, bytes(rng.choice(256, size=a, replace=False).astype(np.uint8)), 3)
     cases.append((f"dense {q}x{a}", d.table, d.alphabet, d.start, d.accepting))
-for spec in W.config5_specs()[:40:3]:
-    d, _ = W.config5_pair(spec, with_text=False)
+for spec in W.batch_specs()[:40:3]:
+    d, _ = W.batch_pair(spec, with_text=False)
     cases.append((f"batch pair {spec.index}", d.table, d.alphabet, d.start, d.accepting))
 
 options = [{}, {"layout": P.LAYOUT_BYTE_GLOBAL}, {"layout": P.LAYOUT_HOT_LDS}, {"layout": P.LAYOUT_CLASS_LDS},

@@ -251,10 +251,10 @@ def test_batch_uneven_4096_full_size():
 
     from paper_1412_1741_amd.autotune import Autotuner
 
-    specs = W.config5_specs()
+    specs = W.batch_specs()
 
     def make(spec):
-        dfa, text = W.config5_pair(spec)
+        dfa, text = W.batch_pair(spec)
         want = oracle.walk_dfa(dfa, text)
         return dfa, text, (want.final_state, want.accept, want.count)
 
@@ -288,7 +288,7 @@ def test_batch_learned_pairs():
     replays with new texts (new pointers re-capture the graph)."""
     rng = np.random.default_rng(77)
     pairs = random_pairs(606, 12, max_states=300, max_len=200_000)
-    dna, dtext = W.config2(n=(1 << 20) + 13)
+    dna, dtext = W.dna_motif(n=(1 << 20) + 13)
     dense = W.random_dense_dfa(rng, 1200, bytes(rng.choice(256, size=4, replace=False).astype(np.uint8)),
                                num_accepting=40)
     pairs += [(dna, dtext), (dense, W.uniform_text(rng, dense.alphabet, 300_000))]

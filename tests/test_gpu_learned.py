@@ -73,7 +73,7 @@ def oracle_params_bf16(flat, states):
 @pytest.mark.parametrize("L", [64, 128, 1024])
 def test_boundary_states_match_oracle(L):
     rng = np.random.default_rng(L)
-    cases = [W.config2(n=1 << 20, copies=300)]
+    cases = [W.dna_motif(n=1 << 20, copies=300)]
     for _ in range(4):
         cases.append(W.random_case(rng, max_states=60, max_alpha=6, max_len=300000))
     q = 7
@@ -118,7 +118,7 @@ def random_params(states, seed):
 
 
 def test_forward_logits_match_oracle():
-    dfa, text = W.config2(n=1 << 18, copies=100)
+    dfa, text = W.dna_motif(n=1 << 18, copies=100)
     states = dfa.num_states
     params = random_params(states, 5)
     m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting)
@@ -164,12 +164,12 @@ def head_case(kind):
     fused inference), a dense random 1200-state DFA over ACGT and the
     4096-state sparse byte DFA (unfused inference: heads over 64 states)."""
     if kind == "motif35":
-        return W.config2(n=1 << 18, copies=100)
+        return W.dna_motif(n=1 << 18, copies=100)
     if kind == "dense1200":
         rng = np.random.default_rng(1200)
         dfa = W.random_dense_dfa(rng, 1200, b"ACGT", num_accepting=19)
         return dfa, W.uniform_text(rng, b"ACGT", 1 << 18)
-    return W.config3(n=1 << 20)
+    return W.sparse4096(n=1 << 20)
 
 
 @pytest.mark.parametrize("kind,batch", [("motif35", 512), ("dense1200", 512), ("sparse4096", 256)])
@@ -247,7 +247,7 @@ def test_training_on_text_with_invalid_bytes():
     after them have no state and are left out of the labels; training runs,
     its loss and weights stay finite, and matching that text still reports
     the invalid byte."""
-    dfa, text = W.config4_train_text(n=4 << 20)
+    dfa, text = W.motif_train_text(n=4 << 20)
     text = text.copy()
     rng = np.random.default_rng(8)
     text[rng.integers(1000, text.size - 1000, size=40)] = ord("N")
@@ -308,7 +308,7 @@ def test_adamw_matches_oracle():
 
 
 def test_training_lowers_loss_and_predicts():
-    dfa, text = W.config4_train_text(n=16 << 20)
+    dfa, text = W.motif_train_text(n=16 << 20)
     states = dfa.num_states
     m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting)
     td = dev(text)
@@ -317,7 +317,7 @@ def test_training_lowers_loss_and_predicts():
     say(f"[train] {hist}")
     assert hist[-1][1] < 0.5 * hist[0][1]
     # held-out boundaries of the benchmark text distribution
-    _, test_text = W.config2(n=1 << 20, copies=100)
+    _, test_text = W.dna_motif(n=1 << 20, copies=100)
     pos = np.arange(64, test_text.size, 64, dtype=np.uint64)
     want, _ = oracle.states_at(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, test_text, pos)
     z = prop.logits(dev(test_text), pos).cpu().numpy()
@@ -437,8 +437,8 @@ def learned_case(name, dfa, text, params, mm, chunk_len=0, **opts):
 
 @pytest.mark.parametrize("mm", [1, 4, 16])
 def test_learned_exact_untrained(mm):
-    dfa, text = W.config2(n=4 << 20)
-    got = learned_case("config2 untrained", dfa, text, random_params(dfa.num_states, 3), mm, chunk_len=2048)
+    dfa, text = W.dna_motif(n=4 << 20)
+    got = learned_case("dna_motif untrained", dfa, text, random_params(dfa.num_states, 3), mm, chunk_len=2048)
     assert got.chunks == 2048
     if mm >= 16:
         assert got.rerun_chunks <= got.chunks
@@ -447,7 +447,7 @@ def test_learned_exact_untrained(mm):
 def test_learned_reruns_equal_misses():
     """m = 1 on the motif automaton (runs merge: every map is uniform): a chunk
     is walked again exactly when its true entry state was not selected."""
-    dfa, text = W.config2(n=2 << 20)
+    dfa, text = W.dna_motif(n=2 << 20)
     L = 1024
     params = random_params(dfa.num_states, 7)
     m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, chunk_len=L)
@@ -477,7 +477,7 @@ def test_learned_subchunk_rewalk(n, L):
     """Chunks walked again from their whole set: up to 2048 marked chunks a
     round are walked in sub-chunks (64, or single bytes in a tail under 64),
     more go to the whole-set walk; ragged tails, both ways exact."""
-    dfa, text = W.config2(n=n, copies=100)
+    dfa, text = W.dna_motif(n=n, copies=100)
     got = learned_case(f"sub-chunk re-walk n={n} L={L}", dfa, text, random_params(dfa.num_states, 17), 1,
                        chunk_len=L)
     assert got.rerun_chunks > 0
@@ -521,7 +521,7 @@ def test_learned_fuzz_and_invalid():
         params = random_params(dfa.num_states, i)
         for mm in (1, 5):
             learned_case(f"fuzz {i}", dfa, text, params, mm, chunk_len=int(rng.choice([64, 256, 1024])))
-    dfa, text = W.config2(n=1 << 20, copies=200)
+    dfa, text = W.dna_motif(n=1 << 20, copies=200)
     text = text.copy()
     text[70000] = ord("N")
     m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, chunk_len=1024)
@@ -536,11 +536,11 @@ def test_learned_fuzz_and_invalid():
 def test_learned_gain_over_plain_speculation():
     """What the trained network buys: one walk per chunk instead of the whole
     speculated set, with almost no chunk walked again, and the same result."""
-    dfa, train_text = W.config4_train_text(n=16 << 20)
+    dfa, train_text = W.motif_train_text(n=16 << 20)
     m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, chunk_len=2048)
     prop, hist = P.train_proposal(m, dev(train_text), W.mlp_init_params(dfa.num_states), steps=300, batch=2048,
                                   lr=2e-3, log_every=100, seed=2)
-    _, text = W.config2(n=8 << 20)
+    _, text = W.dna_motif(n=8 << 20)
     td = dev(text)
     plain = m.match(td)
     learned = m.match_learned(prop, td, 1)

@@ -70,18 +70,18 @@ def test_worked_example():
         run_case(f"example L={L}", dfa, text, chunk_len=L)
 
 
-def test_config1_full():
-    dfa, text, chunks = W.config1()
-    got = run_case("config1", dfa, text, chunk_len=text.size // chunks)
+def test_random8_full():
+    dfa, text, chunks = W.random8()
+    got = run_case("random8", dfa, text, chunk_len=text.size // chunks)
     assert got.chunks == 1024
     ref = oracle.parem(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, text, chunks)
     assert got.spec_runs == ref.runs
 
 
 @pytest.mark.parametrize("group", [2, 4, 8, 16])
-def test_config2_small_groups(group):
-    dfa, text = W.config2(n=4 << 20)
-    run_case(f"config2 4MiB G={group}", dfa, text, chunk_len=1024, group=group)
+def test_dna_motif_small_groups(group):
+    dfa, text = W.dna_motif(n=4 << 20)
+    run_case(f"dna_motif 4MiB G={group}", dfa, text, chunk_len=1024, group=group)
 
 
 
@@ -90,11 +90,11 @@ def all_layouts():
             P.LAYOUT_CLASS_LDS]
 
 
-def test_config2_layouts():
-    dfa, text = W.config2(n=1 << 22)
+def test_dna_motif_layouts():
+    dfa, text = W.dna_motif(n=1 << 22)
     for lay in all_layouts():
         for g in (4, 16):
-            run_case(f"config2 layout={lay} G={g}", dfa, text, chunk_len=2048, layout=lay, group=g)
+            run_case(f"dna_motif layout={lay} G={g}", dfa, text, chunk_len=2048, layout=lay, group=g)
     m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting)
     assert m.describe()["layout"] == P.LAYOUT_KGRAM_LDS and m.describe()["kgram"] == 4
     m.close()
@@ -134,17 +134,17 @@ def test_kgram_invalid_bytes():
 
 
 @pytest.mark.parametrize("tile", [64, 128])
-def test_config2_no_merge(tile):
+def test_dna_motif_no_merge(tile):
     """The paper's plain scheme: every speculated run walks its whole chunk."""
-    dfa, text = W.config2(n=1 << 22)
+    dfa, text = W.dna_motif(n=1 << 22)
     for g in (4, 16):
-        run_case(f"config2 no-merge G={g} tile={tile}", dfa, text, chunk_len=4096, group=g, no_merge=True,
+        run_case(f"dna_motif no-merge G={g} tile={tile}", dfa, text, chunk_len=4096, group=g, no_merge=True,
                  tile=tile)
 
 
-def test_config2_full_size():
-    dfa, text = W.config2()
-    got = run_case("config2 1GiB", dfa, text)
+def test_dna_motif_full_size():
+    dfa, text = W.dna_motif()
+    got = run_case("dna_motif 1GiB", dfa, text)
     assert got.chunks >= 1024
 
 
@@ -311,7 +311,7 @@ def test_invalid_bytes():
 
 
 def test_host_text_path():
-    dfa, text = W.config2(n=1 << 20)
+    dfa, text = W.dna_motif(n=1 << 20)
     m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting)
     got = m.match(text)
     want = oracle.walk_dfa(dfa, text)
@@ -337,29 +337,29 @@ def test_compile_errors():
     assert ei.value.status == P.PAREM_EINVAL
 
 
-def test_config3_reduced():
-    dfa, text = W.config3(n=64 << 20)
-    run_case("config3 64MiB", dfa, text)
+def test_sparse4096_reduced():
+    dfa, text = W.sparse4096(n=64 << 20)
+    run_case("sparse4096 64MiB", dfa, text)
     m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting)
     assert m.describe()["layout"] == P.LAYOUT_SPARSE_LDS
     m.close()
-    run_case("config3 64MiB hot rows", dfa, text, layout=P.LAYOUT_HOT_LDS)
+    run_case("sparse4096 64MiB hot rows", dfa, text, layout=P.LAYOUT_HOT_LDS)
 
 
-def test_config5_sample_pairs():
-    specs = W.config5_specs()
+def test_batch_sample_pairs():
+    specs = W.batch_specs()
     rng = np.random.default_rng(0)
     picks = sorted(rng.choice(len(specs), size=12, replace=False).tolist())
     for i in picks:
         s = specs[i]
         if s.text_len > (8 << 20):
             s = W.PairSpec(s.index, s.num_states, s.alphabet_size, 8 << 20)
-        dfa, text = W.config5_pair(s)
-        run_case(f"config5 pair {i}", dfa, text)
+        dfa, text = W.batch_pair(s)
+        run_case(f"batch_pairs pair {i}", dfa, text)
 
 
 def test_repeat_determinism():
-    dfa, text = W.config2(n=1 << 22)
+    dfa, text = W.dna_motif(n=1 << 22)
     m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting)
     dev = torch.from_numpy(text).cuda()
     outs = set()
@@ -430,7 +430,7 @@ def test_lookback_sets(K):
                                num_accepting=50)
     sym = rng.choice(256, size=20, replace=False).astype(np.uint8)
     sparse = W.sparse_dfa(rng, 1500, bytes(sym), 4, 16, rng.choice(1500, size=24, replace=False))
-    dna, _ = W.config2(n=1024)
+    dna, _ = W.dna_motif(n=1024)
     cases = [("dense", dense), ("sparse", sparse), ("dna", dna)]
     for name, dfa in cases:
         text = W.uniform_text(rng, dfa.alphabet, (1 << 19) + 33)
@@ -463,12 +463,12 @@ def test_lookback_invalid_bytes():
             m.close()
 
 
-def test_config3_full_size():
+def test_sparse4096_full_size():
     """The large sparse byte DFA over its full 4 GiB Zipf text (the
     benchmark's sparse workload), sparse-row layout (the automatic choice),
     against the oracle."""
-    dfa, text = W.config3()
-    say(f"[case] config3 full: n={text.size}")
+    dfa, text = W.sparse4096()
+    say(f"[case] sparse4096 full: n={text.size}")
     m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting)
     assert m.describe()["layout"] == P.LAYOUT_SPARSE_LDS
     dev = torch.from_numpy(text).cuda()

@@ -81,7 +81,7 @@ def test_enumeration_parallel_automaton():
 
 
 def test_enumeration_motif_and_random():
-    dfa, text = W.config2(n=4 << 20)
+    dfa, text = W.dna_motif(n=4 << 20)
     enum_case("motif", dfa, text, chunk_len=4096)
     enum_case("motif, paper scheme", dfa, text, chunk_len=4096, no_merge=True, group=16)
     rng = np.random.default_rng(5)
@@ -93,7 +93,7 @@ def test_enumeration_motif_and_random():
 
 
 def test_enumeration_gives_plain_results_with_more_walks():
-    dfa, text = W.config2(n=1 << 20)
+    dfa, text = W.dna_motif(n=1 << 20)
     plain = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, chunk_len=1024)
     enum = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, chunk_len=1024, policy=P.POLICY_ENUMERATE)
     a, b = plain.match(dev(text)), enum.match(dev(text))

@@ -67,7 +67,7 @@ def test_positions_parallel_words():
 
 
 def test_positions_motif_4MiB_and_edges():
-    dfa, text = W.config2(n=(4 << 20) + 5, copies=3000)
+    dfa, text = W.dna_motif(n=(4 << 20) + 5, copies=3000)
     pos_case("motif 4 MiB", dfa.table, dfa.alphabet, dfa.start, dfa.accepting, text)
     none = W.uniform_text(np.random.default_rng(3), b"AC", 100_000)  # the motif needs G/T
     assert pos_case("no matches", dfa.table, dfa.alphabet, dfa.start, dfa.accepting, none) == 0
@@ -78,7 +78,7 @@ def test_positions_motif_4MiB_and_edges():
 def test_positions_motif_full_size():
     """The 1 GiB DNA workload (1e5 planted copies): every offset equals the
     oracle's."""
-    dfa, text = W.config2()
+    dfa, text = W.dna_motif()
     total = pos_case("motif 1 GiB", dfa.table, dfa.alphabet, dfa.start, dfa.accepting, text)
     assert total >= 99_000
 
@@ -90,7 +90,7 @@ def test_positions_random_layouts():
             dfa, text = W.random_case(rng, max_states=200, max_alpha=20, max_len=500_000)
             pos_case(f"random layout={lay} {i}", dfa.table, dfa.alphabet, dfa.start, dfa.accepting, text,
                      layout=lay, chunk_len=int(rng.choice([64, 512, 4096])))
-    dfa, text = W.config3(n=1 << 22)
+    dfa, text = W.sparse4096(n=1 << 22)
     pos_case("sparse byte DFA", dfa.table, dfa.alphabet, dfa.start, dfa.accepting, text)
 
 
@@ -108,7 +108,7 @@ def test_positions_partial():
 
 
 def test_positions_invalid_byte():
-    dfa, text = W.config2(n=1 << 20, copies=100)
+    dfa, text = W.dna_motif(n=1 << 20, copies=100)
     text = text.copy()
     text[70000] = ord("N")
     m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting)

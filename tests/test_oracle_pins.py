@@ -210,7 +210,7 @@ def brute_force_motif_count(text: np.ndarray, motif: bytes, wild: np.ndarray) ->
 
 @pytest.mark.parametrize("seed", [2, 7, 19, 23])
 def test_motif_count_equals_sliding_compare(seed):
-    dfa, text = W.config2(seed, n=1 << 21, copies=2000)
+    dfa, text = W.dna_motif(seed, n=1 << 21, copies=2000)
     motif, wild = dfa.meta["motif"], dfa.meta["wild"]
     r = oracle.walk_dfa(dfa, text)
     want = brute_force_motif_count(text, motif, wild)
@@ -222,7 +222,7 @@ def test_motif_count_equals_sliding_compare(seed):
 def test_motif_dfa_final_state_tracks_suffix():
     """The motif automaton's state depends only on the last 16 symbols: two
     texts with the same 16-symbol suffix end in the same state."""
-    dfa = W.config2_dfa(2)
+    dfa = W.dna_motif_dfa(2)
     rng = np.random.default_rng(5)
     suffix = W.uniform_text(rng, W.ACGT, 16)
     ends = set()
@@ -355,7 +355,7 @@ def test_motif_count_full_size_equals_sliding_compare():
     the oracle's count equals the sliding-window compare at the motif's 12
     fixed positions over the whole text, taken in 64 MiB blocks that overlap
     by the motif length minus one."""
-    dfa, text = W.config2()
+    dfa, text = W.dna_motif()
     assert text.size == 1 << 30
     motif, wild = dfa.meta["motif"], dfa.meta["wild"]
     m = len(motif)
@@ -578,7 +578,7 @@ def test_positions_of_the_regex_example():
 
 
 def test_positions_of_the_motif_automaton():
-    dfa, text = W.config2(seed=7, n=1 << 20, copies=300)
+    dfa, text = W.dna_motif(seed=7, n=1 << 20, copies=300)
     motif, wild = dfa.meta["motif"], dfa.meta["wild"]
     m = len(motif)
     n = text.size - m + 1

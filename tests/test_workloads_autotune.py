@@ -36,7 +36,7 @@ def test_zipf_text_blocks_do_not_depend_on_threads():
 
 
 def test_batch_specs_follow_their_distributions():
-    specs = W.config5_specs()
+    specs = W.batch_specs()
     assert len(specs) == 4096
     q = np.array([s.num_states for s in specs])
     a = np.array([s.alphabet_size for s in specs])
@@ -47,7 +47,7 @@ def test_batch_specs_follow_their_distributions():
     assert abs(math.log(np.median(q)) - math.log(128)) < 0.3
     assert abs(math.log(np.median(n)) - (math.log(1024) + math.log(64 << 20)) / 2) < 0.3
     assert 0.15 < float((q >= 1024).mean()) < 0.25
-    dfa, text = W.config5_pair(specs[5])
+    dfa, text = W.batch_pair(specs[5])
     assert dfa.table.shape == (specs[5].num_states, specs[5].alphabet_size)
     assert text.size == specs[5].text_len and np.isin(text, np.frombuffer(dfa.alphabet, dtype=np.uint8)).all()
     # explicit transitions: 4..16 per state, capped at A; the rest go to state 0
@@ -62,7 +62,7 @@ def test_autotune_size_classes_and_defaults(tmp_path):
     assert [batch_chunk_len(n) for n in (1, 16384, 16385, 1 << 20, 1 << 30)] == [64, 64, 128, 4096, 8192]
     rng = np.random.default_rng(1)
     wide = W.random_dense_dfa(rng, 500, b"ACGT")
-    narrow, _ = W.config2(n=64)
+    narrow, _ = W.dna_motif(n=64)
     assert Autotuner.default(wide)[1].get("lookback") == 256
     assert Autotuner.default(narrow)[1] == {}
     path = tmp_path / "cache.json"

@@ -41,7 +41,7 @@ def both(m, text):
 
 def test_noalloc_matches_async_twice():
     assert P.parem_noalloc_scratch_bytes() == 64 << 20
-    dfa, text = W.config2(n=(256 << 20) + 77, copies=20000)
+    dfa, text = W.dna_motif(n=(256 << 20) + 77, copies=20000)
     d = torch.from_numpy(text).cuda()
     m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting)
     assert P.parem_workspace_size(m.handle, d.numel()) <= P.parem_noalloc_scratch_bytes()
@@ -73,7 +73,7 @@ def test_noalloc_matches_async_twice():
 
 
 def test_noalloc_refuses_oversized_and_empty_works():
-    dfa, text = W.config3(n=64 << 20)
+    dfa, text = W.sparse4096(n=64 << 20)
     m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting)
     need = P.parem_workspace_size(m.handle, text.size)
     assert need > P.parem_noalloc_scratch_bytes()

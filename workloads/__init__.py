@@ -6,19 +6,18 @@ made by explicit construction (random tables, or the subset construction of a
 motif-search NFA) and the texts by seeded random draws. Both the CPU oracle
 and the HIP path consume what it returns; neither is imported here.
 
-Workload shapes follow the five benchmark configurations of the method's
-evaluation plan:
+Workload shapes (the five workloads the path is measured and tested on):
 
-* ``config1``: random 8-state DFA over {A,C,G,T}, 1 MiB uniform text, 1024
+* ``random8``: random 8-state DFA over {A,C,G,T}, 1 MiB uniform text, 1024
   chunks.
-* ``config2``: Sigma*.P search automaton for a random length-16 DNA motif with
+* ``dna_motif``: Sigma*.P search automaton for a random length-16 DNA motif with
   4 wildcard positions (17-state NFA, subset construction), 1 GiB uniform
   ACGT text with 1e5 planted motif copies.
-* ``config3``: 4096-state sparse byte DFA (4 explicit transitions per state,
+* ``sparse4096``: 4096-state sparse byte DFA (4 explicit transitions per state,
   the rest to state 0), 4 GiB Zipf(1.1) text over 64 byte values.
-* ``config4``: training text for the learned proposal: config-2 distribution,
+* ``motif_train``: training text for the learned proposal: the DNA motif distribution,
   another seed, 128 MiB.
-* ``config5``: 4096 (DFA, text) pairs of log-uniform sizes.
+* ``batch_pairs``: 4096 (DFA, text) pairs of log-uniform sizes.
 
 The paper gives no input text (its five strings of 6.69e7..1.07e9 characters
 are unspecified), so these stand in for it.
@@ -262,18 +261,18 @@ def plant_motifs(rng: np.random.Generator, text: np.ndarray, motif: bytes, wild:
 # the five configurations
 # ---------------------------------------------------------------------------
 
-CFG1_SEED = 1
-CFG2_SEED = 2
-CFG3_SEED = 3
-CFG4_SEED = 4
-CFG5_SEED = 5
+SEED_RANDOM8 = 1
+SEED_MOTIF = 2
+SEED_SPARSE = 3
+SEED_TRAIN = 4
+SEED_BATCH = 5
 
 
-def config1(seed: int = CFG1_SEED, n: int = 1 << 20):
+def random8(seed: int = SEED_RANDOM8, n: int = 1 << 20):
     """Random 8x4 uint8 table over ACGT, start 0, F={7}; i.i.d. text."""
     rng = np.random.default_rng(seed)
     table = rng.integers(0, 8, size=(8, 4), dtype=np.uint8)
-    dfa = Dfa(table, ACGT, 0, np.asarray([7], dtype=np.uint32), "cfg1")
+    dfa = Dfa(table, ACGT, 0, np.asarray([7], dtype=np.uint32), "random8")
     text = uniform_text(rng, ACGT, n)
     return dfa, text, 1024
 
@@ -310,17 +309,17 @@ def motif_spec(seed: int):
     return motif, wild
 
 
-def config2_dfa(seed: int = CFG2_SEED) -> Dfa:
+def dna_motif_dfa(seed: int = SEED_MOTIF) -> Dfa:
     motif, wild = motif_spec(seed)
     d = motif_dfa(motif, wild)
-    d.name = "cfg2"
+    d.name = "dna_motif"
     return d
 
 
-def config2(seed: int = CFG2_SEED, n: int = 1 << 30, copies: int | None = None,
+def dna_motif(seed: int = SEED_MOTIF, n: int = 1 << 30, copies: int | None = None,
             text_seed: int | None = None):
     """Motif DFA plus i.i.d. ACGT text with planted copies (1e5 per GiB)."""
-    dfa = config2_dfa(seed)
+    dfa = dna_motif_dfa(seed)
     rng = np.random.default_rng([seed if text_seed is None else text_seed, 0x7E47])
     text = uniform_text(rng, ACGT, n)
     if copies is None:
@@ -329,27 +328,27 @@ def config2(seed: int = CFG2_SEED, n: int = 1 << 30, copies: int | None = None,
     return dfa, text
 
 
-def config3_dfa(seed: int = CFG3_SEED, num_states: int = 4096):
+def sparse4096_dfa(seed: int = SEED_SPARSE, num_states: int = 4096):
     rng = np.random.default_rng([seed, 0x5A])
     symbols = rng.choice(256, size=64, replace=False).astype(np.uint8)  # Zipf rank order
     alphabet = bytes(range(256))
     acc = np.sort(rng.choice(np.arange(1, num_states), size=16, replace=False))
-    d = sparse_dfa(rng, num_states, alphabet, 4, 4, acc, explicit_cols=symbols, name="cfg3")
+    d = sparse_dfa(rng, num_states, alphabet, 4, 4, acc, explicit_cols=symbols, name="sparse4096")
     d.table = d.table.astype(np.uint16)
     d.meta["symbols"] = symbols
     return d
 
 
-def config3(seed: int = CFG3_SEED, n: int = 1 << 32, num_states: int = 4096):
-    dfa = config3_dfa(seed, num_states)
+def sparse4096(seed: int = SEED_SPARSE, n: int = 1 << 32, num_states: int = 4096):
+    dfa = sparse4096_dfa(seed, num_states)
     rng = np.random.default_rng([seed, 0x7E47])
     text = zipf_text(rng, dfa.meta["symbols"], n)
     return dfa, text
 
 
-def config4_train_text(seed: int = CFG4_SEED, n: int = 128 << 20, dfa_seed: int = CFG2_SEED):
-    """Config-2 text distribution for the same motif, drawn from another seed."""
-    dfa, text = config2(dfa_seed, n=n, text_seed=seed)
+def motif_train_text(seed: int = SEED_TRAIN, n: int = 128 << 20, dfa_seed: int = SEED_MOTIF):
+    """The DNA motif text distribution for the same motif, drawn from another seed."""
+    dfa, text = dna_motif(dfa_seed, n=n, text_seed=seed)
     return dfa, text
 
 
@@ -361,7 +360,7 @@ class PairSpec:
     text_len: int
 
 
-def config5_specs(seed: int = CFG5_SEED, pairs: int = 4096,
+def batch_specs(seed: int = SEED_BATCH, pairs: int = 4096,
                   q_range=(4, 4096), len_range=(1 << 10, 64 << 20)):
     rng = np.random.default_rng([seed, 0xBA7C])
     q = np.floor(np.exp(rng.uniform(math.log(q_range[0]), math.log(q_range[1]), size=pairs))).astype(np.int64)
@@ -370,12 +369,12 @@ def config5_specs(seed: int = CFG5_SEED, pairs: int = 4096,
     return [PairSpec(i, int(q[i]), int(a[i]), int(ln[i])) for i in range(pairs)]
 
 
-def config5_pair(spec: PairSpec, seed: int = CFG5_SEED, with_text: bool = True):
+def batch_pair(spec: PairSpec, seed: int = SEED_BATCH, with_text: bool = True):
     """Regenerates pair ``spec.index`` alone (its own seed stream)."""
     rng = np.random.default_rng([seed, 0x9A1, spec.index])
     alphabet = bytes(rng.choice(256, size=spec.alphabet_size, replace=False).astype(np.uint8))
     acc = rng.choice(spec.num_states, size=math.ceil(spec.num_states / 64), replace=False)
-    dfa = sparse_dfa(rng, spec.num_states, alphabet, 4, 16, acc, name=f"cfg5[{spec.index}]")
+    dfa = sparse_dfa(rng, spec.num_states, alphabet, 4, 16, acc, name=f"batch[{spec.index}]")
     if spec.num_states <= 256:
         dfa.table = dfa.table.astype(np.uint8)
     elif spec.num_states <= 65536:
