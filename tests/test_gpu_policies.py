@@ -223,6 +223,34 @@ def test_partial_random_tables(layout):
     say(f"[partial] {layout}: {dead} of 6 runs died")
 
 
+def test_partial_sparse_rows():
+    """Partial byte tables in the sparse-row layout (every byte valid, so the
+    keys are the bytes themselves): per state a default of 0, two explicit
+    transitions on bytes of a 64-symbol set, and byte 255 undefined for about
+    half the states; Zipf text over the 64 symbols with a few 255s planted.
+    Up to 4095 states (4096 with the dead state: the largest sparse-row table
+    without a sentinel row)."""
+    rng = np.random.default_rng(4096)
+    symbols = np.sort(rng.choice(255, size=64, replace=False)).astype(np.uint8)
+    alphabet = bytes(range(256))
+    for q, n, L in [(300, 700_000, 1024), (2000, 2_000_003, 4096), (4095, 4_000_000, 8192)]:
+        t = np.zeros((q, 256), dtype=np.int64)
+        for s_ in range(q):
+            cols = rng.choice(symbols, size=2, replace=False)
+            t[s_, cols] = rng.integers(0, q, size=2)
+        t[rng.random(q) < 0.5, 255] = -1
+        acc = rng.choice(q, size=16, replace=False)
+        text = symbols[np.minimum(rng.zipf(1.1, size=n) - 1, 63)].astype(np.uint8)
+        text[rng.integers(0, n, size=3)] = 255
+        tt = np.where(t < 0, 0xFFFF, t).astype(np.uint16)
+        m = P.Matcher(tt, alphabet, 0, acc, partial=True, layout=P.LAYOUT_SPARSE_LDS)
+        assert m.describe()["layout"] == P.LAYOUT_SPARSE_LDS
+        m.close()
+        for g in (4, 16):
+            partial_case(f"sparse rows Q={q} G={g}", t, alphabet, 0, acc, text, L, layout=P.LAYOUT_SPARSE_LDS,
+                         group=g)
+
+
 def test_partial_regex_example():
     """(a|b)?c*[0-3]b+ without its dead state: accepted texts stay alive to
     the end, others die where the total automaton would enter its dead state."""
