@@ -85,7 +85,8 @@ def test_positions_motif_full_size():
 
 def test_positions_random_layouts():
     rng = np.random.default_rng(7)
-    for lay in (P.LAYOUT_AUTO, P.LAYOUT_BYTE_LDS, P.LAYOUT_CLASS_LDS, P.LAYOUT_BYTE_GLOBAL, P.LAYOUT_HOT_LDS):
+    for lay in (P.LAYOUT_AUTO, P.LAYOUT_BYTE_LDS, P.LAYOUT_CLASS_LDS, P.LAYOUT_BYTE_GLOBAL, P.LAYOUT_HOT_LDS,
+                P.LAYOUT_SPARSE_LDS):
         for i in range(3):
             dfa, text = W.random_case(rng, max_states=200, max_alpha=20, max_len=500_000)
             pos_case(f"random layout={lay} {i}", dfa.table, dfa.alphabet, dfa.start, dfa.accepting, text,

@@ -67,7 +67,7 @@ def test_regex_search_positions_and_layouts():
     text = W.uniform_text(rng, alphabet, 8 << 20)
     want = R.run(pattern, alphabet, text, "search")
     d = torch.from_numpy(text).cuda()
-    for lay in (P.LAYOUT_AUTO, P.LAYOUT_BYTE_LDS, P.LAYOUT_CLASS_LDS, P.LAYOUT_BYTE_GLOBAL):
+    for lay in (P.LAYOUT_AUTO, P.LAYOUT_BYTE_LDS, P.LAYOUT_CLASS_LDS, P.LAYOUT_BYTE_GLOBAL, P.LAYOUT_SPARSE_LDS):
         m = P.Matcher.from_regex(pattern, alphabet, P.RE_SEARCH, layout=lay)
         got = m.match(d)
         assert (got.accept, got.count) == (want.accept, want.count), lay
