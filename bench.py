@@ -381,6 +381,69 @@ def bench_learned(args, m, dfa, dev, stream, steps):
     return res, results
 
 
+def bench_learned_wide(args):
+    """Learned speculation at the full head width: the 4096-state sparse
+    byte DFA over 1 GiB of its Zipf text (sparse rows), a proposal with 4096
+    logits trained on 64 MiB of the same distribution (another seed), top-m
+    in the given list against the plain walk of the same handle; top-1
+    accuracy at the chunk boundaries."""
+    import torch
+    import paper_1412_1741_amd as P
+    import workloads as W
+    log("learned (4096 states): generating")
+    dfa, text = W.sparse4096(n=args.wide_size)
+    dev = torch.from_numpy(text).cuda()
+    del text
+    _, train_text = W.sparse4096_train_text()
+    tdev = torch.from_numpy(train_text).cuda()
+    del train_text
+    stream = torch.cuda.current_stream()
+    m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting)
+    n = dev.numel()
+    out = {"text_bytes": int(n), "dfa_states": int(dfa.num_states), "layout": m.describe()["layout"]}
+    res_t = torch.empty(P.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+    ms = event_times(lambda: m.match_async(dev, res_t), max(5, args.steps // 2), stream)
+    plain = P.MatchResult.from_bytes(res_t.cpu().numpy().tobytes())
+    s = summary(ms, n)
+    s.update({"GBps": s["GBps_median"], "spec_runs": plain.spec_runs})
+    out["plain"] = s
+    log("learned (4096 states): training")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prop, hist = P.train_proposal(m, tdev, W.mlp_init_params(dfa.num_states), steps=args.wide_train_steps,
+                                  batch=4096, lr=2e-3, log_every=max(1, args.wide_train_steps // 4), seed=1)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del tdev
+    agree = True
+    chunks = plain.chunks
+    for mm in [int(x) for x in args.learned_m.split(",") if x]:
+        log(f"learned (4096 states) m={mm}")
+        outl = torch.empty(P.RESULT_BYTES, dtype=torch.uint8, device="cuda")
+        ms = event_times(lambda: m.match_learned_async(prop, dev, mm, outl), max(5, args.steps // 2), stream)
+        rl = P.MatchResult.from_bytes(outl.cpu().numpy().tobytes())
+        agree &= (rl.final_state, rl.accept, rl.count) == (plain.final_state, plain.accept, plain.count)
+        chunks = rl.chunks
+        s = summary(ms, n)
+        s.update({"GBps": s["GBps_median"], "spec_runs": rl.spec_runs,
+                  "rerun_share": round(rl.rerun_chunks / max(rl.chunks, 1), 6)})
+        out[f"learned_m{mm}"] = s
+    L = max(64, (n // max(chunks, 1)) // 64 * 64)
+    truth = P.boundary_states(m, dev, L).cpu().numpy().view(np.uint32)
+    sel, _ = prop.select(dev, L, 1)
+    sel = sel[:, 0].cpu().numpy().astype(np.int64)
+    images = [np.unique(dfa.table[:, j]) for j in range(dfa.alphabet_size)]
+    prev = dev[L - 1::L].cpu().numpy()[: truth.size - 1]
+    chosen = np.asarray([images[int(x)][s_] for x, s_ in zip(prev, sel[1:truth.size])])
+    out["training"] = {"text_bytes": 64 << 20, "steps": args.wide_train_steps, "batch": 4096,
+                       "seconds": round(train_s, 3), "loss": [[a, round(b, 5)] for a, b in hist],
+                       "top1_accuracy": round(float(np.mean(chosen == truth[1:])), 5), "chunk_len": L}
+    out["learned_agrees_with_plain"] = agree
+    prop.close()
+    m.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -393,11 +456,14 @@ def main():
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--no-merge", action="store_true", help="walk every speculated run through its whole chunk")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--modes", default="plain,paper,learned,enum,small,sparse,batch",
+    ap.add_argument("--modes", default="plain,paper,learned,wide,enum,small,sparse,batch",
                     help="comma list: plain (merged runs), paper (every run walks its chunk), learned, "
+                         "wide (learned speculation over the 4096-state sparse DFA), "
                          "enum (PaREM vs Enumeration), small (8-state DFA, 1 MiB, latency), "
                          "sparse (4096-state byte DFA), batch (4096 uneven pairs)")
     ap.add_argument("--learned-m", default="1,4,16")
+    ap.add_argument("--wide-size", type=int, default=1 << 30, help="text bytes of the 4096-state learned run")
+    ap.add_argument("--wide-train-steps", type=int, default=200)
     ap.add_argument("--train-steps", type=int, default=400)
     ap.add_argument("--batch-pairs", type=int, default=4096, help="pairs of the batched workload")
     ap.add_argument("--sparse-size", type=int, default=1 << 32, help="text bytes of the sparse byte DFA workload")
@@ -526,6 +592,8 @@ def main():
     agree = all((r.final_state, r.accept, r.count) == (res.final_state, res.accept, res.count)
                 for r in results.values())
 
+    if "wide" in wanted:
+        modes["learned_wide_sparse4096_1GiB"] = bench_learned_wide(args)
     if "enum" in wanted:
         log("PaREM vs Enumeration")
         modes["parem_vs_enumeration"] = bench_enum(args, dfa, dev)

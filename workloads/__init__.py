@@ -346,6 +346,14 @@ def sparse4096(seed: int = SEED_SPARSE, n: int = 1 << 32, num_states: int = 4096
     return dfa, text
 
 
+def sparse4096_train_text(seed: int = SEED_TRAIN, n: int = 64 << 20, dfa_seed: int = SEED_SPARSE):
+    """The sparse byte DFA's text distribution (Zipf over its 64 symbols),
+    drawn from another seed: training text for a 4096-row proposal."""
+    dfa = sparse4096_dfa(dfa_seed)
+    rng = np.random.default_rng([seed, 0x7E48])
+    return dfa, zipf_text(rng, dfa.meta["symbols"], n)
+
+
 def motif_train_text(seed: int = SEED_TRAIN, n: int = 128 << 20, dfa_seed: int = SEED_MOTIF):
     """The DNA motif text distribution for the same motif, drawn from another seed."""
     dfa, text = dna_motif(dfa_seed, n=n, text_seed=seed)
