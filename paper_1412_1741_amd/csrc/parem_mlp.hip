@@ -493,22 +493,25 @@ __global__ void k_to_bf16(const float *__restrict__ w, uint16_t *__restrict__ w1
 // Top-m of each row's logits among the states of its class list (ties: the
 // lower state id). Writes the chosen states' positions in the class list,
 // ascending, and their number. The first chunk (start class) keeps {q0}.
-__global__ void k_topm(const float *__restrict__ Z, uint32_t rows, uint32_t S, const uint16_t *__restrict__ wcls,
-                       const uint32_t *__restrict__ loff, const uint32_t *__restrict__ llist, uint32_t m,
-                       uint32_t RM, uint16_t *__restrict__ sel, uint8_t *__restrict__ nsel) {
-    const uint32_t row = blockIdx.x * blockDim.x + threadIdx.x;
-    if (row >= rows) return;
+// One wave per row: pass t takes the best item strictly after pass t-1's
+// pick in the order (logit descending, position ascending), each lane over
+// positions lane, lane + 64, ... and the wave joining the lanes' bests; lists
+// are sorted by state id, so position order is state-id order.
+__global__ __launch_bounds__(256) void k_topm(const float *__restrict__ Z, uint32_t rows, uint32_t S,
+                                              const uint16_t *__restrict__ wcls, const uint32_t *__restrict__ loff,
+                                              const uint32_t *__restrict__ llist, uint32_t m, uint32_t RM,
+                                              uint16_t *__restrict__ sel, uint8_t *__restrict__ nsel) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t row = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (row >= rows) return;  // whole waves
     const uint32_t c = wcls[row];
     const uint32_t lo = loff[c], sz = loff[c + 1] - lo;
     uint16_t *out = sel + (size_t)row * RM;
     if (sz <= m) {
-        for (uint32_t j = 0; j < sz; ++j) out[j] = (uint16_t)j;
-        nsel[row] = (uint8_t)sz;
+        for (uint32_t j = lane; j < sz; j += 64) out[j] = (uint16_t)j;
+        if (lane == 0) nsel[row] = (uint8_t)sz;
         return;
     }
-    // m passes; pass t takes the best item strictly after pass t-1's pick in
-    // the order (logit descending, position ascending). Lists are sorted by
-    // state id, so position order is state-id order.
     const float *z = Z + (size_t)row * S;
     uint32_t picked[16];
     float last_v = INFINITY;
@@ -516,7 +519,7 @@ __global__ void k_topm(const float *__restrict__ Z, uint32_t rows, uint32_t S, c
     for (uint32_t t = 0; t < m; ++t) {
         float best = -INFINITY;
         uint32_t bj = 0xffffffffu;
-        for (uint32_t j = 0; j < sz; ++j) {
+        for (uint32_t j = lane; j < sz; j += 64) {
             const uint32_t s = llist[lo + j];
             const float v = s < S ? z[s] : -INFINITY;
             const bool after = t == 0 || v < last_v || (v == last_v && j > last_j);
@@ -526,18 +529,30 @@ __global__ void k_topm(const float *__restrict__ Z, uint32_t rows, uint32_t S, c
                 bj = j;
             }
         }
+        // join: larger logit, then lower position; lanes without a candidate
+        // carry position 0xffffffff and lose every comparison
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const float ov = __shfl_xor(best, o, 64);
+            const uint32_t oj = (uint32_t)__shfl_xor((int)bj, o, 64);
+            const bool take = oj != 0xffffffffu && (bj == 0xffffffffu || ov > best || (ov == best && oj < bj));
+            best = take ? ov : best;
+            bj = take ? oj : bj;
+        }
         picked[t] = bj;
         last_v = best;
         last_j = bj;
     }
-    for (uint32_t a = 1; a < m; ++a)
-        for (uint32_t b = a; b > 0 && picked[b - 1] > picked[b]; --b) {
-            const uint32_t x = picked[b];
-            picked[b] = picked[b - 1];
-            picked[b - 1] = x;
-        }
-    for (uint32_t t = 0; t < m; ++t) out[t] = (uint16_t)picked[t];
-    nsel[row] = (uint8_t)m;
+    if (lane == 0) {
+        for (uint32_t a = 1; a < m; ++a)
+            for (uint32_t b = a; b > 0 && picked[b - 1] > picked[b]; --b) {
+                const uint32_t x = picked[b];
+                picked[b] = picked[b - 1];
+                picked[b - 1] = x;
+            }
+        for (uint32_t t = 0; t < m; ++t) out[t] = (uint16_t)picked[t];
+        nsel[row] = (uint8_t)m;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1030,7 +1045,7 @@ parem_status proposal_select(const Proposal &p, const uint8_t *d_text, uint64_t 
     hipLaunchKernelGGL(k_windows_chunks, dim3((chunks * kMlpWindow + 255) / 256), dim3(256), 0, s, d_text, L, chunks,
                        d.d_cls, d.A + 1, win, wcls);
     forward_rows(p, s, win, chunks, X, nullptr, H1, nullptr, H2, Z);
-    hipLaunchKernelGGL(k_topm, dim3((chunks + 255) / 256), dim3(256), 0, s, Z, chunks, p.S, wcls, d.d_loff,
+    hipLaunchKernelGGL(k_topm, dim3((chunks + 3) / 4), dim3(256), 0, s, Z, chunks, p.S, wcls, d.d_loff,
                        d.d_llist, m, RM, sel, nsel);
     if (nzero) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, zero, nzero);
     return hipGetLastError() == hipSuccess ? PAREM_OK : PAREM_EDEVICE;
