@@ -222,7 +222,7 @@ def bench_sparse(args):
                      ("hot_rows_lookback64", {"layout": P.LAYOUT_HOT_LDS, "lookback": 64}),
                      ("sparse_rows", {"layout": S}),
                      ("sparse_rows_g2", {"layout": S, "group": 2}),
-                     ("sparse_rows_g8", {"layout": S, "group": 8}),
+                     ("sparse_rows_g4", {"layout": S, "group": 4}),
                      ("sparse_rows_lookback4", {"layout": S, "lookback": 4}),
                      ("sparse_rows_L32k", {"layout": S, "chunk_len": 32768})):
         m = P.Matcher(dfa.table, dfa.alphabet, dfa.start, dfa.accepting, **kw)

@@ -58,10 +58,12 @@ enum {
     PAREM_LAYOUT_CLASS_LDS = 5,  /* (Q+1) x (A+1) table indexed by column, plus the
                                     byte-to-column map, in LDS (up to 48 KiB) */
     PAREM_LAYOUT_SPARSE_LDS = 6  /* sparse rows in LDS: per state a default next
-                                    state and at most 4 (column, next) exceptions,
-                                    16 bytes a row (up to 5103 states). AUTO takes
-                                    it when no dense LDS table fits and every row
-                                    qualifies; asked for on another table, the
+                                    state and its exceptions (columns with another
+                                    next state), the rows displaced into one vector
+                                    of 4-byte slots: one slot per exception and one
+                                    per state, at most 24512 slots (96 KiB). AUTO
+                                    takes it when no dense LDS table fits and the
+                                    slots fit; asked for on another table, the
                                     compile falls back as AUTO would. Batches walk
                                     such a handle's byte table through L2. */
 };
@@ -410,9 +412,9 @@ parem_status parem_match_learned_async(parem_handle h, parem_proposal p, uint32_
  *                      Allocates the plan's device memory (workspace for
  *                      every pair). Pairs with lens[i] == 0 are allowed.
  *                      The handles and proposals must outlive the plan.
- *                      A handle with the sparse-row layout is walked with
+ *                      A handle with the sparse layout is walked with
  *                      its byte table through L2 (no batch kernel stages
- *                      sparse rows).
+ *                      the sparse slots).
  * parem_batch_run      d_texts: host array of n device pointers, each
  *                      16-byte aligned (PAREM_EINVAL otherwise), holding
  *                      lens[i] bytes. d_out: device array of n results.

@@ -39,7 +39,9 @@ void release(DeviceDfa &d) {
     hipFree(d.d_next);
     hipFree(d.d_step);
     hipFree(d.d_bytes);
+    hipFree(d.d_sids);
     hipFree(d.d_coltab);
+    d.d_sids = nullptr;
     d.d_coltab = nullptr;
     d.d_next = nullptr;
     d.d_step = nullptr;
@@ -79,66 +81,100 @@ std::vector<E> byte_table(const DeviceDfa &d, const std::vector<uint32_t> &t, ui
     return out;
 }
 
-// Sparse rows: LDS image [256 B byte -> column][rows of kSparseRow = 16 B].
-// Row q: word 0 the keys of four exceptions (one byte each), words 1-2 their
-// entries (u16 each), word 3 the default entry in its low half and the final
-// flag of q in its high half. An entry is the next state's row offset
-// (16 * id), so every reachable row must start below 64 KiB: Q + 1 <= 4096
-// rows, or Q = 4096 when every byte is valid (the sentinel row is then
-// unreachable and left out). Unused exception slots repeat a key with its
-// own entry, so a key not among the exceptions always has the default. The
-// default is the row's most frequent next state. False when some row has
-// more than kSparseExc other columns or the rows do not fit.
-bool sparse_rows(const DeviceDfa &d, const std::vector<uint32_t> &t, std::vector<uint8_t> &image) {
+// Sparse layout: the rows of a table with few exceptions per row displaced
+// into one vector of u32 slots (row displacement, the compression used for
+// parser and scanner tables). Row q has a base slot b(q). Its exception on
+// key k (the byte itself when every byte is valid, else the byte's column)
+// sits in slot b(q) + k and holds the next state's base in its low half and
+// k in its high half. Slot b(q) + 256, the header, holds the base of q's
+// default next state (its most frequent one) in its low half, q's final flag
+// in bits 16-23 and 1 in bits 24-31. Free slots hold 0xffff in their high
+// half. A step from q on key k reads slot b(q) + k and takes its low half
+// when its high half is k, else the header's: a slot that another row r owns
+// at b(r) + k' = b(q) + k has k' != k because bases differ (each base has its
+// own header slot), and a header's or a free slot's high half is at least
+// 256. The walk's state is the base; `base` maps states to bases and `sids`
+// bases back to states. LDS image: [256 B byte -> column][slots], slots
+// padded to a multiple of four. Rows are placed first-fit, rows with more
+// exceptions first; false when the slots do not fit kSparseLdsMax or the
+// placement search runs over its budget.
+bool sparse_slots(const DeviceDfa &d, const std::vector<uint32_t> &t, std::vector<uint8_t> &image,
+                  std::vector<uint32_t> &base, std::vector<uint16_t> &sids) {
     // the invalid column A is reachable only when some byte is outside the alphabet
     bool invalid_used = false;
     for (uint32_t x = 0; x < 256; ++x) invalid_used |= d.cls[x] >= d.A;
     const uint32_t ncol = d.A + (invalid_used ? 1u : 0u);
     if (ncol > 256) return false;
-    const uint32_t nrows = std::min<uint32_t>(d.Q + 1, 65536 / parem::kSparseRow);
-    if (d.Q + 1 > nrows && (invalid_used || d.Q > nrows)) return false;
-    const size_t bytes = 256 + (size_t)nrows * parem::kSparseRow;
-    if (bytes > parem::kSparseLdsMax) return false;
-    image.assign(bytes, 0);
-    for (uint32_t x = 0; x < 256; ++x) image[x] = (uint8_t)d.cls[x];
-    // every byte valid: exceptions name the byte itself (the walk then needs
-    // no byte -> column read); else the column
-    uint8_t key[256];
-    for (uint32_t a = 0; a < 256; ++a) key[a] = (uint8_t)a;
+    // every byte valid: keys are the bytes themselves (the walk then needs no
+    // byte -> column read); else the columns
+    uint32_t key[256];
+    for (uint32_t a = 0; a < 256; ++a) key[a] = a;
     if (!invalid_used)
-        for (uint32_t x = 0; x < 256; ++x) key[d.cls[x]] = (uint8_t)x;
-    std::vector<uint32_t> next(ncol), count(d.Q + 1, 0);
-    for (uint32_t q = 0; q < nrows; ++q) {
+        for (uint32_t x = 0; x < 256; ++x) key[d.cls[x]] = x;
+    const uint32_t rows = d.Q + 1;  // row Q, the sentinel, keeps every key in itself
+    const uint32_t cap = (parem::kSparseLdsMax - 256) / 4;
+    std::vector<uint32_t> dflt(rows), eoff(rows + 1, 0), ekey, enext;
+    std::vector<uint32_t> next(ncol), count(rows, 0);
+    uint64_t need = 0;
+    for (uint32_t q = 0; q < rows; ++q) {
         for (uint32_t a = 0; a < ncol; ++a) next[a] = (q < d.Q && a < d.A) ? t[(size_t)q * d.A + a] : d.sent;
-        uint32_t dflt = next[0], best = 0;
+        uint32_t df = next[0], best = 0;
         for (uint32_t a = 0; a < ncol; ++a)
             if (++count[next[a]] > best) {
                 best = count[next[a]];
-                dflt = next[a];
+                df = next[a];
             }
         for (uint32_t a = 0; a < ncol; ++a) count[next[a]] = 0;
-        auto entry = [&](uint32_t nx) { return nx * parem::kSparseRow; };
-        uint8_t col[parem::kSparseExc];
-        uint32_t ent[parem::kSparseExc];
-        uint32_t ne = 0;
+        dflt[q] = df;
         for (uint32_t a = 0; a < ncol; ++a) {
-            if (next[a] == dflt) continue;
-            if (ne == parem::kSparseExc) return false;
-            col[ne] = key[a];
-            ent[ne] = entry(next[a]);
-            ++ne;
+            if (next[a] == df) continue;
+            ekey.push_back(key[a]);
+            enext.push_back(next[a]);
         }
-        for (uint32_t k = ne; k < parem::kSparseExc; ++k) {
-            col[k] = key[0];
-            ent[k] = entry(next[0]);
-        }
-        uint8_t *row = image.data() + 256 + (size_t)q * parem::kSparseRow;
-        const uint32_t w[4] = {(uint32_t)col[0] | (uint32_t)col[1] << 8 | (uint32_t)col[2] << 16 |
-                                   (uint32_t)col[3] << 24,
-                               ent[0] | ent[1] << 16, ent[2] | ent[3] << 16,
-                               entry(dflt) | (uint32_t)d.final_flag[q] << 16};
-        std::memcpy(row, w, sizeof(w));
+        eoff[q + 1] = (uint32_t)ekey.size();
+        need += eoff[q + 1] - eoff[q] + 1;
+        if (need > cap) return false;
     }
+    std::vector<uint32_t> order(rows);
+    for (uint32_t q = 0; q < rows; ++q) order[q] = q;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t x, uint32_t y) { return eoff[x + 1] - eoff[x] > eoff[y + 1] - eoff[y]; });
+    std::vector<uint8_t> used(cap, 0);
+    base.assign(rows, 0);
+    uint32_t first_free = 0, slots = 0;
+    uint64_t budget = 1ull << 27;  // candidate bases tried
+    for (const uint32_t q : order) {
+        const uint32_t lo = eoff[q], hi = eoff[q + 1];
+        uint32_t least = parem::kSparseHead;
+        for (uint32_t k = lo; k < hi; ++k) least = std::min(least, ekey[k]);
+        // a base below first_free - least would put the row's lowest slot on a used one
+        uint32_t b = first_free > least ? first_free - least : 0;
+        for (;; ++b) {
+            if (b + parem::kSparseHead >= cap || budget == 0) return false;
+            --budget;
+            bool ok = !used[b + parem::kSparseHead];
+            for (uint32_t k = lo; ok && k < hi; ++k) ok = !used[b + ekey[k]];
+            if (ok) break;
+        }
+        used[b + parem::kSparseHead] = 1;
+        for (uint32_t k = lo; k < hi; ++k) used[b + ekey[k]] = 1;
+        base[q] = b;
+        slots = std::max(slots, b + parem::kSparseHead + 1);
+        while (first_free < cap && used[first_free]) ++first_free;
+    }
+    slots = (slots + 3) / 4 * 4;
+    if (256 + (size_t)slots * 4 > parem::kSparseLdsMax) return false;
+    image.assign(256 + (size_t)slots * 4, 0);
+    for (uint32_t x = 0; x < 256; ++x) image[x] = (uint8_t)d.cls[x];
+    std::vector<uint32_t> w(slots, 0xffff0000u);
+    sids.assign(slots, 0xffffu);
+    for (uint32_t q = 0; q < rows; ++q) {
+        const uint32_t b = base[q];
+        w[b + parem::kSparseHead] = base[dflt[q]] | (uint32_t)d.final_flag[q] << 16 | 1u << 24;
+        for (uint32_t k = eoff[q]; k < eoff[q + 1]; ++k) w[b + ekey[k]] = base[enext[k]] | ekey[k] << 16;
+        sids[b] = (uint16_t)q;
+    }
+    std::memcpy(image.data() + 256, w.data(), (size_t)slots * 4);
     return true;
 }
 
@@ -428,8 +464,11 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
     // sparse rows when every row qualifies (checked once), hot rows only when
     // they hold most of the walk's weight, else the byte table through L2
     std::vector<uint8_t> sparse_image;
+    std::vector<uint32_t> sparse_base;
+    std::vector<uint16_t> sparse_sids;
     const bool big_auto = layout == PAREM_LAYOUT_AUTO && !kg_ok && !lds_ok && !class_ok;
-    const bool sparse_ok = (big_auto || layout == PAREM_LAYOUT_SPARSE_LDS) && sparse_rows(d, t, sparse_image);
+    const bool sparse_ok = (big_auto || layout == PAREM_LAYOUT_SPARSE_LDS) &&
+                           sparse_slots(d, t, sparse_image, sparse_base, sparse_sids);
     const bool hot_auto = hot_ok && !kg_ok && !lds_ok && !class_ok && !(big_auto && sparse_ok) &&
                           hot_share(d, t, hot_order) >= 0.9;
     const uint32_t big = hot_auto ? PAREM_LAYOUT_HOT_LDS : PAREM_LAYOUT_BYTE_GLOBAL;
@@ -439,9 +478,10 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
     if (layout == PAREM_LAYOUT_BYTE_LDS && !lds_ok) layout = class_ok ? PAREM_LAYOUT_CLASS_LDS : big;
     if (layout == PAREM_LAYOUT_CLASS_LDS && !class_ok) layout = big;
     if (layout == PAREM_LAYOUT_HOT_LDS && !hot_ok) layout = PAREM_LAYOUT_BYTE_GLOBAL;
-    // sparse rows: asked for, or chosen automatically when no dense table fits
-    // LDS, and only when every row has a default and at most kSparseExc other
-    // columns (the invalid column counts unless every byte is in the alphabet)
+    // sparse layout: asked for, or chosen automatically when no dense table
+    // fits LDS, and only when the rows' exceptions (columns other than a row's
+    // default; the invalid column counts unless every byte is in the
+    // alphabet) and headers fit the slots
     if (layout == PAREM_LAYOUT_SPARSE_LDS && !sparse_ok) layout = class_ok ? PAREM_LAYOUT_CLASS_LDS : big;
     if (big_auto && sparse_ok) layout = PAREM_LAYOUT_SPARSE_LDS;
     d.layout = layout;
@@ -495,13 +535,14 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
             st = upload(image, &p);
             d.d_table = p;
         } else if (layout == PAREM_LAYOUT_SPARSE_LDS) {
-            d.entry_bytes = 2;
-            d.row_stride = 8;
+            d.entry_bytes = 4;
+            d.row_stride = 0;
             d.table_bytes = (uint32_t)sparse_image.size();
             d.lds_bytes = d.table_bytes;
             uint8_t *p = nullptr;
             st = upload(sparse_image, &p);
             d.d_table = p;
+            if (st == PAREM_OK) st = upload(sparse_sids, &d.d_sids);
             // batches walk such a table as the byte table through L2
             if (st == PAREM_OK) st = upload(byte_table<uint16_t>(d, t, 256), &d.d_bytes);
         } else if (layout == PAREM_LAYOUT_HOT_LDS) {
@@ -534,10 +575,12 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
     if (st == PAREM_OK) st = upload(d.loff, &d.d_loff);
     if (st == PAREM_OK) st = upload(d.llist, &d.d_llist);
     d.d_llist_walk = d.d_llist;
-    if (st == PAREM_OK && layout == PAREM_LAYOUT_HOT_LDS) {
-        // walks start from encoded ids: no lookup of the encoding per walk
+    if (st == PAREM_OK && (layout == PAREM_LAYOUT_HOT_LDS || layout == PAREM_LAYOUT_SPARSE_LDS)) {
+        // walks start from encoded ids (hot rows) or bases (sparse layout): no
+        // lookup of the encoding per walk
         std::vector<uint32_t> enc_list(d.llist.size());
-        for (size_t k = 0; k < d.llist.size(); ++k) enc_list[k] = hot_enc[d.llist[k]];
+        for (size_t k = 0; k < d.llist.size(); ++k)
+            enc_list[k] = layout == PAREM_LAYOUT_HOT_LDS ? hot_enc[d.llist[k]] : sparse_base[d.llist[k]];
         st = upload(enc_list, &d.d_llist_walk);
     }
     if (st == PAREM_OK) st = upload(d.final_flag, &d.d_final);

@@ -397,8 +397,10 @@ static parem_status batch_plan(const parem_handle *dfas, const uint64_t *lens, u
         q.ca = compose_args(d, p);
         if (lens[i] == 0 || b->props[i]) continue;
         q.w = walk_args(d, p, nullptr, pws);
-        // sparse rows: the batch kernels walk the byte table through L2
+        // sparse layout: the batch kernels walk the byte table through L2,
+        // from the lists of state ids (not the lists of slot bases)
         q.table = d.layout == PAREM_LAYOUT_SPARSE_LDS ? d.d_bytes : d.d_table;
+        if (d.layout == PAREM_LAYOUT_SPARSE_LDS) q.w.llist = d.d_llist;
         q.table_bytes = d.table_bytes;
         q.full = d.d_full;
         q.enc = d.d_enc;

@@ -19,16 +19,23 @@ constexpr int kWalkThreads = 256;
 // register cap for more waves spills)
 constexpr int kSparseThreads = 1024;
 constexpr int kComposeThreads = 256;
-// A staged tile holds TILE bytes of each of a wave's 64 chunks; LDS rows are
+// A staged tile holds TILE bytes of each of a wave's 64 chunks. Rows are
 // TILE + 16 bytes apart so that 8 consecutive lanes' 16-byte reads hit
-// distinct banks.
-template <uint32_t TILE>
+// distinct banks; or, SWZ, TILE = 64 bytes apart with the 16-byte pieces of
+// row r stored in the order piece ^ ((r >> 1) & 3), which spreads the same
+// reads over the banks without the padding.
+template <uint32_t TILE, bool SWZ = false>
 struct Stage {
-    static constexpr uint32_t kRow = TILE + 16;
+    static_assert(!SWZ || TILE == 64, "the swizzle permutes four pieces");
+    static constexpr uint32_t kRow = SWZ ? TILE : TILE + 16;
     static constexpr uint32_t kWave = 64 * kRow;
     static constexpr uint32_t kBytes = (kWalkThreads / 64) * kWave;
     static constexpr uint32_t kPieces = TILE / 16;      // 16-byte loads per lane per tile
     static constexpr uint32_t kChunksPerLoad = 64 / kPieces;
+    // byte offset of piece k within row r
+    static __device__ __forceinline__ uint32_t piece_at(uint32_t r, uint32_t k) {
+        return 16u * (SWZ ? (k ^ ((r >> 1) & 3u)) : k);
+    }
 };
 
 // u16 at LDS byte address `addr`. The k-gram walk kernels declare no static
@@ -138,39 +145,35 @@ struct ClassStep {
 // four column compares. The table leaves room for two workgroups per CU only
 // without the text staging area, so lanes load their chunks 16 bytes at a
 // time themselves (the lines stay in L2 between a lane's loads).
-// Sparse rows: per state one 16-byte LDS row: the keys of four exceptions
-// (one byte each), their entries (u16 each), the default entry (u16) and
-// the final flag of the row's own state (u16). A key is the byte itself when
-// every byte is valid (RAW), else the byte's column. An entry is the next
-// state's row offset (16 * id), which is also the walk's state, so a step is
-// one 16-byte LDS read, four compares and four selects, and one add for the
-// count: the compares take the byte straight out of the text dword and the
-// selects take the 16-bit entries straight out of the row (SDWA operand
-// selects, written out below because the compiler extracts them with extra
-// instructions), and the row offset is the next read's address. The count
+// Sparse layout: the table's rows displaced into one vector of u32 slots.
+// The walk's state is its row's base slot b. The slot b + k holds the step on
+// key k (a byte when every byte is valid, RAW, else the byte's column) when
+// its high half is k: its low half is the next state's base. Otherwise the
+// step takes the row's default, the low half of the header slot b + 256,
+// whose bits 16-23 hold the final flag of the row's own state. A step is two
+// independent LDS reads (slot and header, both addressed from b), a compare,
+// a select and the count's add; the add of b and the key takes the byte
+// straight out of the text dword, and the compare and the select take their
+// halves straight out of the slots (SDWA operand selects, written out below
+// because the compiler extracts them with extra instructions). The count
 // takes the flag of the state a step leaves, so it is shifted by one step:
 // it starts at minus the start state's flag and the end state's flag is
 // added when the walk is stored (kDeferredCount).
 //
-// One step: v = default; then v = entry i where key i equals the byte (keys
-// in row byte order, i = 0..3); c += own final flag. KSEL selects the byte
-// of `key` compared (BYTE_k of a text dword, or DWORD for a column). A
-// VALU write of VCC needs two wait states before v_cndmask reads it.
+// KSEL selects the byte of `key` used (BYTE_k of a text dword, or DWORD for a
+// column). A VALU write of VCC needs two wait states before v_cndmask reads
+// it: the count's add and one s_nop.
+#define PAREM_SPARSE_KEYADD(KSEL)                                                                       \
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:" KSEL " src1_sel:DWORD" \
+        : "=v"(u)                                                                                       \
+        : "v"(key), "v"(s))
 #define PAREM_SPARSE_STEP(KSEL)                                                                                  \
-    asm("v_cmp_eq_u32_sdwa vcc, %1, %5 src0_sel:BYTE_0 src1_sel:" KSEL "\n\t"                                   \
-        "s_nop 1\n\t"                                                                                            \
-        "v_cndmask_b32_sdwa %0, %4, %2, vcc dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_0 src1_sel:WORD_0\n\t" \
-        "v_cmp_eq_u32_sdwa vcc, %1, %5 src0_sel:BYTE_1 src1_sel:" KSEL "\n\t"                                   \
-        "s_nop 1\n\t"                                                                                            \
-        "v_cndmask_b32_sdwa %0, %0, %2, vcc dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_1\n\t" \
-        "v_cmp_eq_u32_sdwa vcc, %1, %5 src0_sel:BYTE_2 src1_sel:" KSEL "\n\t"                                   \
-        "s_nop 1\n\t"                                                                                            \
-        "v_cndmask_b32_sdwa %0, %0, %3, vcc dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_0\n\t" \
-        "v_cmp_eq_u32_sdwa vcc, %1, %5 src0_sel:BYTE_3 src1_sel:" KSEL "\n\t"                                   \
-        "s_nop 1\n\t"                                                                                            \
-        "v_cndmask_b32_sdwa %0, %0, %3, vcc dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_1"    \
-        : "=&v"(v)                                                                                               \
-        : "v"(r.x), "v"(r.y), "v"(r.z), "v"(r.w), "v"(key)                                                       \
+    asm("v_cmp_eq_u32_sdwa vcc, %2, %3 src0_sel:WORD_1 src1_sel:" KSEL "\n\t"                                  \
+        "v_add_u32_sdwa %1, %1, %4 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2\n\t"       \
+        "s_nop 0\n\t"                                                                                            \
+        "v_cndmask_b32_sdwa %0, %4, %2, vcc dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_0 src1_sel:WORD_0" \
+        : "=&v"(v), "+v"(c)                                                                                      \
+        : "v"(e), "v"(key), "v"(h)                                                                               \
         : "vcc")
 
 template <bool RAW>
@@ -180,29 +183,36 @@ struct SparseStep {
     static constexpr bool kStage = true;   // text staged through LDS when aligned (64-byte tiles)
     static constexpr bool kCachedText = true;
     static constexpr bool kDeferredCount = true;
+    static constexpr bool kSwizzle = true;  // unpadded tiles: the slots take the LDS
     // The kernel declares no static LDS: its dynamic LDS (the byte -> column
-    // map, then the rows) starts at LDS address 0, so row offset + kRows is
-    // the row's LDS address.
-    static constexpr uint32_t kRows = 256;
-    const uint8_t *__restrict__ col;   // LDS: [256] byte -> column (unused when RAW)
+    // map, then the slots) starts at LDS address 0, so kSlots + 4 * slot is
+    // the slot's LDS address.
+    static constexpr uint32_t kSlots = 256;
+    static constexpr uint32_t kHeads = kSlots + 4 * kSparseHead;
+    const uint8_t *__restrict__ col;    // LDS: [256] byte -> column (unused when RAW)
+    const uint16_t *__restrict__ sids;  // global: state of the row based at each slot
 
-    __device__ __forceinline__ uint32_t init(uint32_t s) const { return s * kSparseRow; }
-    __device__ __forceinline__ uint32_t id(uint32_t r) const { return r / kSparseRow; }
+    // walks start from the lists of bases
+    __device__ __forceinline__ uint32_t init(uint32_t s) const { return s; }
+    __device__ __forceinline__ uint32_t id(uint32_t r) const { return sids[r]; }
     __device__ __forceinline__ bool same(uint32_t a, uint32_t b) const { return a == b; }
-    __device__ __forceinline__ uint32_t fin(uint32_t r) const { return lds_abs<uint32_t>(kRows + r + 12) >> 16; }
-    // K = 0..3: compare byte K of `key` (a text dword); K = 4: `key` is a column
+    __device__ __forceinline__ uint32_t fin(uint32_t r) const { return (lds_abs<uint32_t>(kHeads + 4u * r) >> 16) & 0xffu; }
+    // K = 0..3: the key is byte K of `key` (a text dword); K = 4: `key` is a column
     template <int K>
     __device__ __forceinline__ void one(uint32_t &s, uint32_t &c, uint32_t key) const {
-        const u32x4 r = lds_abs<u32x4>(kRows + s);
-        uint32_t v;
+        uint32_t u, v;
+        if constexpr (K == 0) PAREM_SPARSE_KEYADD("BYTE_0");
+        else if constexpr (K == 1) PAREM_SPARSE_KEYADD("BYTE_1");
+        else if constexpr (K == 2) PAREM_SPARSE_KEYADD("BYTE_2");
+        else if constexpr (K == 3) PAREM_SPARSE_KEYADD("BYTE_3");
+        else u = s + key;
+        const uint32_t e = lds_abs<uint32_t>(kSlots + 4u * u);
+        const uint32_t h = lds_abs<uint32_t>(kHeads + 4u * s);
         if constexpr (K == 0) PAREM_SPARSE_STEP("BYTE_0");
         else if constexpr (K == 1) PAREM_SPARSE_STEP("BYTE_1");
         else if constexpr (K == 2) PAREM_SPARSE_STEP("BYTE_2");
         else if constexpr (K == 3) PAREM_SPARSE_STEP("BYTE_3");
         else PAREM_SPARSE_STEP("DWORD");
-        asm("v_add_u32_sdwa %0, %0, %1 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_1"
-            : "+v"(c)
-            : "v"(r.w));
         s = v;
     }
     template <int K, int G>
@@ -233,6 +243,7 @@ struct SparseStep {
         else one<4>(R, c, (uint32_t)col[x]);
     }
 };
+#undef PAREM_SPARSE_KEYADD
 #undef PAREM_SPARSE_STEP
 
 // Hot-row layout: the byte-table rows of the H most visited states sit in
@@ -477,6 +488,12 @@ struct Deferred : std::false_type {};
 template <typename ST>
 struct Deferred<ST, std::void_t<decltype(ST::kDeferredCount)>> : std::bool_constant<ST::kDeferredCount> {};
 
+// Steppers with kSwizzle stage text tiles in unpadded, swizzled rows.
+template <typename ST, typename = void>
+struct Swizzled : std::false_type {};
+template <typename ST>
+struct Swizzled<ST, std::void_t<decltype(ST::kSwizzle)>> : std::bool_constant<ST::kSwizzle> {};
+
 template <typename ST>
 __device__ __forceinline__ uint32_t count_start(const ST &st, uint32_t r) {
     if constexpr (Deferred<ST>::value) return 0u - st.fin(r);
@@ -550,18 +567,21 @@ __device__ __forceinline__ Tile<TILE> tile_load(const uint8_t *s, size_t step) {
     return tile_load_seq<TILE, NT>(s, step, std::make_index_sequence<TILE / 16>{});
 }
 
-template <uint32_t TILE, size_t... K>
+// (load K's chunks are kChunksPerLoad rows further: with the swizzle, an
+// even step of rows, so every load K of a lane lands at the same piece slot)
+template <uint32_t TILE, bool SWZ, size_t... K>
 __device__ __forceinline__ void tile_store_seq(Tile<TILE> x, uint8_t *dst, std::index_sequence<K...>) {
-    ((*reinterpret_cast<uint4 *>(dst + K * Stage<TILE>::kChunksPerLoad * Stage<TILE>::kRow) = piece_of<K>(x)),
-     ...);
+    using SG = Stage<TILE, SWZ>;
+    static_assert(!SWZ || SG::kChunksPerLoad % 8 == 0, "the swizzle must repeat every kChunksPerLoad rows");
+    ((*reinterpret_cast<uint4 *>(dst + K * SG::kChunksPerLoad * SG::kRow) = piece_of<K>(x)), ...);
 }
 
 // write the wave's tile to LDS (this lane then reads its chunk's TILE bytes
 // back one 16-byte piece at a time, just before walking it)
-template <uint32_t TILE>
+template <uint32_t TILE, bool SWZ = false>
 __device__ __forceinline__ void tile_store(const Tile<TILE> x, uint8_t *dst) {
     __builtin_amdgcn_wave_barrier();
-    tile_store_seq<TILE>(x, dst, std::make_index_sequence<TILE / 16>{});
+    tile_store_seq<TILE, SWZ>(x, dst, std::make_index_sequence<TILE / 16>{});
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -571,11 +591,12 @@ template <int G, typename ST, uint32_t TILE>
 __device__ __forceinline__ void walk_staged(const ST &st, Walks<G> &w, const uint8_t *__restrict__ wave_text,
                                             uint32_t L, uint32_t ntiles, uint32_t lane, uint8_t *stage,
                                             uint32_t &bad) {
-    using SG = Stage<TILE>;
+    constexpr bool SWZ = Swizzled<ST>::value;
+    using SG = Stage<TILE, SWZ>;
     const uint32_t ch0 = lane / SG::kPieces, sub = (lane % SG::kPieces) * 16u;
     const uint8_t *src = wave_text + (size_t)ch0 * L + sub;
     const size_t step = (size_t)SG::kChunksPerLoad * L;
-    uint8_t *dst = stage + ch0 * SG::kRow + sub;
+    uint8_t *dst = stage + ch0 * SG::kRow + SG::piece_at(ch0, lane % SG::kPieces);
     const uint8_t *mine = stage + lane * SG::kRow;
     // one tile ahead; the prefetch is unconditional (past the last tile it
     // reloads the last tile, an L2 hit) so the wait before each store covers
@@ -584,11 +605,11 @@ __device__ __forceinline__ void walk_staged(const ST &st, Walks<G> &w, const uin
     constexpr bool NT = !CachedText<ST>::value;
     Tile<TILE> nxt = tile_load<TILE, NT>(src, step);
     for (uint32_t t = 0; t < ntiles; ++t) {
-        tile_store<TILE>(nxt, dst);
+        tile_store<TILE, SWZ>(nxt, dst);
         nxt = tile_load<TILE, NT>(src + (size_t)min(t + 1, last) * TILE, step);
 #pragma unroll
         for (uint32_t k = 0; k < SG::kPieces; ++k)
-            piece<G>(st, w, *reinterpret_cast<const uint4 *>(mine + 16 * k), bad);
+            piece<G>(st, w, *reinterpret_cast<const uint4 *>(mine + SG::piece_at(lane, k)), bad);
     }
 }
 
@@ -753,7 +774,7 @@ __device__ __forceinline__ void walk_chunk(const ST &st, const WalkArgs &a, uint
     if (ntiles) {
         const uint64_t wave_first = c - lane;
         walk_staged<G, ST, TILE>(st, w, a.text + wave_first * a.L, a.L, ntiles, lane,
-                                 stage + (threadIdx.x >> 6) * Stage<TILE>::kWave, bad);
+                                 stage + (threadIdx.x >> 6) * Stage<TILE, Swizzled<ST>::value>::kWave, bad);
     }
     if (!active) return;
     const uint8_t *p = a.text + b;

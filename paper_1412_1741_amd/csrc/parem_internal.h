@@ -73,19 +73,23 @@ struct DeviceDfa {
     uint16_t *d_next = nullptr;      // [(Q+1) x A] next state by class (lookback sets); row Q: the sentinel
     uint16_t *d_enc = nullptr;       // [Q+1] encoded id of each state (slot when hot, 0x4000 | id else)
     uint16_t *d_step = nullptr;      // [(Q+1) x (A+1)] next state by class | final << 15 (small tables only)
-    uint16_t *d_bytes = nullptr;     // sparse-row layout: the (Q+1) x 256 u16 byte table for batch walks
+    uint16_t *d_bytes = nullptr;     // sparse layout: the (Q+1) x 256 u16 byte table for batch walks
+    uint16_t *d_sids = nullptr;      // sparse layout: [slots] state whose row is based at each slot
     uint16_t *d_coltab = nullptr;    // [(Q+1) x (A+1)] next state by column | final << 15 (match positions)
     uint32_t hot_rows = 0;
-    bool sparse_raw = false;         // sparse rows name exception bytes, not columns (every byte valid)
+    bool sparse_raw = false;         // sparse rows are keyed by bytes, not columns (every byte valid)
 };
 
 // hot-row layout: at most kHotMax rows of kHotRow u16 entries (256 bytes plus
 // padding that shifts successive rows by one LDS bank)
 constexpr uint32_t kHotMax = 32;
 constexpr uint32_t kClassLdsMax = 48 * 1024;  // largest column-indexed LDS table
-constexpr uint32_t kSparseRow = 16;             // bytes per sparse row
-constexpr uint32_t kSparseLdsMax = 256 + 65536; // largest sparse-row LDS image (row offsets are u16)
-constexpr uint32_t kSparseExc = 4;            // exceptions per sparse row
+// sparse layout (rows displaced into one vector of u32 slots): a row's
+// header slot sits kSparseHead slots after its base; the LDS image is the
+// 256-byte byte -> column map and the slots, at most kSparseLdsMax bytes
+// (160 KiB of LDS less sixteen waves' 4 KiB text tiles)
+constexpr uint32_t kSparseHead = 256;
+constexpr uint32_t kSparseLdsMax = 160 * 1024 - 16 * 4096;
 constexpr uint32_t kHotRow = 258;
 constexpr uint32_t kHotFlag = 0x4000u;  // cold state: kHotFlag | id; hot state: its slot
 constexpr uint32_t kHotLost = 0x7fffu;  // entries of the extra LDS row H

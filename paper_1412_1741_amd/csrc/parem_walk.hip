@@ -602,13 +602,13 @@ parem_status plan_chunks(const DeviceDfa &d, uint64_t len, const parem_options &
     q.tile = o.tile ? o.tile : 128;
     q.merge = o.no_merge ? 0u : 1u;
     if (q.tile != 64 && q.tile != 128) return PAREM_EINVAL;
-    // sparse rows: four runs a pass keep the walk within 128 registers (four
-    // waves per SIMD); their followers merge within a few bytes. k-gram
-    // tables: sixteen when a set holds more than eight states, so that one
-    // pass walks it (the LDS already limits these kernels to two waves per
-    // SIMD, which leaves the registers; 1 GiB DNA motif: 197 against 205 us)
+    // sparse layout: eight runs a pass fit the 128 registers of four waves
+    // per SIMD (a few spills outside the walk loop; 4 GiB Zipf text over the
+    // 4096-state byte DFA: 1.90 against 1.98 ms with four). k-gram tables:
+    // sixteen when a set holds more than eight states, so that one pass
+    // walks it (the LDS already limits these kernels to two waves per SIMD,
+    // which leaves the registers; 1 GiB DNA motif: 197 against 205 us)
     uint32_t G = o.group ? o.group : 8;
-    if (!o.group && d.layout == PAREM_LAYOUT_SPARSE_LDS) G = 4;
     if (!o.group && d.layout == PAREM_LAYOUT_KGRAM_LDS && d.max_spec > 8) G = 16;
     if (G != 2 && G != 4 && G != 8 && G != 16) return PAREM_EINVAL;
     q.G = G;

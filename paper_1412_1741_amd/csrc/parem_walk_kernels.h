@@ -63,11 +63,12 @@ __global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_walk_class(W
 // one workgroup of kSparseThreads per CU: four waves per SIMD
 template <int G, bool ALIGNED, int MODE, bool RAW>
 __global__ __launch_bounds__(kSparseThreads) void k_walk_sparse(WalkArgs a, const uint8_t *__restrict__ g_table,
-                                                                uint32_t table_bytes) {
+                                                                uint32_t table_bytes,
+                                                                const uint16_t *__restrict__ sids) {
     extern __shared__ __align__(16) uint8_t smem[];
     stage_table<kSparseThreads>(reinterpret_cast<uint4 *>(smem), reinterpret_cast<const uint4 *>(g_table),
                                 table_bytes / 16u);
-    SparseStep<RAW> st{smem};
+    SparseStep<RAW> st{smem, sids};
     walk_chunk<G, SparseStep<RAW>, ALIGNED, 64, MODE>(st, a, smem + table_bytes, (uint64_t)blockIdx.x * kSparseThreads);
 }
 
@@ -133,11 +134,13 @@ inline void launch_walk_class(const DeviceDfa &d, const PlainPlan &p, const Walk
 template <bool ALIGNED, int MODE, bool RAW>
 inline void launch_walk_sparse_t(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, hipStream_t stream) {
     const uint32_t grid = (uint32_t)((p.chunks + kSparseThreads - 1) / kSparseThreads);
-    const size_t lds = d.table_bytes + ((ALIGNED && MODE != WALK_REDO) ? (kSparseThreads / 64) * Stage<64>::kWave : 0);
+    using SG = Stage<64, SparseStep<RAW>::kSwizzle>;
+    static_assert(kSparseLdsMax + (kSparseThreads / 64) * SG::kWave <= 160 * 1024, "slots and tiles exceed LDS");
+    const size_t lds = d.table_bytes + ((ALIGNED && MODE != WALK_REDO) ? (kSparseThreads / 64) * SG::kWave : 0);
     const uint8_t *tab = reinterpret_cast<const uint8_t *>(d.d_table);
 #define PAREM_SPR(GG)                                                                                           \
     hipLaunchKernelGGL((k_walk_sparse<GG, ALIGNED, MODE, RAW>), dim3(grid), dim3(kSparseThreads), lds, stream, a, \
-                       tab, d.table_bytes)
+                       tab, d.table_bytes, d.d_sids)
     PAREM_GROUP_SWITCH(PAREM_SPR)
 #undef PAREM_SPR
 }

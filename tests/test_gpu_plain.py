@@ -240,12 +240,13 @@ def test_hot_rows_sparse_and_dense(group):
 
 @pytest.mark.parametrize("group", [2, 4, 8, 16])
 def test_sparse_rows(group):
-    """Sparse-row layout (a default and at most four exceptions per state):
-    a byte DFA with explicit columns among 64 Zipf symbols, the same table
-    with a default per state other than state 0, a 20-symbol alphabet whose
-    invalid column is one of the exceptions (and a text with a byte outside
-    it), lookback sets, and a table with five exceptions in a row, which
-    falls back to another layout."""
+    """Sparse layout (rows of a default and a few exceptions displaced into
+    one vector of slots): a byte DFA with explicit columns among 64 Zipf
+    symbols, the same table with a default per state other than state 0, a
+    20-symbol alphabet whose invalid column is one of the exceptions (and a
+    text with a byte outside it), lookback sets, a table with five
+    exceptions in every row, and one whose slots do not fit LDS, which falls
+    back to another layout."""
     rng = np.random.default_rng(900 + group)
     sym = rng.choice(256, size=64, replace=False).astype(np.uint8)
     acc = rng.choice(np.arange(1, 3000), size=16, replace=False)
@@ -285,9 +286,16 @@ def test_sparse_rows(group):
     m.close()
     five = W.sparse_dfa(rng, 300, bytes(range(256)), 5, 5, acc[:3] % 300)
     m = P.Matcher(five.table, five.alphabet, five.start, five.accepting, layout=P.LAYOUT_SPARSE_LDS)
+    assert m.describe()["layout"] == P.LAYOUT_SPARSE_LDS
+    m.close()
+    run_case(f"sparse five G={group}", five, W.uniform_text(rng, five.alphabet, 200_000), chunk_len=1024,
+             group=group, layout=P.LAYOUT_SPARSE_LDS)
+    # 2000 rows of 8-16 exceptions need about 26000 slots: more than LDS holds
+    wide = W.sparse_dfa(rng, 2000, bytes(range(256)), 8, 16, acc[:3] % 2000)
+    m = P.Matcher(wide.table, wide.alphabet, wide.start, wide.accepting, layout=P.LAYOUT_SPARSE_LDS)
     assert m.describe()["layout"] != P.LAYOUT_SPARSE_LDS
     m.close()
-    run_case(f"sparse fallback G={group}", five, W.uniform_text(rng, five.alphabet, 200_000), chunk_len=1024,
+    run_case(f"sparse fallback G={group}", wide, W.uniform_text(rng, wide.alphabet, 200_000), chunk_len=1024,
              group=group, layout=P.LAYOUT_SPARSE_LDS)
 
 

@@ -224,12 +224,12 @@ def test_partial_random_tables(layout):
 
 
 def test_partial_sparse_rows():
-    """Partial byte tables in the sparse-row layout (every byte valid, so the
+    """Partial byte tables in the sparse layout (every byte valid, so the
     keys are the bytes themselves): per state a default of 0, two explicit
     transitions on bytes of a 64-symbol set, and byte 255 undefined for about
-    half the states; Zipf text over the 64 symbols with a few 255s planted.
-    Up to 4095 states (4096 with the dead state: the largest sparse-row table
-    without a sentinel row)."""
+    half the states (an exception to the dead state); Zipf text over the 64
+    symbols with a few 255s planted. Up to 4095 states (4096 with the dead
+    state)."""
     rng = np.random.default_rng(4096)
     symbols = np.sort(rng.choice(255, size=64, replace=False)).astype(np.uint8)
     alphabet = bytes(range(256))
