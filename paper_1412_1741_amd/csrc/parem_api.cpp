@@ -83,23 +83,82 @@ std::vector<E> byte_table(const DeviceDfa &d, const std::vector<uint32_t> &t, ui
 
 // Sparse layout: the rows of a table with few exceptions per row displaced
 // into one vector of u32 slots (row displacement, the compression used for
-// parser and scanner tables). Row q has a base slot b(q). Its exception on
-// key k (the byte itself when every byte is valid, else the byte's column)
-// sits in slot b(q) + k and holds the next state's base in its low half and
-// k in its high half. Slot b(q) + 256, the header, holds the base of q's
-// default next state (its most frequent one) in its low half, q's final flag
-// in bits 16-23 and 1 in bits 24-31. Free slots hold 0xffff in their high
-// half. A step from q on key k reads slot b(q) + k and takes its low half
-// when its high half is k, else the header's: a slot that another row r owns
-// at b(r) + k' = b(q) + k has k' != k because bases differ (each base has its
-// own header slot), and a header's or a free slot's high half is at least
-// 256. The walk's state is the base; `base` maps states to bases and `sids`
-// bases back to states. LDS image: [256 B byte -> column][slots], slots
-// padded to a multiple of four. Rows are placed first-fit, rows with more
-// exceptions first; false when the slots do not fit kSparseLdsMax or the
-// placement search runs over its budget.
-bool sparse_slots(const DeviceDfa &d, const std::vector<uint32_t> &t, std::vector<uint8_t> &image,
-                  std::vector<uint32_t> &base, std::vector<uint16_t> &sids) {
+// parser and scanner tables). Row q has a base slot b(q), distinct for every
+// row; its exception on key k (the byte itself when every byte is valid,
+// else the byte's column) sits in slot b(q) + k. A step from q on key k
+// reads slot b(q) + k and takes it when the slot's key field is k, else the
+// default: a slot that another row r owns at b(r) + k' = b(q) + k has
+// k' != k because bases differ, and the key field of a slot no row owns
+// never matches (below). The walk's state is the base, or for the uniform
+// form the base with the state's final flag in bits 16-23.
+//
+// Uniform form, when every row's exceptions against one common default D
+// (the most frequent default) fit: a slot holds the next state's base
+// (bits 0-15), its final flag (bits 16-23) and the key (bits 24-31); the
+// walk keeps D's value in a register, so a step is one LDS read. The key
+// field of a free slot j is a byte x such that no row has base j - x.
+//
+// General form: each row has a header slot at b(q) + 256 holding the base
+// of its own default (its most frequent next state) in its low half, q's
+// final flag in bits 16-23 and 1 in bits 24-31 (so its high half, like a
+// free slot's 0xffff, is at least 256); an exception slot holds the next
+// state's base in its low half and the key in its high half. A step reads
+// the slot and the header.
+//
+// Rows are placed first-fit, rows with more exceptions first. LDS image:
+// [256 B byte -> column][slots], slots padded to a multiple of four. False
+// when neither form fits kSparseLdsMax or the placement search runs over its
+// budget.
+struct SparseImage {
+    std::vector<uint8_t> image;
+    std::vector<uint32_t> walk;   // [Q+1] value a walk from each state starts with
+    std::vector<uint16_t> sids;   // [slots] state whose row is based at each slot
+    bool uniform = false;
+    uint32_t d0 = 0;              // uniform form: the default's walk value
+};
+
+// first-fit placement of rows (key lists eoff/ekey); `head` adds the header
+// slot at base + 256. Bases are distinct; every lookup b + key stays below
+// the returned slot count.
+bool place_rows(const std::vector<uint32_t> &eoff, const std::vector<uint32_t> &ekey, bool head, uint32_t cap,
+                std::vector<uint32_t> &base, std::vector<uint8_t> &used, std::vector<uint8_t> &is_base,
+                uint32_t &slots) {
+    const uint32_t rows = (uint32_t)eoff.size() - 1;
+    std::vector<uint32_t> order(rows);
+    for (uint32_t q = 0; q < rows; ++q) order[q] = q;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t x, uint32_t y) { return eoff[x + 1] - eoff[x] > eoff[y + 1] - eoff[y]; });
+    used.assign(cap, 0);
+    is_base.assign(cap, 0);
+    base.assign(rows, 0);
+    uint32_t first_free = 0;
+    slots = 0;
+    uint64_t budget = 1ull << 27;  // candidate bases tried
+    for (const uint32_t q : order) {
+        const uint32_t lo = eoff[q], hi = eoff[q + 1];
+        uint32_t least = head ? parem::kSparseHead : 256u;
+        for (uint32_t k = lo; k < hi; ++k) least = std::min(least, ekey[k]);
+        if (lo == hi && !head) least = 0;
+        // a base below first_free - least would put the row's lowest slot on a used one
+        uint32_t b = first_free > least ? first_free - least : 0;
+        for (;; ++b) {
+            if (b + 256 >= cap || budget == 0) return false;
+            --budget;
+            bool ok = !is_base[b] && !(head && used[b + parem::kSparseHead]);
+            for (uint32_t k = lo; ok && k < hi; ++k) ok = !used[b + ekey[k]];
+            if (ok) break;
+        }
+        is_base[b] = 1;
+        if (head) used[b + parem::kSparseHead] = 1;
+        for (uint32_t k = lo; k < hi; ++k) used[b + ekey[k]] = 1;
+        base[q] = b;
+        slots = std::max(slots, b + 257);
+        while (first_free < cap && used[first_free]) ++first_free;
+    }
+    return true;
+}
+
+bool sparse_slots(const DeviceDfa &d, const std::vector<uint32_t> &t, SparseImage &out) {
     // the invalid column A is reachable only when some byte is outside the alphabet
     bool invalid_used = false;
     for (uint32_t x = 0; x < 256; ++x) invalid_used |= d.cls[x] >= d.A;
@@ -113,69 +172,82 @@ bool sparse_slots(const DeviceDfa &d, const std::vector<uint32_t> &t, std::vecto
         for (uint32_t x = 0; x < 256; ++x) key[d.cls[x]] = x;
     const uint32_t rows = d.Q + 1;  // row Q, the sentinel, keeps every key in itself
     const uint32_t cap = (parem::kSparseLdsMax - 256) / 4;
-    std::vector<uint32_t> dflt(rows), eoff(rows + 1, 0), ekey, enext;
-    std::vector<uint32_t> next(ncol), count(rows, 0);
-    uint64_t need = 0;
+    auto next_of = [&](uint32_t q, uint32_t a) { return (q < d.Q && a < d.A) ? t[(size_t)q * d.A + a] : d.sent; };
+    // each row's own default (its most frequent next state)
+    std::vector<uint32_t> dflt(rows), count(rows, 0), votes(rows, 0);
     for (uint32_t q = 0; q < rows; ++q) {
-        for (uint32_t a = 0; a < ncol; ++a) next[a] = (q < d.Q && a < d.A) ? t[(size_t)q * d.A + a] : d.sent;
-        uint32_t df = next[0], best = 0;
+        uint32_t df = next_of(q, 0), best = 0;
         for (uint32_t a = 0; a < ncol; ++a)
-            if (++count[next[a]] > best) {
-                best = count[next[a]];
-                df = next[a];
+            if (++count[next_of(q, a)] > best) {
+                best = count[next_of(q, a)];
+                df = next_of(q, a);
             }
-        for (uint32_t a = 0; a < ncol; ++a) count[next[a]] = 0;
+        for (uint32_t a = 0; a < ncol; ++a) count[next_of(q, a)] = 0;
         dflt[q] = df;
-        for (uint32_t a = 0; a < ncol; ++a) {
-            if (next[a] == df) continue;
-            ekey.push_back(key[a]);
-            enext.push_back(next[a]);
+    }
+    uint32_t D = dflt[0], top = 0;
+    for (uint32_t q = 0; q < d.Q; ++q)
+        if (++votes[dflt[q]] > top) {
+            top = votes[dflt[q]];
+            D = dflt[q];
         }
-        eoff[q + 1] = (uint32_t)ekey.size();
-        need += eoff[q + 1] - eoff[q] + 1;
-        if (need > cap) return false;
-    }
-    std::vector<uint32_t> order(rows);
-    for (uint32_t q = 0; q < rows; ++q) order[q] = q;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](uint32_t x, uint32_t y) { return eoff[x + 1] - eoff[x] > eoff[y + 1] - eoff[y]; });
-    std::vector<uint8_t> used(cap, 0);
-    base.assign(rows, 0);
-    uint32_t first_free = 0, slots = 0;
-    uint64_t budget = 1ull << 27;  // candidate bases tried
-    for (const uint32_t q : order) {
-        const uint32_t lo = eoff[q], hi = eoff[q + 1];
-        uint32_t least = parem::kSparseHead;
-        for (uint32_t k = lo; k < hi; ++k) least = std::min(least, ekey[k]);
-        // a base below first_free - least would put the row's lowest slot on a used one
-        uint32_t b = first_free > least ? first_free - least : 0;
-        for (;; ++b) {
-            if (b + parem::kSparseHead >= cap || budget == 0) return false;
-            --budget;
-            bool ok = !used[b + parem::kSparseHead];
-            for (uint32_t k = lo; ok && k < hi; ++k) ok = !used[b + ekey[k]];
-            if (ok) break;
+    std::vector<uint32_t> base;
+    std::vector<uint8_t> used, is_base;
+    uint32_t slots = 0;
+    for (int form = 0; form < 2; ++form) {
+        const bool uni = form == 0;
+        // exceptions: columns whose next state is not the default in force
+        std::vector<uint32_t> eoff(rows + 1, 0), ekey, enext;
+        uint64_t need = 0;
+        bool fits = true;
+        for (uint32_t q = 0; q < rows && fits; ++q) {
+            const uint32_t df = uni ? D : dflt[q];
+            for (uint32_t a = 0; a < ncol; ++a) {
+                if (next_of(q, a) == df) continue;
+                ekey.push_back(key[a]);
+                enext.push_back(next_of(q, a));
+            }
+            eoff[q + 1] = (uint32_t)ekey.size();
+            need += eoff[q + 1] - eoff[q] + (uni ? 0 : 1);
+            fits = need <= cap;
         }
-        used[b + parem::kSparseHead] = 1;
-        for (uint32_t k = lo; k < hi; ++k) used[b + ekey[k]] = 1;
-        base[q] = b;
-        slots = std::max(slots, b + parem::kSparseHead + 1);
-        while (first_free < cap && used[first_free]) ++first_free;
+        if (!fits || !place_rows(eoff, ekey, !uni, cap, base, used, is_base, slots)) continue;
+        slots = (slots + 3) / 4 * 4;
+        if (256 + (size_t)slots * 4 > parem::kSparseLdsMax) continue;
+        std::vector<uint32_t> w(slots, 0xffff0000u);
+        if (uni) {
+            // a free slot's key field: a byte x with no row based at j - x
+            bool ok = true;
+            for (uint32_t j = 0; j < slots && ok; ++j) {
+                if (j < cap && used[j]) continue;
+                uint32_t x = 0;
+                while (x < 256 && x <= j && j - x < cap && is_base[j - x]) ++x;
+                ok = x < 256;
+                w[j] = 0xffffu | x << 24;
+            }
+            if (!ok) continue;
+        }
+        auto walk_value = [&](uint32_t q) { return base[q] | (uni ? (uint32_t)d.final_flag[q] << 16 : 0u); };
+        for (uint32_t q = 0; q < rows; ++q) {
+            const uint32_t b = base[q];
+            for (uint32_t k = eoff[q]; k < eoff[q + 1]; ++k)
+                w[b + ekey[k]] = uni ? walk_value(enext[k]) | ekey[k] << 24 : base[enext[k]] | ekey[k] << 16;
+            if (!uni) w[b + parem::kSparseHead] = base[dflt[q]] | (uint32_t)d.final_flag[q] << 16 | 1u << 24;
+        }
+        out.image.assign(256 + (size_t)slots * 4, 0);
+        for (uint32_t x = 0; x < 256; ++x) out.image[x] = (uint8_t)d.cls[x];
+        std::memcpy(out.image.data() + 256, w.data(), (size_t)slots * 4);
+        out.sids.assign(slots, 0xffffu);
+        out.walk.assign(rows, 0);
+        for (uint32_t q = 0; q < rows; ++q) {
+            out.sids[base[q]] = (uint16_t)q;
+            out.walk[q] = walk_value(q);
+        }
+        out.uniform = uni;
+        out.d0 = uni ? walk_value(D) : 0u;
+        return true;
     }
-    slots = (slots + 3) / 4 * 4;
-    if (256 + (size_t)slots * 4 > parem::kSparseLdsMax) return false;
-    image.assign(256 + (size_t)slots * 4, 0);
-    for (uint32_t x = 0; x < 256; ++x) image[x] = (uint8_t)d.cls[x];
-    std::vector<uint32_t> w(slots, 0xffff0000u);
-    sids.assign(slots, 0xffffu);
-    for (uint32_t q = 0; q < rows; ++q) {
-        const uint32_t b = base[q];
-        w[b + parem::kSparseHead] = base[dflt[q]] | (uint32_t)d.final_flag[q] << 16 | 1u << 24;
-        for (uint32_t k = eoff[q]; k < eoff[q + 1]; ++k) w[b + ekey[k]] = base[enext[k]] | ekey[k] << 16;
-        sids[b] = (uint16_t)q;
-    }
-    std::memcpy(image.data() + 256, w.data(), (size_t)slots * 4);
-    return true;
+    return false;
 }
 
 // Hot-row layout. The hot states are the kHotMax states of largest weight
@@ -463,12 +535,10 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
     // automatic choice: k-gram, LDS byte table, column-indexed LDS table, then
     // sparse rows when every row qualifies (checked once), hot rows only when
     // they hold most of the walk's weight, else the byte table through L2
-    std::vector<uint8_t> sparse_image;
-    std::vector<uint32_t> sparse_base;
-    std::vector<uint16_t> sparse_sids;
+    SparseImage sparse;
     const bool big_auto = layout == PAREM_LAYOUT_AUTO && !kg_ok && !lds_ok && !class_ok;
     const bool sparse_ok = (big_auto || layout == PAREM_LAYOUT_SPARSE_LDS) &&
-                           sparse_slots(d, t, sparse_image, sparse_base, sparse_sids);
+                           sparse_slots(d, t, sparse);
     const bool hot_auto = hot_ok && !kg_ok && !lds_ok && !class_ok && !(big_auto && sparse_ok) &&
                           hot_share(d, t, hot_order) >= 0.9;
     const uint32_t big = hot_auto ? PAREM_LAYOUT_HOT_LDS : PAREM_LAYOUT_BYTE_GLOBAL;
@@ -489,6 +559,8 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
         bool all_valid = true;
         for (uint32_t x = 0; x < 256; ++x) all_valid &= d.cls[x] < d.A;
         d.sparse_raw = all_valid;
+        d.sparse_uniform = sparse.uniform;
+        d.sparse_d0 = sparse.d0;
     }
     if (layout != PAREM_LAYOUT_KGRAM_LDS) {
         d.kgram = 0;
@@ -537,12 +609,12 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
         } else if (layout == PAREM_LAYOUT_SPARSE_LDS) {
             d.entry_bytes = 4;
             d.row_stride = 0;
-            d.table_bytes = (uint32_t)sparse_image.size();
+            d.table_bytes = (uint32_t)sparse.image.size();
             d.lds_bytes = d.table_bytes;
             uint8_t *p = nullptr;
-            st = upload(sparse_image, &p);
+            st = upload(sparse.image, &p);
             d.d_table = p;
-            if (st == PAREM_OK) st = upload(sparse_sids, &d.d_sids);
+            if (st == PAREM_OK) st = upload(sparse.sids, &d.d_sids);
             // batches walk such a table as the byte table through L2
             if (st == PAREM_OK) st = upload(byte_table<uint16_t>(d, t, 256), &d.d_bytes);
         } else if (layout == PAREM_LAYOUT_HOT_LDS) {
@@ -580,7 +652,7 @@ parem_status parem_compile(const void *table, int entry_bytes, uint32_t num_stat
         // lookup of the encoding per walk
         std::vector<uint32_t> enc_list(d.llist.size());
         for (size_t k = 0; k < d.llist.size(); ++k)
-            enc_list[k] = layout == PAREM_LAYOUT_HOT_LDS ? hot_enc[d.llist[k]] : sparse_base[d.llist[k]];
+            enc_list[k] = layout == PAREM_LAYOUT_HOT_LDS ? hot_enc[d.llist[k]] : sparse.walk[d.llist[k]];
         st = upload(enc_list, &d.d_llist_walk);
     }
     if (st == PAREM_OK) st = upload(d.final_flag, &d.d_final);

@@ -146,26 +146,36 @@ struct ClassStep {
 // without the text staging area, so lanes load their chunks 16 bytes at a
 // time themselves (the lines stay in L2 between a lane's loads).
 // Sparse layout: the table's rows displaced into one vector of u32 slots.
-// The walk's state is its row's base slot b. The slot b + k holds the step on
-// key k (a byte when every byte is valid, RAW, else the byte's column) when
-// its high half is k: its low half is the next state's base. Otherwise the
-// step takes the row's default, the low half of the header slot b + 256,
-// whose bits 16-23 hold the final flag of the row's own state. A step is two
-// independent LDS reads (slot and header, both addressed from b), a compare,
-// a select and the count's add; the add of b and the key takes the byte
-// straight out of the text dword, and the compare and the select take their
-// halves straight out of the slots (SDWA operand selects, written out below
-// because the compiler extracts them with extra instructions). The count
-// takes the flag of the state a step leaves, so it is shifted by one step:
-// it starts at minus the start state's flag and the end state's flag is
-// added when the walk is stored (kDeferredCount).
+// The slot at row base b + k holds the step on key k (a byte when every
+// byte is valid, RAW, else the byte's column) when its key field is k;
+// otherwise the step takes the default. Two forms:
+//
+// UNI (every row shares one default): the walk's state is the row's base
+// (bits 0-15) with the state's final flag in bits 16-23 (bits 24-31 carry
+// whatever key led there and are ignored). A slot holds the next state's
+// value in bits 0-23 and its key in bits 24-31; the default's value is a
+// kernel argument. A step is one LDS read, a compare, a select and the
+// count's add.
+//
+// General: the state is the base; the slot's key is its high half, and the
+// header slot b + 256 holds the row's own default (low half) and the final
+// flag of the row's state (bits 16-23). A step is two independent LDS reads
+// (slot and header), a compare, a select and the count's add.
+//
+// The add of the base and the key takes the byte straight out of the text
+// dword, and the compare and the select take their fields straight out of
+// the slots (SDWA operand selects, written out below because the compiler
+// extracts them with extra instructions). The count takes the flag of the
+// state a step leaves, so it is shifted by one step: it starts at minus the
+// start state's flag and the end state's flag is added when the walk is
+// stored (kDeferredCount).
 //
 // KSEL selects the byte of `key` used (BYTE_k of a text dword, or DWORD for a
 // column). A VALU write of VCC needs two wait states before v_cndmask reads
 // it: the count's add and one s_nop.
-#define PAREM_SPARSE_KEYADD(KSEL)                                                                       \
-    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:" KSEL " src1_sel:DWORD" \
-        : "=v"(u)                                                                                       \
+#define PAREM_SPARSE_KEYADD(KSEL)                                                                      \
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:" KSEL " src1_sel:WORD_0" \
+        : "=v"(u)                                                                                      \
         : "v"(key), "v"(s))
 #define PAREM_SPARSE_STEP(KSEL)                                                                                  \
     asm("v_cmp_eq_u32_sdwa vcc, %2, %3 src0_sel:WORD_1 src1_sel:" KSEL "\n\t"                                  \
@@ -175,8 +185,16 @@ struct ClassStep {
         : "=&v"(v), "+v"(c)                                                                                      \
         : "v"(e), "v"(key), "v"(h)                                                                               \
         : "vcc")
+#define PAREM_SPARSE_STEP_UNI(KSEL)                                                                        \
+    asm("v_cmp_eq_u32_sdwa vcc, %2, %3 src0_sel:BYTE_3 src1_sel:" KSEL "\n\t"                            \
+        "v_add_u32_sdwa %1, %1, %4 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2\n\t" \
+        "s_nop 0\n\t"                                                                                      \
+        "v_cndmask_b32_e32 %0, %5, %2, vcc"                                                                \
+        : "=&v"(v), "+v"(c)                                                                                \
+        : "v"(e), "v"(key), "v"(s), "v"(d0)                                                                \
+        : "vcc")
 
-template <bool RAW>
+template <bool RAW, bool UNI>
 struct SparseStep {
     static constexpr bool kRedo = false;
     static constexpr bool kPrefixPasses = true;
@@ -191,12 +209,19 @@ struct SparseStep {
     static constexpr uint32_t kHeads = kSlots + 4 * kSparseHead;
     const uint8_t *__restrict__ col;    // LDS: [256] byte -> column (unused when RAW)
     const uint16_t *__restrict__ sids;  // global: state of the row based at each slot
+    uint32_t d0;                        // UNI: the default's value
 
-    // walks start from the lists of bases
+    // walks start from the lists of walk values
     __device__ __forceinline__ uint32_t init(uint32_t s) const { return s; }
-    __device__ __forceinline__ uint32_t id(uint32_t r) const { return sids[r]; }
-    __device__ __forceinline__ bool same(uint32_t a, uint32_t b) const { return a == b; }
-    __device__ __forceinline__ uint32_t fin(uint32_t r) const { return (lds_abs<uint32_t>(kHeads + 4u * r) >> 16) & 0xffu; }
+    __device__ __forceinline__ uint32_t id(uint32_t r) const { return sids[r & 0xffffu]; }
+    __device__ __forceinline__ bool same(uint32_t a, uint32_t b) const {
+        if constexpr (UNI) return ((a ^ b) & 0xffffu) == 0;
+        else return a == b;
+    }
+    __device__ __forceinline__ uint32_t fin(uint32_t r) const {
+        if constexpr (UNI) return (r >> 16) & 0xffu;
+        else return (lds_abs<uint32_t>(kHeads + 4u * r) >> 16) & 0xffu;
+    }
     // K = 0..3: the key is byte K of `key` (a text dword); K = 4: `key` is a column
     template <int K>
     __device__ __forceinline__ void one(uint32_t &s, uint32_t &c, uint32_t key) const {
@@ -205,14 +230,22 @@ struct SparseStep {
         else if constexpr (K == 1) PAREM_SPARSE_KEYADD("BYTE_1");
         else if constexpr (K == 2) PAREM_SPARSE_KEYADD("BYTE_2");
         else if constexpr (K == 3) PAREM_SPARSE_KEYADD("BYTE_3");
-        else u = s + key;
+        else PAREM_SPARSE_KEYADD("DWORD");
         const uint32_t e = lds_abs<uint32_t>(kSlots + 4u * u);
-        const uint32_t h = lds_abs<uint32_t>(kHeads + 4u * s);
-        if constexpr (K == 0) PAREM_SPARSE_STEP("BYTE_0");
-        else if constexpr (K == 1) PAREM_SPARSE_STEP("BYTE_1");
-        else if constexpr (K == 2) PAREM_SPARSE_STEP("BYTE_2");
-        else if constexpr (K == 3) PAREM_SPARSE_STEP("BYTE_3");
-        else PAREM_SPARSE_STEP("DWORD");
+        if constexpr (UNI) {
+            if constexpr (K == 0) PAREM_SPARSE_STEP_UNI("BYTE_0");
+            else if constexpr (K == 1) PAREM_SPARSE_STEP_UNI("BYTE_1");
+            else if constexpr (K == 2) PAREM_SPARSE_STEP_UNI("BYTE_2");
+            else if constexpr (K == 3) PAREM_SPARSE_STEP_UNI("BYTE_3");
+            else PAREM_SPARSE_STEP_UNI("DWORD");
+        } else {
+            const uint32_t h = lds_abs<uint32_t>(kHeads + 4u * s);
+            if constexpr (K == 0) PAREM_SPARSE_STEP("BYTE_0");
+            else if constexpr (K == 1) PAREM_SPARSE_STEP("BYTE_1");
+            else if constexpr (K == 2) PAREM_SPARSE_STEP("BYTE_2");
+            else if constexpr (K == 3) PAREM_SPARSE_STEP("BYTE_3");
+            else PAREM_SPARSE_STEP("DWORD");
+        }
         s = v;
     }
     template <int K, int G>
@@ -245,6 +278,7 @@ struct SparseStep {
 };
 #undef PAREM_SPARSE_KEYADD
 #undef PAREM_SPARSE_STEP
+#undef PAREM_SPARSE_STEP_UNI
 
 // Hot-row layout: the byte-table rows of the H most visited states sit in
 // LDS, the other rows are read through L2. A walk carries its state encoded:

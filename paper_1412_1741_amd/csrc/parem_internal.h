@@ -78,6 +78,8 @@ struct DeviceDfa {
     uint16_t *d_coltab = nullptr;    // [(Q+1) x (A+1)] next state by column | final << 15 (match positions)
     uint32_t hot_rows = 0;
     bool sparse_raw = false;         // sparse rows are keyed by bytes, not columns (every byte valid)
+    bool sparse_uniform = false;     // sparse rows share one default (no header slots)
+    uint32_t sparse_d0 = 0;          // that default's walk value (base | final flag << 16)
 };
 
 // hot-row layout: at most kHotMax rows of kHotRow u16 entries (256 bytes plus

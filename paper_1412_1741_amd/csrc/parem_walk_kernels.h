@@ -61,15 +61,16 @@ __global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_walk_class(W
 }
 
 // one workgroup of kSparseThreads per CU: four waves per SIMD
-template <int G, bool ALIGNED, int MODE, bool RAW>
+template <int G, bool ALIGNED, int MODE, bool RAW, bool UNI>
 __global__ __launch_bounds__(kSparseThreads) void k_walk_sparse(WalkArgs a, const uint8_t *__restrict__ g_table,
                                                                 uint32_t table_bytes,
-                                                                const uint16_t *__restrict__ sids) {
+                                                                const uint16_t *__restrict__ sids, uint32_t d0) {
     extern __shared__ __align__(16) uint8_t smem[];
     stage_table<kSparseThreads>(reinterpret_cast<uint4 *>(smem), reinterpret_cast<const uint4 *>(g_table),
                                 table_bytes / 16u);
-    SparseStep<RAW> st{smem, sids};
-    walk_chunk<G, SparseStep<RAW>, ALIGNED, 64, MODE>(st, a, smem + table_bytes, (uint64_t)blockIdx.x * kSparseThreads);
+    SparseStep<RAW, UNI> st{smem, sids, d0};
+    walk_chunk<G, SparseStep<RAW, UNI>, ALIGNED, 64, MODE>(st, a, smem + table_bytes,
+                                                           (uint64_t)blockIdx.x * kSparseThreads);
 }
 
 template <int G, int B, bool ALIGNED, uint32_t TILE, int MODE>
@@ -131,24 +132,29 @@ inline void launch_walk_class(const DeviceDfa &d, const PlainPlan &p, const Walk
 }
 
 // the table, then (aligned texts) a 64-byte text tile per wave
-template <bool ALIGNED, int MODE, bool RAW>
+template <bool ALIGNED, int MODE, bool RAW, bool UNI>
 inline void launch_walk_sparse_t(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, hipStream_t stream) {
     const uint32_t grid = (uint32_t)((p.chunks + kSparseThreads - 1) / kSparseThreads);
-    using SG = Stage<64, SparseStep<RAW>::kSwizzle>;
+    using SG = Stage<64, SparseStep<RAW, UNI>::kSwizzle>;
     static_assert(kSparseLdsMax + (kSparseThreads / 64) * SG::kWave <= 160 * 1024, "slots and tiles exceed LDS");
     const size_t lds = d.table_bytes + ((ALIGNED && MODE != WALK_REDO) ? (kSparseThreads / 64) * SG::kWave : 0);
     const uint8_t *tab = reinterpret_cast<const uint8_t *>(d.d_table);
 #define PAREM_SPR(GG)                                                                                           \
-    hipLaunchKernelGGL((k_walk_sparse<GG, ALIGNED, MODE, RAW>), dim3(grid), dim3(kSparseThreads), lds, stream, a, \
-                       tab, d.table_bytes, d.d_sids)
+    hipLaunchKernelGGL((k_walk_sparse<GG, ALIGNED, MODE, RAW, UNI>), dim3(grid), dim3(kSparseThreads), lds, stream, \
+                       a, tab, d.table_bytes, d.d_sids, d.sparse_d0)
     PAREM_GROUP_SWITCH(PAREM_SPR)
 #undef PAREM_SPR
 }
 
 template <bool ALIGNED, int MODE>
 inline void launch_walk_sparse(const DeviceDfa &d, const PlainPlan &p, const WalkArgs &a, hipStream_t stream) {
-    if (d.sparse_raw) launch_walk_sparse_t<ALIGNED, MODE, true>(d, p, a, stream);
-    else launch_walk_sparse_t<ALIGNED, MODE, false>(d, p, a, stream);
+    if (d.sparse_raw) {
+        if (d.sparse_uniform) launch_walk_sparse_t<ALIGNED, MODE, true, true>(d, p, a, stream);
+        else launch_walk_sparse_t<ALIGNED, MODE, true, false>(d, p, a, stream);
+    } else {
+        if (d.sparse_uniform) launch_walk_sparse_t<ALIGNED, MODE, false, true>(d, p, a, stream);
+        else launch_walk_sparse_t<ALIGNED, MODE, false, false>(d, p, a, stream);
+    }
 }
 
 template <int LAYOUT, bool ALIGNED, uint32_t TILE, int MODE>
