@@ -242,11 +242,13 @@ def test_hot_rows_sparse_and_dense(group):
 def test_sparse_rows(group):
     """Sparse layout (rows of a default and a few exceptions displaced into
     one vector of slots): a byte DFA with explicit columns among 64 Zipf
-    symbols, the same table with a default per state other than state 0, a
-    20-symbol alphabet whose invalid column is one of the exceptions (and a
-    text with a byte outside it), lookback sets, a table with five
-    exceptions in every row, and one whose slots do not fit LDS, which falls
-    back to another layout."""
+    symbols (one default for every row: the uniform form), the same table
+    with a default per state other than state 0 (per-row defaults: the
+    general form), a 200-byte alphabet with per-row defaults (general form
+    keyed by columns, with the invalid column), a 20-symbol alphabet whose
+    invalid column is one of the exceptions (and a text with a byte outside
+    it), lookback sets, a table with five exceptions in every row, and one
+    whose slots do not fit LDS, which falls back to another layout."""
     rng = np.random.default_rng(900 + group)
     sym = rng.choice(256, size=64, replace=False).astype(np.uint8)
     acc = rng.choice(np.arange(1, 3000), size=16, replace=False)
@@ -269,6 +271,16 @@ def test_sparse_rows(group):
     assert m.describe()["layout"] == P.LAYOUT_SPARSE_LDS
     m.close()
     run_case(f"sparse defaults G={group}", shifted, text, chunk_len=512, group=group, layout=P.LAYOUT_SPARSE_LDS)
+    a200 = bytes(np.sort(rng.choice(256, size=200, replace=False)).astype(np.uint8))
+    cols = W.sparse_dfa(rng, 1500, a200, 1, 3, acc[:5] % 1500)
+    cdef = (np.arange(1500, dtype=np.uint32) % 89 + 2)[:, None]
+    cols = W.Dfa(np.where(cols.table == 0, cdef, cols.table).astype(np.uint32), a200, 3, cols.accepting)
+    m = P.Matcher(cols.table, cols.alphabet, cols.start, cols.accepting, layout=P.LAYOUT_SPARSE_LDS)
+    assert m.describe()["layout"] == P.LAYOUT_SPARSE_LDS
+    m.close()
+    ctext = W.uniform_text(rng, a200, 400_003)
+    run_case(f"sparse column defaults G={group}", cols, ctext, chunk_len=512, group=group,
+             layout=P.LAYOUT_SPARSE_LDS)
     a20 = bytes(rng.choice(256, size=20, replace=False).astype(np.uint8))
     small = W.sparse_dfa(rng, 400, a20, 0, 3, rng.choice(np.arange(1, 400), size=9, replace=False))
     m = P.Matcher(small.table, small.alphabet, small.start, small.accepting, layout=P.LAYOUT_SPARSE_LDS,
