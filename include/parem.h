@@ -99,8 +99,11 @@ typedef struct {
                              bytes before the chunk (K capped at the chunk's
                              offset), a subset of R_c that still holds the true
                              entry state, so results are identical; chunks
-                             whose image has more than 64 states use R_c. At
-                             most 4096; ignored when Q >= 16384. Not with
+                             whose image has more than 64 states use R_c (32
+                             for a sparse-layout handle whose rows share one
+                             default and whose alphabet is every byte, with
+                             K <= 16: its sets are read from the slot image).
+                             At most 4096; ignored when Q >= 16384. Not with
                              partial tables or the Enumeration policy.       */
     uint32_t partial;     /* 1: the table is a partial DFA (Section II-B): an
                              entry equal to the all-ones value of its width

@@ -497,6 +497,114 @@ __global__ __launch_bounds__(256) void k_lookback(LookArgs a, uint32_t start, ui
     lookback_chunk(a, start, c, smem + (threadIdx.x >> 6) * wave_bytes);
 }
 
+// Lookback sets over the sparse layout's slot image (uniform form, every
+// byte valid; windows of 2..kSlotLookMaxK bytes, at most the chunk length):
+// one lane per chunk instead of one wave, the image read from LDS. The image
+// of every state under the window's first byte is that byte's class list;
+// each further byte maps the states collected so far through one slot read
+// each. The shared default D is kept as a flag, since most states fall back
+// to it; the others (at most kSlotLookCap, else the chunk walks its whole
+// set) sit in LDS, element k of thread t at k * kSparseThreads + t.
+// Duplicates are dropped at the end; the states become positions in the
+// class list of the chunk's previous byte (ascending, as k_lookback writes
+// them). Chunk 0 starts in q0 at position 0 of the start class.
+constexpr uint32_t kSlotLookCap = 32;
+constexpr uint32_t kSlotLookMaxK = 16;
+static_assert(kSparseLdsMax + kSlotLookCap * kSparseThreads * 2 <= 160 * 1024, "slot lookback exceeds LDS");
+
+__global__ __launch_bounds__(kSparseThreads) void k_lookback_slots(LookArgs a, const uint32_t *__restrict__ walk_list,
+                                                                   const uint8_t *__restrict__ g_table,
+                                                                   uint32_t table_bytes,
+                                                                   const uint16_t *__restrict__ sids, uint32_t d0) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    stage_table<kSparseThreads>(reinterpret_cast<uint4 *>(smem), reinterpret_cast<const uint4 *>(g_table),
+                                table_bytes / 16u);
+    // no workgroup barrier follows: lanes past the last chunk leave
+    const uint64_t c = (uint64_t)blockIdx.x * kSparseThreads + threadIdx.x;
+    if (c >= a.nchunks) return;
+    uint16_t *out = a.sel + c * kLookCap;
+    if (c == 0) {
+        a.nsel[0] = 1;
+        out[0] = 0;
+        return;
+    }
+    uint16_t *buf = reinterpret_cast<uint16_t *>(smem + table_bytes) + threadIdx.x;
+    constexpr uint32_t T = kSparseThreads;
+    const uint32_t dbase = d0 & 0xffffu;
+    // slot-image step of the uniform form (the slots start at LDS address 256)
+    auto step = [&](uint32_t base, uint32_t x) -> uint32_t {
+        const uint32_t e = lds_abs<uint32_t>(256u + 4u * (base + x));
+        return (e >> 24) == x ? (e & 0xffffu) : dbase;
+    };
+    const uint8_t *win = a.text + (c * (uint64_t)a.L - a.K);
+    const uint32_t cl0 = a.cls[win[0]];
+    const uint32_t lo = a.loff[cl0], hi = a.loff[cl0 + 1];
+    uint32_t n = 0;
+    bool has_d = false, over = false;
+    const uint32_t x1 = win[1];
+    // eight list entries loaded before their steps (the list is read through L2)
+    for (uint32_t i0 = lo; i0 < hi && !over; i0 += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u) v[u] = walk_list[min(i0 + u, hi - 1)];
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u) {
+            if (i0 + u >= hi) break;
+            const uint32_t r = step(v[u] & 0xffffu, x1);
+            if (r == dbase) has_d = true;
+            else if (n < kSlotLookCap) buf[T * n++] = (uint16_t)r;
+            else over = true;
+        }
+    }
+    for (uint32_t k = 2; k < a.K && !over; ++k) {
+        const uint32_t x = win[k];
+        uint32_t m = 0;
+        bool nd = false;
+        for (uint32_t j = 0; j < n; ++j) {  // in place: m <= j
+            const uint32_t r = step(buf[T * j], x);
+            if (r == dbase) nd = true;
+            else buf[T * m++] = (uint16_t)r;
+        }
+        if (has_d) {
+            const uint32_t r = step(dbase, x);
+            if (r == dbase) nd = true;
+            else if (m < kSlotLookCap) buf[T * m++] = (uint16_t)r;
+            else over = true;
+        }
+        n = m;
+        has_d = nd;
+    }
+    if (!over && has_d) {
+        if (n < kSlotLookCap) buf[T * n++] = (uint16_t)dbase;
+        else over = true;
+    }
+    if (over) {
+        a.nsel[c] = 0;  // the whole set
+        return;
+    }
+    // positions in the class list of the previous byte, sorted, duplicates dropped
+    const uint16_t *pos = a.inv + (size_t)a.cls[win[a.K - 1]] * (a.Q + 1);
+    uint32_t cnt = 0;
+    bool missing = false;
+    for (uint32_t j = 0; j < n; ++j) {
+        const uint32_t id = sids[buf[T * j]];
+        const uint32_t p = id <= a.Q ? pos[id] : 0xffffu;
+        missing |= p == 0xffffu;
+        uint32_t at = cnt;
+        while (at > 0 && out[at - 1] > p) --at;
+        if (at > 0 && out[at - 1] == p) continue;
+        for (uint32_t q = cnt; q > at; --q) out[q] = out[q - 1];
+        out[at] = (uint16_t)p;
+        ++cnt;
+    }
+    a.nsel[c] = missing ? 0 : (uint8_t)cnt;  // a state outside R_c cannot occur
+}
+
+static bool slot_lookback(const DeviceDfa &d, const PlainPlan &p) {
+    return d.layout == PAREM_LAYOUT_SPARSE_LDS && d.sparse_uniform && d.sparse_raw && p.look >= 2 &&
+           p.look <= kSlotLookMaxK && p.look <= p.L;
+}
+
 __global__ void k_learned_total(const unsigned long long *__restrict__ acc, parem_result *__restrict__ result) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         result->spec_runs = acc[0];
@@ -741,9 +849,16 @@ void launch_walk_phase(const DeviceDfa &d, const PlainPlan &p, WalkArgs &a, cons
     const uint32_t g = (uint32_t)((p.chunks + 255) / 256);
     if (p.look) {
         const LookArgs la = look_args(d, p, d_text, ws);
-        const uint32_t wb = look_wave_bytes(la.words);
-        hipLaunchKernelGGL(k_lookback, dim3((uint32_t)((p.chunks + 3) / 4)), dim3(256), 4 * wb, stream, la, d.start, wb,
-                           nullptr);
+        if (slot_lookback(d, p)) {
+            const size_t lds = d.table_bytes + (size_t)kSlotLookCap * kSparseThreads * 2;
+            hipLaunchKernelGGL(k_lookback_slots, dim3((uint32_t)((p.chunks + kSparseThreads - 1) / kSparseThreads)),
+                               dim3(kSparseThreads), lds, stream, la, d.d_llist_walk,
+                               reinterpret_cast<const uint8_t *>(d.d_table), d.table_bytes, d.d_sids, d.sparse_d0);
+        } else {
+            const uint32_t wb = look_wave_bytes(la.words);
+            hipLaunchKernelGGL(k_lookback, dim3((uint32_t)((p.chunks + 3) / 4)), dim3(256), 4 * wb, stream, la,
+                               d.start, wb, nullptr);
+        }
         a.sel = la.sel;
         a.nsel = la.nsel;
         a.sel_stride = kLookCap;

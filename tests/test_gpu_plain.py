@@ -265,6 +265,14 @@ def test_sparse_rows(group):
              layout=P.LAYOUT_SPARSE_LDS)
     run_case(f"sparse lookback G={group}", sp, text, chunk_len=2048, group=group, layout=P.LAYOUT_SPARSE_LDS,
              lookback=64, check_spec=False)
+    # windows of 2..16 bytes: lookback sets read from the slot image, one lane a chunk
+    full = expected_spec_runs(sp, text, 2048)
+    for k in (2, 4, 16):
+        got = run_case(f"sparse slot lookback K={k} G={group}", sp, text, chunk_len=2048, group=group,
+                       layout=P.LAYOUT_SPARSE_LDS, lookback=k, check_spec=False)
+        assert got.spec_runs < full / 4, (got.spec_runs, full)
+    run_case(f"sparse slot lookback tiny G={group}", sp, text[:5000], chunk_len=64, group=group, offset=3,
+             layout=P.LAYOUT_SPARSE_LDS, lookback=16, check_spec=False)
     dflt = (np.arange(3000, dtype=np.uint32) % 97 + 1)[:, None]
     shifted = W.Dfa(np.where(sp.table == 0, dflt, sp.table).astype(np.uint32), sp.alphabet, 5, sp.accepting)
     m = P.Matcher(shifted.table, shifted.alphabet, shifted.start, shifted.accepting, layout=P.LAYOUT_SPARSE_LDS)
@@ -364,6 +372,8 @@ def test_sparse4096_reduced():
     assert m.describe()["layout"] == P.LAYOUT_SPARSE_LDS
     m.close()
     run_case("sparse4096 64MiB hot rows", dfa, text, layout=P.LAYOUT_HOT_LDS)
+    got = run_case("sparse4096 64MiB lookback 4", dfa, text, lookback=4, check_spec=False)
+    assert got.spec_runs < 2 * got.chunks, (got.spec_runs, got.chunks)
 
 
 def test_batch_sample_pairs():
