@@ -158,6 +158,7 @@ struct PlainPlan {
     uint64_t bytes = 0;
     uint64_t off_map = 0, off_mcls = 0, off_mlead = 0, off_dummy = 0;
     uint64_t off_sel = 0, off_nsel = 0, off_redo = 0, off_done = 0, off_flags = 0, off_mlp = 0, off_rlist = 0, off_part = 0;
+    uint64_t off_todo = 0;   // wide maps (P <= 64): per first-level group, 1 when it needs the LDS tree
 };
 
 constexpr uint32_t kByteLdsRow = 260;  // row stride of the LDS byte table

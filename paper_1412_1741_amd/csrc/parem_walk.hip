@@ -47,6 +47,88 @@ __global__ __launch_bounds__(kComposeThreads) void k_compose_chunks(const uint32
     compose_chunks_seg(smem, map, map_cls, map_lead, a, o, blockIdx.x, result);
 }
 
+// First level for wide maps (P <= 64 chunk maps a group, so the LDS tree
+// allows few groups per CU): one wave per group. A group whose maps are all
+// uniform composes here, as compose_chunks_seg does it (each map sends every
+// walk to its lead: chain the leads through the maps, sum the counts, and
+// give each entry of the group's first map the chain's end); a group with a
+// non-uniform map is flagged in `todo` (one u32 per group, written by every
+// group) for k_compose_chunks_list.
+__global__ __launch_bounds__(256) void k_compose_chunks_uniform(const uint32_t *__restrict__ map,
+                                                                const uint16_t *__restrict__ map_cls,
+                                                                const uint16_t *__restrict__ map_lead, ComposeArgs a,
+                                                                SegOut o, uint64_t ngroups, uint32_t *__restrict__ todo) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t seg = (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6);
+    if (seg >= ngroups) return;  // whole waves leave; no workgroup barrier follows
+    const uint64_t g0 = seg * a.P, C = a.chunks;
+    const uint32_t np = (uint32_t)min((uint64_t)a.P, C - g0);
+    uint32_t cl = 0, sz = 0, lead = 0;
+    bool nonuni = false;
+    if (lane < np) {
+        const uint32_t v = map_cls[g0 + lane];
+        cl = v & 0x7fffu;
+        sz = a.loff[cl + 1] - a.loff[cl];
+        nonuni = (v & 0x8000u) != 0;
+        lead = map_lead[g0 + lane];
+    }
+    const bool tree = __any(nonuni);
+    if (lane == 0) todo[seg] = tree ? 1u : 0u;
+    if (tree) return;
+    const uint32_t prev = (uint32_t)__shfl_up((int)lead, 1, 64);
+    unsigned long long contrib = 0;
+    int fail = 0;
+    if (lane >= 1 && lane < np) {
+        int x = -1;
+        if (prev < a.Q1) {
+            if (a.inv) {
+                const uint32_t v = a.inv[cl * a.Q1 + prev];
+                x = v == 0xffffu ? -1 : (int)v;
+            } else {
+                x = find_state(a.llist + a.loff[cl], sz, prev);
+            }
+        }
+        const uint32_t v = x < 0 ? kAbsent16 : map[(uint64_t)x * C + g0 + lane];
+        if ((v & 0xffffu) == kAbsent16) fail = 1;
+        else contrib = v >> 16;
+    }
+    unsigned long long runs = sz;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        contrib += (unsigned long long)__shfl_xor((long long)contrib, off, 64);
+        runs += (unsigned long long)__shfl_xor((long long)runs, off, 64);
+    }
+    fail = __any(fail);
+    const uint32_t last = (uint32_t)__shfl((int)lead, (int)np - 1, 64);
+    const uint32_t end = fail ? a.sent : last;
+    const uint32_t sz0 = (uint32_t)__shfl((int)sz, 0, 64), cl0 = (uint32_t)__shfl((int)cl, 0, 64);
+    for (uint32_t j = lane; j < sz0; j += 64) {
+        const uint32_t v = map[(uint64_t)j * C + g0];
+        o.end[seg * a.RM + j] = (v & 0xffffu) != kAbsent16 ? end : kAbsent32;
+        o.cnt[seg * a.RM + j] = (uint64_t)(v >> 16) + contrib;
+    }
+    if (lane == 0) {
+        o.cls[seg] = cl0;
+        o.runs[seg] = runs;
+        o.lead[seg] = end;
+    }
+}
+
+// the first-level groups k_compose_chunks_uniform flagged, through the LDS
+// tree; workgroups stride over the groups
+__global__ __launch_bounds__(kComposeThreads) void k_compose_chunks_list(const uint32_t *__restrict__ map,
+                                                                          const uint16_t *__restrict__ map_cls,
+                                                                          const uint16_t *__restrict__ map_lead,
+                                                                          ComposeArgs a, SegOut o, uint64_t ngroups,
+                                                                          const uint32_t *__restrict__ todo) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    for (uint64_t k = blockIdx.x; k < ngroups; k += gridDim.x) {
+        if (!todo[k]) continue;  // the same for the whole workgroup
+        compose_chunks_seg(smem, map, map_cls, map_lead, a, o, k, nullptr);
+        __syncthreads();  // the next group reuses the LDS
+    }
+}
+
 __global__ __launch_bounds__(kComposeThreads) void k_compose_segs(SegOut in, uint64_t nin, ComposeArgs a, SegOut o,
                                                                    parem_result *__restrict__ result) {
     extern __shared__ __align__(16) uint8_t smem[];
@@ -763,6 +845,9 @@ parem_status plan_chunks(const DeviceDfa &d, uint64_t len, const parem_options &
         g.runs = take(cap * 8);
         g.lead = take(cap * 4);
     }
+    // wide maps: first-level groups of uniform maps compose one wave each,
+    // the others are listed for the LDS tree
+    q.off_todo = (P <= 64 && q.levels[0] > 1) ? take(q.levels[0] * 4) : 0;
     q.keep = keep;
     q.bytes = off;
     *p = q;
@@ -803,8 +888,19 @@ static parem_status launch_compose(const DeviceDfa &d, const PlainPlan &p, uint8
     const uint16_t *mcl = reinterpret_cast<const uint16_t *>(ws + p.off_mcls);
     const uint16_t *mld = reinterpret_cast<const uint16_t *>(ws + p.off_mlead);
     uint64_t nin = p.levels[0];
-    hipLaunchKernelGGL(k_compose_chunks, dim3((uint32_t)nin), dim3(kComposeThreads), lds, stream, map, mcl, mld, a,
-                       seg_out(p, ws, 0), nin == 1 ? d_out : nullptr);
+    if (p.off_todo) {
+        if (lds > 64 * 1024 && hipFuncSetAttribute(reinterpret_cast<const void *>(k_compose_chunks_list),
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+            return PAREM_EDEVICE;
+        uint32_t *todo = reinterpret_cast<uint32_t *>(ws + p.off_todo);
+        hipLaunchKernelGGL(k_compose_chunks_uniform, dim3((uint32_t)((nin + 3) / 4)), dim3(256), 0, stream, map, mcl,
+                           mld, a, seg_out(p, ws, 0), nin, todo);
+        hipLaunchKernelGGL(k_compose_chunks_list, dim3((uint32_t)std::min<uint64_t>(nin, 512)), dim3(kComposeThreads),
+                           lds, stream, map, mcl, mld, a, seg_out(p, ws, 0), nin, todo);
+    } else {
+        hipLaunchKernelGGL(k_compose_chunks, dim3((uint32_t)nin), dim3(kComposeThreads), lds, stream, map, mcl, mld, a,
+                           seg_out(p, ws, 0), nin == 1 ? d_out : nullptr);
+    }
     if (hipGetLastError() != hipSuccess) return PAREM_EDEVICE;
     for (size_t l = 1; l < p.levels.size(); ++l) {
         const size_t src = p.keep ? l - 1 : (l - 1) % 2, dst = p.keep ? l : l % 2;

@@ -425,6 +425,18 @@ def test_nonsynchronizing_dfa():
     run_case("permutation, two wide levels", dfa, text, chunk_len=64, group=4)
     run_case("mixed, two wide levels", dfa2,
              np.frombuffer(b"abcr", dtype=np.uint8)[rng.choice(4, size=64 * 90_000, p=probs)], chunk_len=64, group=8)
+    # wide maps (100-state permutations: every set holds all 100 states, so a
+    # first-level workgroup composes at most 64 maps): groups with a
+    # synchronizing byte in every chunk compose one wave each, the others go
+    # through the LDS tree
+    q = 100
+    wide = np.stack([rng.permutation(q) for _ in range(3)] + [np.zeros(q, dtype=np.int64)], axis=1)
+    dfa3 = W.Dfa(wide.astype(np.uint8), b"abcr", 0, np.asarray([1, 50, 99], dtype=np.uint32))
+    for pr, n in ((0.01, 400_000), (0.2, 400_000), (0.0005, 2_000_003)):
+        p3 = np.asarray([(1 - pr) / 3] * 3 + [pr])
+        text = np.frombuffer(b"abcr", dtype=np.uint8)[rng.choice(4, size=n, p=p3)]
+        for lay in (P.LAYOUT_AUTO, P.LAYOUT_BYTE_LDS, P.LAYOUT_CLASS_LDS):
+            run_case(f"wide permutation r={pr} n={n} layout={lay}", dfa3, text, chunk_len=64, layout=lay, group=8)
 
 
 def lookback_runs(dfa, text, L, K, cap=64, kmax=4096):
