@@ -7,21 +7,27 @@ namespace parem {
 
 typedef uint32_t sweep_u32x4 __attribute__((ext_vector_type(4)));
 
+// XCD x (workgroups b with b % 8 == x, dealt in turn) sweeps the x-th eighth
+// of the buffer, grid-stride over its own workgroups: measured on 1 GiB,
+// 16 workgroups per CU, 6.88 TB/s against 6.15 for one grid-stride sweep of
+// the whole buffer (32 per CU) and 6.80 for one contiguous slice per
+// workgroup. Non-temporal loads (the buffer is read once): 6.08 against 5.26
+// TB/s for plain loads in the single sweep.
 __global__ __launch_bounds__(256) void k_read_sweep(const uint4 *__restrict__ p, uint64_t n16,
                                                     uint32_t *__restrict__ sink) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t x = blockIdx.x % 8u, nb = gridDim.x / 8u;
+    const uint64_t part = (n16 + 7) / 8, lo = part * x, hi = min(lo + part, n16);
+    const uint64_t stride = (uint64_t)nb * blockDim.x;
+    uint64_t i = lo + (uint64_t)(blockIdx.x / 8u) * blockDim.x + threadIdx.x;
     uint32_t acc = 0;
-    // non-temporal loads (the buffer is read once): 6.08 against 5.26 TB/s
-    // for plain loads over 1 GiB, with 32 workgroups per CU
     const sweep_u32x4 *q = reinterpret_cast<const sweep_u32x4 *>(p);
-    for (; i + 3 * stride < n16; i += 4 * stride) {
+    for (; i + 3 * stride < hi; i += 4 * stride) {
         const sweep_u32x4 a = __builtin_nontemporal_load(q + i), b = __builtin_nontemporal_load(q + i + stride),
                     c = __builtin_nontemporal_load(q + i + 2 * stride),
                     d = __builtin_nontemporal_load(q + i + 3 * stride);
         acc ^= a.x ^ a.y ^ a.z ^ a.w ^ b.x ^ b.y ^ b.z ^ b.w ^ c.x ^ c.y ^ c.z ^ c.w ^ d.x ^ d.y ^ d.z ^ d.w;
     }
-    for (; i < n16; i += stride) {
+    for (; i < hi; i += stride) {
         const uint4 a = p[i];
         acc ^= a.x ^ a.y ^ a.z ^ a.w;
     }
@@ -39,7 +45,7 @@ extern "C" parem_status parem_read_sweep(const uint8_t *d_buf, uint64_t len, voi
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return PAREM_EDEVICE;
-    hipLaunchKernelGGL(parem::k_read_sweep, dim3((unsigned)(32 * cus)), dim3(256), 0,
+    hipLaunchKernelGGL(parem::k_read_sweep, dim3((unsigned)(16 * cus)), dim3(256), 0,
                        reinterpret_cast<hipStream_t>(stream), reinterpret_cast<const uint4 *>(d_buf), len / 16,
                        d_sink);
     return hipGetLastError() == hipSuccess ? PAREM_OK : PAREM_EDEVICE;

@@ -35,7 +35,7 @@ __global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_walk_byte(Wa
         st.T = reinterpret_cast<const E *>(smem);
         tb = table_bytes;
     }
-    walk_chunk<G, ByteStep<E, ROW>, ALIGNED, TILE, MODE>(st, a, smem + tb, (uint64_t)blockIdx.x * kWalkThreads);
+    walk_chunk<G, ByteStep<E, ROW>, ALIGNED, TILE, MODE>(st, a, smem + tb, (uint64_t)xcd_block() * kWalkThreads);
 }
 
 template <int G, bool ALIGNED, uint32_t TILE, int MODE>
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_walk_hot(Wal
     stage_table(reinterpret_cast<uint4 *>(smem), reinterpret_cast<const uint4 *>(g_table), table_bytes / 16u);
     const uint16_t *hot = reinterpret_cast<const uint16_t *>(smem);
     HotStep st{hot, hot + (hot_rows + 1) * kHotRow, full, enc, hot_rows};
-    walk_chunk<G, HotStep, ALIGNED, TILE, MODE>(st, a, smem + table_bytes, (uint64_t)blockIdx.x * kWalkThreads);
+    walk_chunk<G, HotStep, ALIGNED, TILE, MODE>(st, a, smem + table_bytes, (uint64_t)xcd_block() * kWalkThreads);
 }
 
 template <int G, bool ALIGNED, uint32_t TILE, int MODE>
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_walk_class(W
     extern __shared__ __align__(16) uint8_t smem[];
     stage_table(reinterpret_cast<uint4 *>(smem), reinterpret_cast<const uint4 *>(g_table), table_bytes / 16u);
     ClassStep st{smem, reinterpret_cast<const uint16_t *>(smem + 256), A1};
-    walk_chunk<G, ClassStep, ALIGNED, TILE, MODE>(st, a, smem + table_bytes, (uint64_t)blockIdx.x * kWalkThreads);
+    walk_chunk<G, ClassStep, ALIGNED, TILE, MODE>(st, a, smem + table_bytes, (uint64_t)xcd_block() * kWalkThreads);
 }
 
 // one workgroup of kSparseThreads per CU: four waves per SIMD
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(kSparseThreads) void k_walk_sparse(WalkArgs a, cons
                                 table_bytes / 16u);
     SparseStep<RAW, UNI> st{smem, sids, d0};
     walk_chunk<G, SparseStep<RAW, UNI>, ALIGNED, 64, MODE>(st, a, smem + table_bytes,
-                                                           (uint64_t)blockIdx.x * kSparseThreads);
+                                                           (uint64_t)xcd_block() * kSparseThreads);
 }
 
 template <int G, int B, bool ALIGNED, uint32_t TILE, int MODE>
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(kWalkThreads, (G <= 8 ? 4 : 2)) void k_walk_kgram(W
     extern __shared__ __align__(16) uint8_t smem[];
     stage_table(reinterpret_cast<uint4 *>(smem), reinterpret_cast<const uint4 *>(g_table), table_bytes / 16u);
     KgStep<B> st{smem, kp};
-    walk_chunk<G, KgStep<B>, ALIGNED, TILE, MODE>(st, a, smem + table_bytes, (uint64_t)blockIdx.x * kWalkThreads);
+    walk_chunk<G, KgStep<B>, ALIGNED, TILE, MODE>(st, a, smem + table_bytes, (uint64_t)xcd_block() * kWalkThreads);
 }
 
 template <typename E, uint32_t ROW, bool LDS, bool ALIGNED, uint32_t TILE, int MODE>
